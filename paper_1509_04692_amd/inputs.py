@@ -1,0 +1,221 @@
+"""Seeded synthetic workloads: shape vertex tables, box sizes and initial states.
+
+This module holds no step of the Monte Carlo method itself.  It only writes
+down the systems the method runs on: particle-frame vertices of the shapes
+(given once per type, as in the paper's job-script API, Fig. 1 and Sec. 2.3),
+the periodic box length for a packing fraction, and non-overlapping lattice
+starting configurations.  The GPU library and the reference oracle both take
+their inputs from here; neither is imported by it.
+
+Arrays: positions are (dim, N) float64 (structure of arrays), orientations
+(2, N) float64 unit complex numbers (c, s) for polygons and (4, N) unit
+quaternions (w, x, y, z) for polyhedra.
+"""
+import math
+
+import numpy as np
+
+INIT_SEED = 12345
+
+
+# -- shapes --------------------------------------------------------------------
+
+def regular_polygon_vertices(n_sides=5, circumradius=0.5):
+    """Regular polygon, vertex 0 on +y, counter-clockwise."""
+    k = np.arange(n_sides)
+    ang = math.pi / 2 + 2 * math.pi * k / n_sides
+    return np.stack([circumradius * np.cos(ang), circumradius * np.sin(ang)], axis=1)
+
+
+def polygon_area(verts):
+    x, y = verts[:, 0], verts[:, 1]
+    return 0.5 * float(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+
+
+def cube_vertices(edge=1.0):
+    h = 0.5 * edge
+    return np.array([[sx * h, sy * h, sz * h]
+                     for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], dtype=np.float64)
+
+
+def truncated_octahedron_vertices(edge=1.0):
+    """All permutations of (0, +-1, +-2), scaled from edge sqrt(2) to `edge`."""
+    pts = set()
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        for s1 in (-1, 1):
+            for s2 in (-1, 1):
+                base = [0.0, s1 * 1.0, s2 * 2.0]
+                pts.add(tuple(base[p] for p in perm))
+    v = np.array(sorted(pts), dtype=np.float64)
+    return v * (edge / math.sqrt(2.0))
+
+
+CUBE_VOLUME_PER_EDGE3 = 1.0
+TRUNC_OCT_VOLUME_PER_EDGE3 = 8.0 * math.sqrt(2.0)
+
+
+def disk_species(diameter=1.0, d=0.1):
+    return {"dim": 2, "shape": "disk", "diameter": float(diameter), "d": float(d),
+            "a": 0.0, "p_rot": 0.0, "rounds": 0, "volume": math.pi * diameter ** 2 / 4}
+
+
+def pentagon_species(circumradius=0.5, d=0.1, a=0.2, p_rot=0.5):
+    v = regular_polygon_vertices(5, circumradius)
+    return {"dim": 2, "shape": "polygon", "verts": v, "d": float(d), "a": float(a),
+            "p_rot": float(p_rot), "rounds": 0, "volume": polygon_area(v)}
+
+
+def cube_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
+    return {"dim": 3, "shape": "polyhedron", "verts": cube_vertices(edge), "d": float(d),
+            "a": float(a), "p_rot": float(p_rot), "rounds": 0,
+            "volume": CUBE_VOLUME_PER_EDGE3 * edge ** 3}
+
+
+def truncated_octahedron_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
+    return {"dim": 3, "shape": "polyhedron", "verts": truncated_octahedron_vertices(edge),
+            "d": float(d), "a": float(a), "p_rot": float(p_rot), "rounds": 0,
+            "volume": TRUNC_OCT_VOLUME_PER_EDGE3 * edge ** 3}
+
+
+def box_length(N, particle_volume, phi, dim):
+    """Side of the square / cubic periodic box holding N particles at phi."""
+    return (N * particle_volume / phi) ** (1.0 / dim)
+
+
+def aligned_extent(sp):
+    """Width of the axis-aligned bounding box of one particle, per axis."""
+    if sp["shape"] == "disk":
+        return np.full(2, sp["diameter"])
+    v = np.asarray(sp["verts"])
+    return v.max(axis=0) - v.min(axis=0)
+
+
+def identity_orientations(sp, N):
+    if sp["shape"] == "polygon":
+        o = np.zeros((2, N))
+        o[0] = 1.0
+        return o
+    if sp["shape"] == "polyhedron":
+        o = np.zeros((4, N))
+        o[0] = 1.0
+        return o
+    return np.zeros((1, max(N, 1)))
+
+
+# -- initial states ------------------------------------------------------------
+
+def simple_lattice(sp, N, L, seed=INIT_SEED):
+    """Aligned particles on a square / cubic lattice of m^dim >= N sites.
+
+    If m^dim > N a seeded random subset of sites is occupied.  Raises if the
+    lattice spacing does not clear the aligned bounding box (the particles
+    would touch or overlap).
+    """
+    dim = sp["dim"]
+    m = int(math.ceil(N ** (1.0 / dim) - 1e-9))
+    while m ** dim < N:
+        m += 1
+    spacing = L / m
+    if np.any(aligned_extent(sp) >= spacing * (1 - 1e-9)):
+        raise ValueError(f"lattice spacing {spacing:.4f} too small for the shape")
+    grids = np.meshgrid(*[np.arange(m)] * dim, indexing="ij")
+    sites = np.stack([g.ravel(order="F") for g in grids], axis=0).astype(np.float64)
+    if m ** dim > N:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        keep = np.sort(rng.choice(m ** dim, size=N, replace=False))
+        sites = sites[:, keep]
+    pos = np.ascontiguousarray((sites + 0.5) * spacing)
+    return pos, identity_orientations(sp, N)
+
+
+# Up / down interlocked rows for regular pentagons: alternating columns hold
+# pentagons rotated by pi, so neighbouring up / down edges are parallel.  For
+# circumradius 0.5 the column pitch 2 r_in / cos(18 deg) = 0.8507 and the row
+# pitch r_in + R = 0.9045 are the touching distances; both get a 0.5 %
+# clearance.  Densest packing fraction reached: about 0.77.
+_PENT_COL_PITCH = 0.8507 * 1.005
+_PENT_ROW_PITCH = 0.9045 * 1.005
+
+
+def pentagon_interlocked_lattice(sp, N, L, seed=INIT_SEED):
+    R = float(np.max(np.hypot(sp["verts"][:, 0], sp["verts"][:, 1])))
+    col = _PENT_COL_PITCH * R / 0.5
+    row = _PENT_ROW_PITCH * R / 0.5
+    mx = int(L // col)
+    mx -= mx % 2
+    if mx < 2:
+        raise ValueError("box too small for an interlocked pentagon lattice")
+    my = -(-N // mx)
+    if L / my < row:
+        raise ValueError("packing fraction too high for an interlocked pentagon lattice")
+    ix, iy = np.meshgrid(np.arange(mx), np.arange(my), indexing="ij")
+    ix, iy = ix.ravel(order="F"), iy.ravel(order="F")
+    if mx * my > N:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        keep = np.sort(rng.choice(mx * my, size=N, replace=False))
+        ix, iy = ix[keep], iy[keep]
+    pos = np.stack([(ix + 0.5) * (L / mx), (iy + 0.5) * (L / my)], axis=0)
+    orient = np.zeros((2, N))
+    orient[0] = np.where(ix % 2 == 0, 1.0, -1.0)
+    return np.ascontiguousarray(pos), orient
+
+
+def initial_state(sp, N, phi, seed=INIT_SEED):
+    """(L, pos, orient) of a valid starting configuration at packing fraction phi."""
+    L = box_length(N, sp["volume"], phi, sp["dim"])
+    try:
+        pos, orient = simple_lattice(sp, N, L, seed)
+    except ValueError:
+        if sp["shape"] != "polygon" or len(sp["verts"]) != 5:
+            raise
+        pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
+    return L, pos, orient
+
+
+# -- workloads -----------------------------------------------------------------
+
+def workload_disks_256():
+    """2D hard disks, N=256, sigma=1, phi=0.50, square lattice, d=0.1."""
+    sp = disk_species(1.0, d=0.1)
+    L, pos, orient = initial_state(sp, 256, 0.50)
+    return sp, 256, L, pos, orient
+
+
+def workload_pentagons(N=4096, phi=0.60):
+    """Regular pentagons, circumradius 0.5, d=0.1, a=0.2, p_rot=0.5."""
+    sp = pentagon_species(0.5, d=0.1, a=0.2, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_cubes(N=32768, phi=0.45):
+    sp = cube_species(1.0, d=0.08, a=0.1, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_truncated_octahedra(N=32768, phi=0.45):
+    sp = truncated_octahedron_species(1.0, d=0.08, a=0.1, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def screening_manifest(n_replicas=512, seed=2026, n_lo=64, n_hi=4096, phi_lo=0.30,
+                       phi_hi=0.70):
+    """Heterogeneous batch: replica r even -> disks, odd -> pentagons; N and phi
+    drawn uniformly from a seeded PCG64 stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ns = rng.integers(n_lo, n_hi + 1, size=n_replicas)
+    phis = rng.uniform(phi_lo, phi_hi, size=n_replicas)
+    return [("disk" if r % 2 == 0 else "pentagon", int(Ns[r]), float(phis[r]))
+            for r in range(n_replicas)]
+
+
+def screening_batch(n_replicas=512, seed=2026, **kw):
+    """Species, N, L, pos, orient lists of the heterogeneous screening batch."""
+    out = []
+    for kind, N, phi in screening_manifest(n_replicas, seed, **kw):
+        sp = disk_species(1.0, d=0.1) if kind == "disk" else pentagon_species(0.5, 0.1, 0.2, 0.5)
+        L, pos, orient = initial_state(sp, N, phi)
+        out.append((sp, N, L, pos, orient))
+    return out

@@ -1,0 +1,325 @@
+"""Pins of the oracle's overlap tests (Sec. 2.3) against independent geometry.
+
+* Disks: overlap iff the centre distance is below the diameter.
+* Convex polygons (separating axes in the oracle) against the paper's own
+  concave-polygon method -- any proper edge-pair intersection or any vertex
+  strictly inside the other shape (Sec. 2.3) -- which is exact for convex
+  polygons too; against dense point sampling (a common point proves overlap);
+  and, for equal orientations, against the closed form "r_AB inside the
+  Minkowski difference A (+) -A" (a decagon for pentagons).
+* Convex polyhedra (XenoCollide in the oracle) against full 3D separating
+  axes (all face normals plus all edge-edge cross products), against the
+  closed form for axis-aligned unit cubes, and against point sampling.
+* Invariants: exchange symmetry and global rotation invariance.
+
+Configurations whose separation or penetration is below 1e-9 are skipped:
+there FP64 rounding may legitimately decide either way.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import ConvexHull
+
+import oracle
+from paper_1509_04692_amd import inputs
+
+MARGIN = 1e-9
+
+
+# -- 2D reference geometry -----------------------------------------------------
+
+def rot2(z):
+    c, s = z
+    return np.array([[c, -s], [s, c]])
+
+
+def world_polygon(verts, z, r):
+    return verts @ rot2(z).T + np.asarray(r)
+
+
+def orient2(a, b, p):
+    return (b[0] - a[0]) * (p[1] - a[1]) - (b[1] - a[1]) * (p[0] - a[0])
+
+
+def inside_convex(poly, p):
+    n = len(poly)
+    return all(orient2(poly[k], poly[(k + 1) % n], p) > 0 for k in range(n))
+
+
+def edges_or_vertices_overlap(PA, PB):
+    """The paper's concave-polygon test: edge pairs and vertices inside."""
+    na, nb = len(PA), len(PB)
+    for i in range(na):
+        p1, p2 = PA[i], PA[(i + 1) % na]
+        for j in range(nb):
+            q1, q2 = PB[j], PB[(j + 1) % nb]
+            d1, d2 = orient2(q1, q2, p1), orient2(q1, q2, p2)
+            d3, d4 = orient2(p1, p2, q1), orient2(p1, p2, q2)
+            if d1 * d2 < 0 and d3 * d4 < 0:
+                return True
+    return any(inside_convex(PB, p) for p in PA) or any(inside_convex(PA, q) for q in PB)
+
+
+def sat_gap_2d(PA, PB):
+    """Largest separation along unit edge normals (> 0: apart, < 0: overlap)."""
+    best = -np.inf
+    for P in (PA, PB):
+        n = len(P)
+        for k in range(n):
+            e = P[(k + 1) % n] - P[k]
+            ax = np.array([e[1], -e[0]]) / np.hypot(*e)
+            pa, pb = PA @ ax, PB @ ax
+            best = max(best, pb.min() - pa.max(), pa.min() - pb.max())
+    return best
+
+
+def random_unit_complex(rng):
+    t = rng.uniform(-math.pi, math.pi)
+    return np.array([math.cos(t), math.sin(t)])
+
+
+def polygon_cases(rng, n, R):
+    for k in range(n):
+        # mostly near contact (inradius-sum .. circumradius-sum), some anywhere
+        rr = rng.uniform(1.5 * R, 2.1 * R) if k % 5 else rng.uniform(0, 2.2 * R)
+        phi = rng.uniform(-math.pi, math.pi)
+        r = np.array([rr * math.cos(phi), rr * math.sin(phi)])
+        yield r, random_unit_complex(rng), random_unit_complex(rng)
+
+
+@pytest.fixture(scope="module")
+def pent():
+    return inputs.pentagon_species()
+
+
+def test_disk_overlap_closed_form():
+    sp = inputs.disk_species(1.0)
+    rng = np.random.Generator(np.random.PCG64(11))
+    for _ in range(3000):
+        r = rng.uniform(-1.3, 1.3, size=2)
+        d = math.hypot(*r)
+        if abs(d - 1.0) < MARGIN:
+            continue
+        assert oracle.pair_overlaps(sp, r) == (d < 1.0)
+    assert not oracle.pair_overlaps(sp, [1.0, 0.0])  # touching is not overlap
+    assert oracle.pair_overlaps(sp, [0.0, 0.0])
+
+
+def test_polygon_sat_matches_edge_and_vertex_test(pent):
+    rng = np.random.Generator(np.random.PCG64(12))
+    v = pent["verts"]
+    checked = n_overlap = 0
+    for r, za, zb in polygon_cases(rng, 3000, 0.5):
+        PA, PB = world_polygon(v, za, [0, 0]), world_polygon(v, zb, r)
+        if abs(sat_gap_2d(PA, PB)) < MARGIN:
+            continue
+        want = edges_or_vertices_overlap(PA, PB)
+        assert oracle.overlap_full(pent, r, za, zb) == want, (r, za, zb)
+        checked += 1
+        n_overlap += want
+    assert checked > 2500 and 0.2 < n_overlap / checked < 0.8
+
+
+def test_polygon_sat_point_sampling(pent):
+    """A sampled point strictly inside both polygons proves overlap."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    v = pent["verts"]
+    proved = 0
+    for r, za, zb in polygon_cases(rng, 400, 0.5):
+        PA, PB = world_polygon(v, za, [0, 0]), world_polygon(v, zb, r)
+        pts = rng.uniform(-0.5, 0.5, size=(400, 2)) + 0.5 * r
+        common = any(inside_convex(PA, p) and inside_convex(PB, p) for p in pts)
+        if common:
+            proved += 1
+            assert oracle.overlap_full(pent, r, za, zb)
+    assert proved > 50
+
+
+def test_polygon_equal_orientation_decagon_closed_form(pent):
+    v = pent["verts"]
+    diff = (v[:, None, :] - v[None, :, :]).reshape(-1, 2)
+    hull = ConvexHull(diff)
+    assert len(hull.vertices) == 10  # A (+) -A of a regular pentagon is a decagon
+    eq = hull.equations  # n . x + d <= 0 inside
+    rng = np.random.Generator(np.random.PCG64(14))
+    for _ in range(3000):
+        r = rng.uniform(-1.05, 1.05, size=2)
+        t = rng.uniform(-math.pi, math.pi)
+        z = np.array([math.cos(t), math.sin(t)])
+        r_world = rot2(z) @ r  # decagon is in the common body frame
+        dist = eq[:, :2] @ r + eq[:, 2]
+        if np.min(np.abs(dist)) < MARGIN:
+            continue
+        inside = bool(np.all(dist < 0))
+        assert oracle.overlap_full(pent, r_world, z, z) == inside
+
+
+def test_polygon_exchange_symmetry_and_rotation_invariance(pent):
+    rng = np.random.Generator(np.random.PCG64(15))
+    v = pent["verts"]
+    for r, za, zb in polygon_cases(rng, 1500, 0.5):
+        PA, PB = world_polygon(v, za, [0, 0]), world_polygon(v, zb, r)
+        if abs(sat_gap_2d(PA, PB)) < MARGIN:
+            continue
+        base = oracle.overlap_full(pent, r, za, zb)
+        assert oracle.overlap_full(pent, -r, zb, za) == base
+        g = random_unit_complex(rng)
+        gz = lambda z: np.array([g[0] * z[0] - g[1] * z[1], g[1] * z[0] + g[0] * z[1]])
+        assert oracle.overlap_full(pent, rot2(g) @ r, gz(za), gz(zb)) == base
+
+
+@pytest.mark.parametrize("flag", ["ORACLE_PLANT_SAT_SIGN", "ORACLE_PLANT_SAT_A_AXES_ONLY"])
+def test_polygon_pins_detect_planted_mistakes(pent, planted, flag):
+    lib = planted(flag)
+    rng = np.random.Generator(np.random.PCG64(16))
+    v = pent["verts"]
+    mismatches = 0
+    for r, za, zb in polygon_cases(rng, 1500, 0.5):
+        PA, PB = world_polygon(v, za, [0, 0]), world_polygon(v, zb, r)
+        if abs(sat_gap_2d(PA, PB)) < MARGIN:
+            continue
+        mismatches += oracle.overlap_full(pent, r, za, zb, lib=lib) != edges_or_vertices_overlap(PA, PB)
+    assert mismatches > 0
+
+
+# -- 3D reference geometry -----------------------------------------------------
+
+def quat_matrix(q):
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def random_quat(rng):
+    q = rng.normal(size=4)
+    return q / np.linalg.norm(q)
+
+
+def hull_axes(P):
+    h = ConvexHull(P)
+    normals = h.equations[:, :3]
+    edges = []
+    for s in h.simplices:
+        for a, b in ((0, 1), (1, 2), (2, 0)):
+            edges.append(P[s[b]] - P[s[a]])
+    return normals, np.array(edges), h
+
+
+def sat_gap_3d(PA, PB):
+    nA, eA, _ = hull_axes(PA)
+    nB, eB, _ = hull_axes(PB)
+    cross = np.cross(eA[:, None, :], eB[None, :, :]).reshape(-1, 3)
+    nrm = np.linalg.norm(cross, axis=1)
+    axes = np.concatenate([nA, nB, cross[nrm > 1e-9] / nrm[nrm > 1e-9, None]])
+    pa, pb = PA @ axes.T, PB @ axes.T
+    gaps = np.maximum(pb.min(axis=0) - pa.max(axis=0), pa.min(axis=0) - pb.max(axis=0))
+    return float(gaps.max())
+
+
+def polyhedron_cases(rng, n, R):
+    for k in range(n):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        rr = rng.uniform(1.0 * R, 2.0 * R) if k % 5 else rng.uniform(0, 2.1 * R)
+        yield d * rr, random_quat(rng), random_quat(rng)
+
+
+SHAPES_3D = {"cube": inputs.cube_species(), "trunc_oct": inputs.truncated_octahedron_species()}
+
+
+@pytest.mark.parametrize("name", sorted(SHAPES_3D))
+def test_xenocollide_matches_3d_separating_axes(name):
+    sp = SHAPES_3D[name]
+    v = sp["verts"]
+    R = float(np.max(np.linalg.norm(v, axis=1)))
+    rng = np.random.Generator(np.random.PCG64(21))
+    checked = n_overlap = 0
+    for r, qa, qb in polyhedron_cases(rng, 1200, R):
+        PA = v @ quat_matrix(qa).T
+        PB = v @ quat_matrix(qb).T + r
+        gap = sat_gap_3d(PA, PB)
+        if abs(gap) < MARGIN:
+            continue
+        want = gap < 0
+        assert oracle.overlap_full(sp, r, qa, qb) == want, (r, qa, qb, gap)
+        checked += 1
+        n_overlap += want
+    assert checked > 1000 and 0.15 < n_overlap / checked < 0.85
+
+
+def test_xenocollide_axis_aligned_cubes_closed_form():
+    sp = SHAPES_3D["cube"]
+    rng = np.random.Generator(np.random.PCG64(22))
+    ident = [1.0, 0.0, 0.0, 0.0]
+    for _ in range(3000):
+        r = rng.uniform(-1.2, 1.2, size=3)
+        if np.min(np.abs(np.abs(r) - 1.0)) < MARGIN:
+            continue
+        assert oracle.overlap_full(sp, r, ident, ident) == bool(np.all(np.abs(r) < 1.0)), r
+
+
+@pytest.mark.parametrize("name", sorted(SHAPES_3D))
+def test_xenocollide_point_sampling(name):
+    sp = SHAPES_3D[name]
+    v = sp["verts"]
+    R = float(np.max(np.linalg.norm(v, axis=1)))
+    rng = np.random.Generator(np.random.PCG64(23))
+    proved = 0
+    for r, qa, qb in polyhedron_cases(rng, 300, R):
+        PA = v @ quat_matrix(qa).T
+        PB = v @ quat_matrix(qb).T + r
+        ea, eb = ConvexHull(PA).equations, ConvexHull(PB).equations
+        pts = rng.uniform(-R, R, size=(3000, 3)) + 0.5 * r
+        ina = np.all(pts @ ea[:, :3].T + ea[:, 3] < 0, axis=1)
+        inb = np.all(pts @ eb[:, :3].T + eb[:, 3] < 0, axis=1)
+        if np.any(ina & inb):
+            proved += 1
+            assert oracle.overlap_full(sp, r, qa, qb)
+    assert proved > 40
+
+
+@pytest.mark.parametrize("name", sorted(SHAPES_3D))
+def test_xenocollide_exchange_symmetry_and_rotation_invariance(name):
+    sp = SHAPES_3D[name]
+    v = sp["verts"]
+    R = float(np.max(np.linalg.norm(v, axis=1)))
+    rng = np.random.Generator(np.random.PCG64(24))
+
+    def qmul(p, q):
+        w1, x1, y1, z1 = p
+        w2, x2, y2, z2 = q
+        return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
+                         w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                         w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
+                         w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+    for r, qa, qb in polyhedron_cases(rng, 500, R):
+        PA = v @ quat_matrix(qa).T
+        PB = v @ quat_matrix(qb).T + r
+        if abs(sat_gap_3d(PA, PB)) < MARGIN:
+            continue
+        base = oracle.overlap_full(sp, r, qa, qb)
+        assert oracle.overlap_full(sp, -r, qb, qa) == base
+        g = random_quat(rng)
+        assert oracle.overlap_full(sp, quat_matrix(g) @ r, qmul(g, qa), qmul(g, qb)) == base
+
+
+@pytest.mark.parametrize("flag", ["ORACLE_PLANT_MPR_TRANSPOSE", "ORACLE_PLANT_MPR_PORTAL"])
+def test_xenocollide_pins_detect_planted_mistakes(planted, flag):
+    lib = planted(flag)
+    sp = SHAPES_3D["trunc_oct"]
+    v = sp["verts"]
+    R = float(np.max(np.linalg.norm(v, axis=1)))
+    rng = np.random.Generator(np.random.PCG64(25))
+    mismatches = 0
+    for r, qa, qb in polyhedron_cases(rng, 600, R):
+        PA = v @ quat_matrix(qa).T
+        PB = v @ quat_matrix(qb).T + r
+        gap = sat_gap_3d(PA, PB)
+        if abs(gap) < MARGIN:
+            continue
+        mismatches += oracle.overlap_full(sp, r, qa, qb, lib=lib) != (gap < 0)
+    assert mismatches > 0
