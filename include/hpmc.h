@@ -1,0 +1,165 @@
+/*
+ * hpmc.h -- C ABI of the MI355X (gfx950) checkerboard hard-shape Monte Carlo
+ * library (libhpmc.so).
+ *
+ * The library runs the checkerboard-parallel Metropolis sweep of hard shapes
+ * of Anderson, Irrgang and Glotzer, "Scalable Metropolis Monte Carlo for
+ * simulation of hard shapes" (HPMC):
+ *   - Metropolis for hard particles: select a particle, propose a small
+ *     translation r + dr or rotation q . dq, reject it if the trial shape
+ *     overlaps any other particle, otherwise accept (Sec. 2.1);
+ *   - a cell list whose cells are at least d_max wide, searched over the own
+ *     cell and its neighbours +-1 per axis (Sec. 2.2.1);
+ *   - overlap checks in the frame of one particle, positions in FP64 and
+ *     orientations as unit complex numbers / quaternions (Sec. 2.3, Eqs. 1-2);
+ *   - one trial move per non-empty active cell of a 2^dim-colour checkerboard,
+ *     moves leaving their cell rejected, a random offset per sweep
+ *     (Sec. 2.5.1-2.5.2), random numbers from a counter-based stream per move
+ *     (Sec. 2.5).
+ * One sweep is N trial moves (Sec. 2): rounds x 2^dim colour passes, each
+ * making one move in every non-empty cell of that colour.
+ *
+ * Memory: every device buffer is owned by the caller (the Python binding
+ * allocates them with PyTorch) and must stay alive until hpmc_destroy().
+ * The library never allocates device memory: all scratch lives in the
+ * caller's workspace.  Host arrays passed to hpmc_init are copied.
+ *
+ * Streams and threads: a state is bound to one HIP stream (passed as void*,
+ * NULL = the default stream) and is not thread safe.  Distinct states on
+ * distinct streams are independent.  hpmc_sweep is asynchronous; calls that
+ * return data to the host synchronise the stream.
+ *
+ * Errors: every call returns HPMC_OK (0) or a negative HPMC_ERR_* code and
+ * never throws.  Device faults surface at the next synchronising call.
+ */
+#ifndef HPMC_H
+#define HPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPMC_OK 0
+#define HPMC_ERR_INVALID_ARG (-1)         /* malformed arguments or shape */
+#define HPMC_ERR_BOX_TOO_SMALL (-2)       /* fewer than 4 cells per side */
+#define HPMC_ERR_INITIAL_OVERLAP (-3)     /* hpmc_init found overlapping pairs */
+#define HPMC_ERR_WORKSPACE_TOO_SMALL (-4) /* workspace_bytes below requirement */
+#define HPMC_ERR_HIP (-5)                 /* a HIP runtime call failed */
+#define HPMC_ERR_SWEEP_OVERFLOW (-6)      /* sweep counter would reach 2^32 */
+#define HPMC_ERR_UNSUPPORTED (-7)         /* valid request this build cannot run */
+
+/* Opaque host-side handle of one set of replicas. */
+typedef struct hpmc_state hpmc_state;
+
+typedef enum { HPMC_DISK = 0, HPMC_POLYGON = 1, HPMC_POLYHEDRON = 2 } hpmc_shape;
+
+/* FP64: every overlap decision in binary64, in the pinned operation order.
+ * MIXED: overlap tests in binary32 with a rigorous forward-error margin; a
+ * pair whose binary32 result falls inside the margin is re-evaluated in
+ * binary64, so every decision equals the FP64 decision (the paper's mixed
+ * mode, Sec. 2.3, trusts binary32 outright; this one does not). */
+typedef enum { HPMC_FP64 = 0, HPMC_MIXED = 1 } hpmc_precision;
+
+/* GRID: one kernel per colour pass over a cell list in global memory, for
+ * large systems.  PERSISTENT: one work-group per replica runs whole sweeps
+ * with the cell list in LDS (small systems and batches).  AUTO picks. */
+typedef enum { HPMC_PATH_AUTO = 0, HPMC_PATH_GRID = 1, HPMC_PATH_PERSISTENT = 2 } hpmc_path;
+
+/* One particle type (all particles of a replica share it), the parameters of
+ * the paper's job script (Fig. 1): vertices in the particle frame, move
+ * sizes d and a. */
+typedef struct {
+    int32_t dim;          /* 2 (disk, polygon) or 3 (polyhedron) */
+    int32_t shape;        /* hpmc_shape */
+    int32_t n_verts;      /* polygon: 3..8 (CCW, strictly convex); polyhedron: 4..64 */
+    const double *verts;  /* host, n_verts x dim row-major; NULL for disks */
+    double diameter;      /* disks */
+    double d;             /* translation: each component uniform in [-d, d] */
+    double a;             /* rotation: 2D angle uniform in [-a, a]; 3D dq = (1, v),
+                             v uniform in [-a, a]^3, renormalised */
+    double p_rot;         /* probability that a move is a rotation (0 for disks) */
+    int32_t rounds;       /* colour rounds per sweep; 0 = max(1, round(N / cells)) */
+} hpmc_species;
+
+typedef struct {
+    int32_t n_replicas;            /* >= 1 independent systems */
+    const hpmc_species *species;   /* host, n_replicas entries */
+    const int32_t *N;              /* host, particles per replica (>= 1) */
+    const double *L;               /* host, periodic box side per replica */
+    int32_t precision;             /* hpmc_precision */
+    int32_t path;                  /* hpmc_path */
+    /* Device, caller-owned, canonical particle order, replicas concatenated.
+     * pos: replica r occupies dim_r * N_r doubles, coordinate a of particle i
+     *      at [a * N_r + i], all values in [0, L_r).
+     * orient: replica r occupies k_r * N_r doubles (k = 0 disk, 2 polygon
+     *      (c, s), 4 polyhedron (w, x, y, z)), component k of particle i at
+     *      [k * N_r + i]; may be NULL when every replica is a disk. */
+    double *pos;
+    double *orient;
+    void *workspace;               /* device, caller-owned, 256-byte aligned */
+    size_t workspace_bytes;
+    void *stream;                  /* hipStream_t or NULL */
+} hpmc_init_args;
+
+/* Per-replica counters since init or the last hpmc_reset_stats. */
+typedef struct {
+    uint64_t attempted;      /* trial moves, including cell-boundary rejects */
+    uint64_t attempted_rot;  /* of which rotations */
+    uint64_t cell_reject;    /* trial position left the active cell */
+    uint64_t overlap_reject; /* trial shape overlapped a neighbour */
+    uint64_t accept;
+    uint64_t pair_tests;     /* full (non-circumsphere) overlap tests run */
+    uint64_t pair_fp64;      /* of which decided in binary64 (all, in FP64 mode;
+                                the re-checked ones, in MIXED mode) */
+    uint64_t sweeps;         /* sweeps completed */
+} hpmc_stats;
+
+/* Workspace size for these arguments (pos/orient/workspace may be NULL). */
+int hpmc_workspace_bytes(const hpmc_init_args *args, size_t *out_bytes);
+
+/* Validate, build the shape tables and grids, copy them to the workspace and
+ * count overlaps of the initial state (HPMC_ERR_INITIAL_OVERLAP if any).
+ * Synchronises the stream.  On success *out owns a host handle. */
+int hpmc_init(hpmc_state **out, const hpmc_init_args *args);
+
+/* n_sweeps sweeps of every replica with Philox key = seed and sweep counter
+ * t, t+1, ... continuing from the state's counter (so two calls of a and b
+ * sweeps equal one call of a + b).  Asynchronous on the state's stream. */
+int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
+
+/* Unordered overlapping pairs per replica under the exact FP64 predicate
+ * (circumsphere test and full test, the paper's system-level check, Sec. 4).
+ * out_per_replica: host, n_replicas entries.  Synchronising. */
+int hpmc_count_overlaps(hpmc_state *st, uint64_t *out_per_replica);
+
+/* Counters per replica.  out_per_replica: host, n_replicas entries.
+ * Synchronising. */
+int hpmc_get_stats(hpmc_state *st, hpmc_stats *out_per_replica);
+int hpmc_reset_stats(hpmc_state *st);
+
+/* Make the caller's pos / orient arrays current (the state works on them in
+ * place, so this only synchronises the stream). */
+int hpmc_sync_to_canonical(hpmc_state *st);
+
+/* Sweep counter, for checkpoint and resume. */
+int hpmc_get_sweep(hpmc_state *st, uint64_t *out_t);
+int hpmc_set_sweep(hpmc_state *st, uint64_t t);
+
+/* Cells per side, rounds per sweep and path chosen for replica r. */
+int hpmc_replica_info(hpmc_state *st, int32_t r, int32_t *cells_per_side, int32_t *rounds,
+                      int32_t *path);
+
+/* The hipError_t of the last failed HIP call of this state (0 if none). */
+int hpmc_last_hip_error(hpmc_state *st);
+
+void hpmc_destroy(hpmc_state *st);
+const char *hpmc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPMC_H */

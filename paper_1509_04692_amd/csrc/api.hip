@@ -1,0 +1,454 @@
+// C ABI of libhpmc: argument validation, shape tables, grids, workspace
+// layout and the sweep / count schedules.  No device allocation happens
+// here: every device buffer belongs to the caller.
+#include "../../include/hpmc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "launch.hpp"
+#include "types.hpp"
+
+using namespace hpmc;
+
+struct hpmc_state {
+    int n_replicas = 0;
+    int precision = HPMC_FP64;
+    int path = HPMC_PATH_GRID;
+    int block = 256;
+    hipStream_t stream = nullptr;
+    double* pos = nullptr;
+    double* orient = nullptr;
+    Workspace ws{};
+    std::vector<ReplicaHost> rep;
+    std::vector<SysDev> sys;
+    std::vector<SpeciesDev> spc;
+    size_t lds_bytes = 0;
+    uint64_t t = 0;
+    uint64_t sweeps_done = 0;
+    int last_hip = 0;
+};
+
+namespace {
+
+constexpr uint64_t kSweepLimit = 1ull << 32;
+constexpr size_t kAlign = 256;
+constexpr size_t kPersistentLdsMax = 64 * 1024;
+constexpr uint32_t kPersistentChunk = 64;  // sweeps per persistent launch
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+int check_hip(hpmc_state* st, hipError_t e) {
+    if (e == hipSuccess) return HPMC_OK;
+    if (st) st->last_hip = (int)e;
+    return HPMC_ERR_HIP;
+}
+
+// Per-type tables (Sec. 2.3: geometry given once per type, particle frame).
+int build_species(const hpmc_species& s, SpeciesDev& P) {
+    std::memset(&P, 0, sizeof(P));
+    P.kind = s.shape;
+    P.dim = s.dim;
+    if (!(s.d >= 0.0) || !(s.a >= 0.0) || !(s.p_rot >= 0.0) || !(s.p_rot <= 1.0))
+        return HPMC_ERR_INVALID_ARG;
+    if (s.rounds < 0) return HPMC_ERR_INVALID_ARG;
+    if (s.shape == HPMC_DISK) {
+        if (s.dim != 2 || !(s.diameter > 0.0) || s.p_rot != 0.0) return HPMC_ERR_INVALID_ARG;
+        P.R = s.diameter * 0.5;
+    } else if (s.shape == HPMC_POLYGON || s.shape == HPMC_POLYHEDRON) {
+        const int want_dim = s.shape == HPMC_POLYGON ? 2 : 3;
+        const int maxv = s.shape == HPMC_POLYGON ? kMaxPolyVerts : kMaxPolyhedronVerts;
+        if (s.dim != want_dim || s.verts == nullptr) return HPMC_ERR_INVALID_ARG;
+        if (s.n_verts < want_dim + 1 || s.n_verts > maxv) return HPMC_ERR_INVALID_ARG;
+        P.nv = s.n_verts;
+        double rmax = 0.0;
+        for (int k = 0; k < P.nv; ++k) {
+            const double x = s.verts[k * s.dim], y = s.verts[k * s.dim + 1];
+            const double z = s.dim == 3 ? s.verts[k * s.dim + 2] : 0.0;
+            if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return HPMC_ERR_INVALID_ARG;
+            P.vx[k] = x;
+            P.vy[k] = y;
+            P.vz[k] = z;
+            double r2 = x * x + y * y;
+            if (s.dim == 3) r2 = r2 + z * z;
+            const double r = std::sqrt(r2);
+            if (r > rmax) rmax = r;
+        }
+        P.R = std::nextafter(rmax, INFINITY);  // every vertex inside the circumsphere
+        if (s.shape == HPMC_POLYGON) {
+            double nmax = 0.0;
+            for (int k = 0; k < P.nv; ++k) {
+                const int k1 = (k + 1) % P.nv, k2 = (k + 2) % P.nv;
+                const double ex = P.vx[k1] - P.vx[k], ey = P.vy[k1] - P.vy[k];
+                const double fx = P.vx[k2] - P.vx[k1], fy = P.vy[k2] - P.vy[k1];
+                if (!(ex * fy - ey * fx > 0.0)) return HPMC_ERR_INVALID_ARG;  // CCW, strictly convex
+                P.nx[k] = ey;
+                P.ny[k] = -ex;
+                nmax = std::fmax(nmax, std::sqrt(ey * ey + ex * ex));
+            }
+            for (int k = 0; k < P.nv; ++k) {
+                double lo = 0.0, hi = 0.0;
+                for (int j = 0; j < P.nv; ++j) {
+                    const double p = P.nx[k] * P.vx[j] + P.ny[k] * P.vy[j];
+                    if (j == 0 || p < lo) lo = p;
+                    if (j == 0 || p > hi) hi = p;
+                }
+                P.pmin[k] = lo;
+                P.pmax[k] = hi;
+                P.vx32[k] = (float)P.vx[k];
+                P.vy32[k] = (float)P.vy[k];
+                P.nx32[k] = (float)P.nx[k];
+                P.ny32[k] = (float)P.ny[k];
+                P.pmin32[k] = (float)lo;
+                P.pmax32[k] = (float)hi;
+            }
+            // certification margin of the binary32 filter (see overlap32.hpp)
+            P.sat_margin_scale = (float)(256.0 * 0x1p-24 * nmax * P.R);
+        }
+    } else {
+        return HPMC_ERR_INVALID_ARG;
+    }
+    const double dmax = P.R + P.R;
+    P.circ2 = dmax * dmax;
+    const double tol = 1e-12 * dmax;
+    P.tol2 = tol * tol;
+    P.d = s.d;
+    P.a = s.a;
+    P.p_rot = s.p_rot;
+    return HPMC_OK;
+}
+
+// Grid of Sec. 2.2.1 with the checkerboard constraint: the largest even n
+// with cells at least d_max (times 1 + 2^-30) wide, n >= 4.
+int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, SysDev& S,
+               ReplicaHost& rh) {
+    if (!(L > 0.0) || !std::isfinite(L) || N < 1) return HPMC_ERR_INVALID_ARG;
+    const double dmax = P.R + P.R;
+    const double nf = L / (dmax * (1.0 + 0x1p-30));
+    if (nf > 65536.0) return HPMC_ERR_UNSUPPORTED;
+    int n = (int)nf;
+    n -= n & 1;
+    if (n < 4) return HPMC_ERR_BOX_TOO_SMALL;
+    if (s.dim == 3 && n > 1024) return HPMC_ERR_UNSUPPORTED;
+    if (!(s.d < L)) return HPMC_ERR_INVALID_ARG;
+    std::memset(&S, 0, sizeof(S));
+    S.L = L;
+    S.inv_L = 1.0 / L;
+    S.w = L / (double)n;
+    S.inv_w = (double)n / L;
+    S.n = n;
+    S.dim = s.dim;
+    S.N = N;
+    const int64_t ncells = s.dim == 2 ? (int64_t)n * n : (int64_t)n * n * n;
+    if (ncells > (int64_t)1 << 30) return HPMC_ERR_UNSUPPORTED;
+    S.ncells = (int32_t)ncells;
+    if (s.rounds > 0) {
+        S.rounds = s.rounds;
+    } else {
+        const int64_t r = ((int64_t)N + ncells / 2) / ncells;
+        S.rounds = r < 1 ? 1 : (int32_t)r;
+    }
+    if ((int64_t)S.rounds * (1 << s.dim) >= ((int64_t)1 << 28)) return HPMC_ERR_INVALID_ARG;
+    rh.kind = s.shape;
+    rh.dim = s.dim;
+    rh.N = N;
+    rh.n = n;
+    rh.ncells = S.ncells;
+    rh.rounds = S.rounds;
+    return HPMC_OK;
+}
+
+struct Layout {
+    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, partial, total;
+};
+
+int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<SysDev>& sys,
+         std::vector<SpeciesDev>& spc, Layout& lay, int& path, size_t& lds_bytes) {
+    if (a == nullptr || a->n_replicas < 1 || a->species == nullptr || a->N == nullptr ||
+        a->L == nullptr)
+        return HPMC_ERR_INVALID_ARG;
+    if (a->precision != HPMC_FP64 && a->precision != HPMC_MIXED) return HPMC_ERR_INVALID_ARG;
+    if (a->path < HPMC_PATH_AUTO || a->path > HPMC_PATH_PERSISTENT) return HPMC_ERR_INVALID_ARG;
+    const int R = a->n_replicas;
+    rep.assign(R, ReplicaHost{});
+    sys.assign(R, SysDev{});
+    spc.assign(R, SpeciesDev{});
+    int64_t pos_off = 0, ori_off = 0;
+    int64_t nc_max = 1, n_max = 1;
+    bool fits_lds = true;
+    lds_bytes = 0;
+    for (int r = 0; r < R; ++r) {
+        int rc = build_species(a->species[r], spc[r]);
+        if (rc) return rc;
+        rc = build_grid(a->species[r], spc[r], a->N[r], a->L[r], sys[r], rep[r]);
+        if (rc) return rc;
+        sys[r].species = r;
+        sys[r].replica = r;
+        sys[r].pos_off = pos_off;
+        sys[r].orient_off = ori_off;
+        rep[r].pos_off = pos_off;
+        rep[r].orient_off = ori_off;
+        const int ncomp = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
+        pos_off += (int64_t)sys[r].dim * sys[r].N;
+        ori_off += (int64_t)ncomp * sys[r].N;
+        nc_max = std::max<int64_t>(nc_max, sys[r].ncells);
+        n_max = std::max<int64_t>(n_max, sys[r].N);
+        const size_t lb = persistent_lds_bytes(sys[r].ncells, sys[r].N);
+        lds_bytes = std::max(lds_bytes, lb);
+        if (sys[r].N > 65535 || lb > kPersistentLdsMax) fits_lds = false;
+    }
+    if (a->path == HPMC_PATH_PERSISTENT && !fits_lds) return HPMC_ERR_UNSUPPORTED;
+    if (a->path == HPMC_PATH_AUTO)
+        path = (fits_lds && R > 1) ? HPMC_PATH_PERSISTENT : HPMC_PATH_GRID;
+    else
+        path = a->path;
+    for (int r = 0; r < R; ++r) {
+        sys[r].path = path;
+        rep[r].path = path;
+    }
+    const int64_t ntiles = (nc_max + kScanTile - 1) / kScanTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    lay.species = take(sizeof(SpeciesDev) * R);
+    lay.sys = take(sizeof(SysDev) * R);
+    lay.stats = take(sizeof(unsigned long long) * kNumStats * R);
+    lay.overlap = take(sizeof(unsigned long long) * R);
+    lay.count = take(4 * (size_t)nc_max);
+    lay.start = take(4 * ((size_t)nc_max + 1));
+    lay.cell_of = take(4 * (size_t)n_max);
+    lay.slot_of = take(4 * (size_t)n_max);
+    lay.members = take(4 * (size_t)n_max);
+    lay.partial = take(4 * (size_t)ntiles);
+    lay.total = off;
+    return HPMC_OK;
+}
+
+int count_all(hpmc_state* st, uint64_t* out) {
+    int rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
+    if (rc) return rc;
+    for (int r = 0; r < st->n_replicas; ++r) {
+        rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, 0u, 0u, 0u, 0, st->stream));
+        if (rc) return rc;
+        rc = check_hip(st, count_pairs(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
+        if (rc) return rc;
+    }
+    rc = check_hip(st, hipMemcpyAsync(out, st->ws.overlap_out, sizeof(uint64_t) * st->n_replicas,
+                                      hipMemcpyDeviceToHost, st->stream));
+    if (rc) return rc;
+    return check_hip(st, hipStreamSynchronize(st->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpmc_workspace_bytes(const hpmc_init_args* args, size_t* out_bytes) {
+    if (out_bytes == nullptr) return HPMC_ERR_INVALID_ARG;
+    std::vector<ReplicaHost> rep;
+    std::vector<SysDev> sys;
+    std::vector<SpeciesDev> spc;
+    Layout lay{};
+    int path = 0;
+    size_t lds = 0;
+    const int rc = plan(args, rep, sys, spc, lay, path, lds);
+    if (rc) return rc;
+    *out_bytes = lay.total;
+    return HPMC_OK;
+}
+
+int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
+    if (out == nullptr) return HPMC_ERR_INVALID_ARG;
+    *out = nullptr;
+    hpmc_state* st = new (std::nothrow) hpmc_state();
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    Layout lay{};
+    int rc = plan(args, st->rep, st->sys, st->spc, lay, st->path, st->lds_bytes);
+    if (rc == HPMC_OK && (args->pos == nullptr || args->workspace == nullptr)) rc = HPMC_ERR_INVALID_ARG;
+    if (rc == HPMC_OK && args->orient == nullptr) {
+        for (const auto& s : st->spc)
+            if (s.kind != kDisk) rc = HPMC_ERR_INVALID_ARG;
+    }
+    if (rc == HPMC_OK && ((uintptr_t)args->workspace % kAlign) != 0) rc = HPMC_ERR_INVALID_ARG;
+    if (rc == HPMC_OK && args->workspace_bytes < lay.total) rc = HPMC_ERR_WORKSPACE_TOO_SMALL;
+    if (rc) {
+        delete st;
+        return rc;
+    }
+    st->n_replicas = args->n_replicas;
+    st->precision = args->precision;
+    st->stream = (hipStream_t)args->stream;
+    st->pos = args->pos;
+    st->orient = args->orient ? args->orient : args->pos;  // never dereferenced for disks
+    char* base = (char*)args->workspace;
+    st->ws.species = (SpeciesDev*)(base + lay.species);
+    st->ws.sys = (SysDev*)(base + lay.sys);
+    st->ws.stats = (unsigned long long*)(base + lay.stats);
+    st->ws.overlap_out = (unsigned long long*)(base + lay.overlap);
+    st->ws.count = (uint32_t*)(base + lay.count);
+    st->ws.start = (uint32_t*)(base + lay.start);
+    st->ws.cell_of = (uint32_t*)(base + lay.cell_of);
+    st->ws.slot_of = (uint32_t*)(base + lay.slot_of);
+    st->ws.members = (uint32_t*)(base + lay.members);
+    st->ws.partial = (uint32_t*)(base + lay.partial);
+
+    rc = check_hip(st, hipMemcpyAsync(st->ws.species, st->spc.data(),
+                                      sizeof(SpeciesDev) * st->n_replicas, hipMemcpyHostToDevice,
+                                      st->stream));
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(st->ws.sys, st->sys.data(), sizeof(SysDev) * st->n_replicas,
+                                          hipMemcpyHostToDevice, st->stream));
+    if (!rc)
+        rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kNumStats * st->n_replicas, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    if (!rc) {  // positions in [0, L) and finite orientations, before any cell lookup
+        std::vector<uint64_t> bad(st->n_replicas, 0);
+        rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
+        for (int r = 0; r < st->n_replicas && !rc; ++r)
+            rc = check_hip(st, validate_state(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
+        if (!rc)
+            rc = check_hip(st, hipMemcpyAsync(bad.data(), st->ws.overlap_out,
+                                              sizeof(uint64_t) * st->n_replicas,
+                                              hipMemcpyDeviceToHost, st->stream));
+        if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+        if (!rc)
+            for (uint64_t b : bad)
+                if (b != 0) rc = HPMC_ERR_INVALID_ARG;
+    }
+    if (!rc) {
+        std::vector<uint64_t> counts(st->n_replicas, 0);
+        rc = count_all(st, counts.data());
+        if (!rc)
+            for (uint64_t c : counts)
+                if (c != 0) rc = HPMC_ERR_INITIAL_OVERLAP;
+    }
+    if (rc) {
+        delete st;
+        return rc;
+    }
+    *out = st;
+    return HPMC_OK;
+}
+
+int hpmc_sweep(hpmc_state* st, uint64_t n_sweeps, uint64_t seed) {
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    if (n_sweeps == 0) return HPMC_OK;
+    if (n_sweeps > kSweepLimit || st->t + n_sweeps > kSweepLimit) return HPMC_ERR_SWEEP_OVERFLOW;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    int rc = HPMC_OK;
+    if (st->path == HPMC_PATH_PERSISTENT) {
+        uint64_t done = 0;
+        while (done < n_sweeps && !rc) {
+            const uint32_t chunk = (uint32_t)std::min<uint64_t>(kPersistentChunk, n_sweeps - done);
+            rc = check_hip(st, persistent_sweeps(st->ws, st->n_replicas, st->lds_bytes, st->pos,
+                                                 st->orient, st->precision,
+                                                 (uint32_t)(st->t + done), chunk, k0, k1, st->block,
+                                                 st->stream));
+            done += chunk;
+        }
+    } else {
+        for (uint64_t s = 0; s < n_sweeps && !rc; ++s) {
+            const uint32_t t = (uint32_t)(st->t + s);
+            for (int r = 0; r < st->n_replicas && !rc; ++r) {
+                rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, t, k0, k1, 1, st->stream));
+                if (!rc)
+                    rc = check_hip(st, grid_passes(st->ws, st->rep[r], r, st->pos, st->orient,
+                                                   st->precision, t, k0, k1, st->stream));
+            }
+        }
+    }
+    if (rc) return rc;
+    st->t += n_sweeps;
+    st->sweeps_done += n_sweeps;
+    return HPMC_OK;
+}
+
+int hpmc_count_overlaps(hpmc_state* st, uint64_t* out_per_replica) {
+    if (st == nullptr || out_per_replica == nullptr) return HPMC_ERR_INVALID_ARG;
+    return count_all(st, out_per_replica);
+}
+
+int hpmc_get_stats(hpmc_state* st, hpmc_stats* out) {
+    if (st == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
+    std::vector<unsigned long long> raw((size_t)kNumStats * st->n_replicas);
+    int rc = check_hip(st, hipMemcpyAsync(raw.data(), st->ws.stats, raw.size() * sizeof(raw[0]),
+                                          hipMemcpyDeviceToHost, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    if (rc) return rc;
+    for (int r = 0; r < st->n_replicas; ++r) {
+        const unsigned long long* v = raw.data() + (size_t)r * kNumStats;
+        out[r].attempted = v[kAttempted];
+        out[r].attempted_rot = v[kAttemptedRot];
+        out[r].cell_reject = v[kCellReject];
+        out[r].overlap_reject = v[kOverlapReject];
+        out[r].accept = v[kAccept];
+        out[r].pair_tests = v[kPairTests];
+        out[r].pair_fp64 = v[kPairFp64];
+        out[r].sweeps = st->sweeps_done;
+    }
+    return HPMC_OK;
+}
+
+int hpmc_reset_stats(hpmc_state* st) {
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    st->sweeps_done = 0;
+    return check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kNumStats * st->n_replicas, st->stream));
+}
+
+int hpmc_sync_to_canonical(hpmc_state* st) {
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    return check_hip(st, hipStreamSynchronize(st->stream));
+}
+
+int hpmc_get_sweep(hpmc_state* st, uint64_t* out_t) {
+    if (st == nullptr || out_t == nullptr) return HPMC_ERR_INVALID_ARG;
+    *out_t = st->t;
+    return HPMC_OK;
+}
+
+int hpmc_set_sweep(hpmc_state* st, uint64_t t) {
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    if (t >= kSweepLimit) return HPMC_ERR_SWEEP_OVERFLOW;
+    st->t = t;
+    return HPMC_OK;
+}
+
+int hpmc_replica_info(hpmc_state* st, int32_t r, int32_t* cells_per_side, int32_t* rounds,
+                      int32_t* path) {
+    if (st == nullptr || r < 0 || r >= st->n_replicas) return HPMC_ERR_INVALID_ARG;
+    if (cells_per_side) *cells_per_side = st->rep[r].n;
+    if (rounds) *rounds = st->rep[r].rounds;
+    if (path) *path = st->path;
+    return HPMC_OK;
+}
+
+int hpmc_last_hip_error(hpmc_state* st) { return st ? st->last_hip : 0; }
+
+void hpmc_destroy(hpmc_state* st) {
+    if (st == nullptr) return;
+    (void)hipStreamSynchronize(st->stream);
+    delete st;
+}
+
+const char* hpmc_strerror(int code) {
+    switch (code) {
+        case HPMC_OK: return "ok";
+        case HPMC_ERR_INVALID_ARG: return "invalid argument";
+        case HPMC_ERR_BOX_TOO_SMALL: return "box too small: fewer than 4 cells per side";
+        case HPMC_ERR_INITIAL_OVERLAP: return "initial configuration has overlapping particles";
+        case HPMC_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case HPMC_ERR_HIP: return "HIP runtime error";
+        case HPMC_ERR_SWEEP_OVERFLOW: return "sweep counter would exceed 2^32";
+        case HPMC_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

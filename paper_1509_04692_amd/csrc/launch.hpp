@@ -1,0 +1,63 @@
+// Host-side view of the workspace and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "types.hpp"
+
+namespace hpmc {
+
+struct Workspace {
+    SpeciesDev* species;              // one per replica
+    SysDev* sys;                      // one per replica
+    unsigned long long* stats;        // n_replicas x kNumStats
+    unsigned long long* overlap_out;  // n_replicas
+    // global-memory cell list, sized for the largest grid-path replica
+    uint32_t* count;    // ncells
+    uint32_t* start;    // ncells + 1
+    uint32_t* cell_of;  // N
+    uint32_t* slot_of;  // N
+    uint32_t* members;  // N
+    uint32_t* partial;  // scan tiles
+};
+
+struct ReplicaHost {
+    int32_t kind, dim, N, n, ncells, rounds, path;
+    int64_t pos_off, orient_off;
+};
+
+constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
+
+// Cell list of replica r in global memory: shifted grid of sweep t when
+// shifted != 0, the unshifted grid otherwise.
+hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                       uint32_t t, uint32_t k0, uint32_t k1, int shifted, hipStream_t stream);
+
+// All colour passes of sweep t for replica r on the global cell list.
+hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
+                       double* orient, int precision, uint32_t t, uint32_t k0, uint32_t k1,
+                       hipStream_t stream);
+
+// n_sweeps whole sweeps of every replica, one work-group of `block` lanes
+// each (all replicas must be on the persistent path).
+hipError_t persistent_sweeps(const Workspace& ws, int n_replicas, size_t lds_bytes, double* pos,
+                             double* orient, int precision, uint32_t t0, uint32_t n_sweeps,
+                             uint32_t k0, uint32_t k1, int block, hipStream_t stream);
+
+// Overlapping pairs of replica r (after build_cells with shifted = 0), added
+// to ws.overlap_out[r].
+hipError_t count_pairs(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                       const double* orient, hipStream_t stream);
+
+// Invalid particles of replica r (coordinate outside [0, L), non-finite
+// orientation) added to ws.overlap_out[r].
+hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                          const double* orient, hipStream_t stream);
+
+hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream);
+
+size_t persistent_lds_bytes(int ncells, int N);
+
+}  // namespace hpmc

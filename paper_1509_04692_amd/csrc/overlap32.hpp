@@ -1,0 +1,95 @@
+// Certified binary32 filter for the polygon overlap test.
+//
+// The mixed-precision mode of the paper computes the min-image separation in
+// binary64, casts it to binary32 and trusts the binary32 test (Sec. 2.3).
+// Here a binary32 decision is only trusted when it cannot differ from the
+// binary64 decision: every projection value computed in binary32 (inputs cast
+// from binary64, any operation order, fused or not) lies within
+// E32 <= 77 u32 |n| R of the exact value defined by the binary64 inputs, and
+// the binary64 evaluation within E64 <= 40 u64 |n| R (u = unit roundoff,
+// |n| the longest edge normal, R the circumradius, |r| < 2R after the
+// circumsphere test).  The margin M = 256 u32 max|n| R exceeds E32 + E64 by
+// more than 3x, covering the rounding of the threshold itself.  An axis is
+// certainly separating when its binary32 gap exceeds +M and certainly not when
+// it is below -M; anything else makes the pair uncertain, and the caller then
+// evaluates it in binary64 exactly as the FP64 path does.
+#pragma once
+
+#include "device_common.hpp"
+#include "types.hpp"
+
+namespace hpmc {
+
+enum : int { kNoOverlap = 0, kOverlap = 1, kUncertain = 2 };
+
+__device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd,
+                                                 double cAd, double sAd, double cBd, double sBd) {
+    const int nv = P.nv;
+    const float M = P.sat_margin_scale;
+    const float rx = (float)rxd, ry = (float)ryd;
+    const float cA = (float)cAd, sA = (float)sAd, cB = (float)cBd, sB = (float)sBd;
+    const float zc = fmaf(cA, cB, sA * sB);
+    const float zs = fmaf(cA, sB, -(sA * cB));
+    const float tx = fmaf(cA, rx, sA * ry);
+    const float ty = fmaf(cA, ry, -(sA * rx));
+
+    bool unsure = false;
+    float px[kMaxPolyVerts], py[kMaxPolyVerts];
+#pragma unroll
+    for (int j = 0; j < kMaxPolyVerts; ++j) {
+        if (j < nv) {
+            px[j] = fmaf(zc, P.vx32[j], fmaf(-zs, P.vy32[j], tx));
+            py[j] = fmaf(zs, P.vx32[j], fmaf(zc, P.vy32[j], ty));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxPolyVerts; ++k) {
+        if (k < nv) {
+            const float nx = P.nx32[k], ny = P.ny32[k];
+            float lo = fmaf(nx, px[0], ny * py[0]);
+            float hi = lo;
+#pragma unroll
+            for (int j = 1; j < kMaxPolyVerts; ++j) {
+                if (j < nv) {
+                    const float p = fmaf(nx, px[j], ny * py[j]);
+                    lo = fminf(lo, p);
+                    hi = fmaxf(hi, p);
+                }
+            }
+            const float amax = P.pmax32[k], amin = P.pmin32[k];
+            if (lo >= amax + M || hi <= amin - M) return kNoOverlap;
+            unsure |= !(lo < amax - M && hi > amin + M);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxPolyVerts; ++j) {
+        if (j < nv) {
+            const float ux = P.vx32[j] - tx;
+            const float uy = P.vy32[j] - ty;
+            px[j] = fmaf(zc, ux, zs * uy);
+            py[j] = fmaf(zc, uy, -(zs * ux));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxPolyVerts; ++k) {
+        if (k < nv) {
+            const float nx = P.nx32[k], ny = P.ny32[k];
+            float lo = fmaf(nx, px[0], ny * py[0]);
+            float hi = lo;
+#pragma unroll
+            for (int j = 1; j < kMaxPolyVerts; ++j) {
+                if (j < nv) {
+                    const float p = fmaf(nx, px[j], ny * py[j]);
+                    lo = fminf(lo, p);
+                    hi = fmaxf(hi, p);
+                }
+            }
+            const float bmax = P.pmax32[k], bmin = P.pmin32[k];
+            if (hi <= bmin - M || lo >= bmax + M) return kNoOverlap;
+            unsure |= !(hi > bmin + M && lo < bmax - M);
+        }
+    }
+    return unsure ? kUncertain : kOverlap;
+}
+
+}  // namespace hpmc

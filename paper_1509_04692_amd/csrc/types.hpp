@@ -1,0 +1,45 @@
+// Tables shared by the host side of the library and its kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace hpmc {
+
+constexpr int kMaxPolyVerts = 8;     // polygons: 3..8 vertices
+constexpr int kMaxPolyhedronVerts = 64;
+
+enum Kind : int32_t { kDisk = 0, kPolygon = 1, kPolyhedron = 2 };
+
+// Counters kept per replica in the workspace (u64 each), same order as
+// hpmc_stats minus the host-side sweep count.
+enum Stat : int { kAttempted = 0, kAttemptedRot, kCellReject, kOverlapReject, kAccept,
+                  kPairTests, kPairFp64, kNumStats };
+
+// One particle type, built on the host at init.  Vertex coordinates are
+// stored per axis so that a uniform loop over vertices reads scalars.
+struct alignas(16) SpeciesDev {
+    int32_t kind, dim, nv, pad0;
+    double R;        // circumradius, rounded up one ulp
+    double circ2;    // circumsphere threshold (R + R)^2
+    double tol2;     // squared XenoCollide tolerance
+    double d, a, p_rot;
+    double vx[kMaxPolyhedronVerts], vy[kMaxPolyhedronVerts], vz[kMaxPolyhedronVerts];
+    double nx[kMaxPolyVerts], ny[kMaxPolyVerts];      // polygon outward edge normals
+    double pmin[kMaxPolyVerts], pmax[kMaxPolyVerts];  // own projections onto them
+    // binary32 copies for the mixed-precision filter
+    float vx32[kMaxPolyVerts], vy32[kMaxPolyVerts];
+    float nx32[kMaxPolyVerts], ny32[kMaxPolyVerts];
+    float pmin32[kMaxPolyVerts], pmax32[kMaxPolyVerts];
+    float sat_margin_scale;  // forward-error bound factor of the polygon filter
+    float pad1[3];
+};
+
+// One replica (independent system) and its grid.
+struct alignas(16) SysDev {
+    double L, inv_L, w, inv_w;
+    int32_t n, dim, N, rounds;
+    int32_t ncells, species, replica, path;
+    int64_t pos_off, orient_off;  // element offsets into the caller's arrays
+};
+
+}  // namespace hpmc

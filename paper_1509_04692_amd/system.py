@@ -1,0 +1,191 @@
+"""Python front end of libhpmc: device buffers and streams come from PyTorch,
+every step of the sweep runs in the library's HIP kernels.
+
+    sys = System(species, N, L, pos, orient, precision="mixed")
+    sys.sweep(1000, seed=1)           # like the paper's hoomd.run(n) (Fig. 1)
+    sys.count_overlaps()              # system-level overlap check (Sec. 4)
+    sys.stats()
+
+``species`` is a dict (or one per replica) with keys dim, shape ("disk",
+"polygon", "polyhedron"), verts (n x dim), diameter, d, a, p_rot and rounds,
+as produced by ``paper_1509_04692_amd.inputs``.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+_NCOMP = {"disk": 0, "polygon": 2, "polyhedron": 4}
+
+
+def _as_list(x, n):
+    if isinstance(x, (list, tuple)):
+        if len(x) != n:
+            raise ValueError("per-replica argument has the wrong length")
+        return list(x)
+    return [x] * n
+
+
+class System:
+    def __init__(self, species, N, L, pos, orient=None, precision="fp64", path="auto",
+                 device="cuda", stream=None):
+        import torch
+
+        self._torch = torch
+        self._lib = _lib.load()
+        if isinstance(pos, (list, tuple)):
+            n_rep = len(pos)
+        else:
+            n_rep = 1
+            pos = [pos]
+            orient = [orient]
+        if orient is None:
+            orient = [None] * n_rep
+        self.n_replicas = n_rep
+        self.species = _as_list(species, n_rep)
+        self.N = [int(x) for x in _as_list(N, n_rep)]
+        self.L = [float(x) for x in _as_list(L, n_rep)]
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("System needs a GPU device")
+
+        pos_parts, ori_parts = [], []
+        self._pos_off, self._ori_off = [], []
+        po = oo = 0
+        for r in range(n_rep):
+            sp, Nr = self.species[r], self.N[r]
+            p = np.ascontiguousarray(np.asarray(pos[r], dtype=np.float64))
+            if p.shape != (sp["dim"], Nr):
+                raise ValueError(f"replica {r}: pos must have shape (dim, N)")
+            pos_parts.append(p.ravel())
+            self._pos_off.append(po)
+            po += p.size
+            k = _NCOMP[sp["shape"]]
+            self._ori_off.append(oo)
+            if k:
+                o = np.ascontiguousarray(np.asarray(orient[r], dtype=np.float64))
+                if o.shape != (k, Nr):
+                    raise ValueError(f"replica {r}: orient must have shape ({k}, N)")
+                ori_parts.append(o.ravel())
+                oo += o.size
+        self.pos = torch.from_numpy(np.concatenate(pos_parts)).to(self.device)
+        ori = np.concatenate(ori_parts) if ori_parts else np.zeros(1)
+        self.orient = torch.from_numpy(ori).to(self.device)
+
+        self._keep = []
+        sp_arr = (_lib.Species * n_rep)()
+        for r, sp in enumerate(self.species):
+            s = sp_arr[r]
+            s.dim = int(sp["dim"])
+            s.shape = _lib.SHAPES[sp["shape"]]
+            if sp["shape"] != "disk":
+                v = np.ascontiguousarray(np.asarray(sp["verts"], dtype=np.float64))
+                self._keep.append(v)
+                s.n_verts = v.shape[0]
+                s.verts = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            s.diameter = float(sp.get("diameter", 0.0))
+            s.d = float(sp.get("d", 0.0))
+            s.a = float(sp.get("a", 0.0))
+            s.p_rot = float(sp.get("p_rot", 0.0))
+            s.rounds = int(sp.get("rounds", 0))
+        self._sp_arr = sp_arr
+        self._N_arr = (ctypes.c_int32 * n_rep)(*self.N)
+        self._L_arr = (ctypes.c_double * n_rep)(*self.L)
+
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        args = _lib.InitArgs()
+        args.n_replicas = n_rep
+        args.species = sp_arr
+        args.N = self._N_arr
+        args.L = self._L_arr
+        args.precision = _lib.PRECISIONS[precision]
+        args.path = _lib.PATHS[path]
+        args.pos = self.pos.data_ptr()
+        args.orient = self.orient.data_ptr()
+        args.stream = stream.cuda_stream
+        nbytes = ctypes.c_size_t()
+        self._check(self._lib.hpmc_workspace_bytes(ctypes.byref(args), ctypes.byref(nbytes)),
+                    "hpmc_workspace_bytes")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        args.workspace = (base + 255) // 256 * 256
+        args.workspace_bytes = nbytes.value
+        self._args = args
+        handle = ctypes.c_void_p()
+        self._handle = None
+        self._check(self._lib.hpmc_init(ctypes.byref(handle), ctypes.byref(args)), "hpmc_init")
+        self._handle = handle
+        self.precision = precision
+
+    # -- calls -------------------------------------------------------------
+    def _check(self, rc, what):
+        if rc != _lib.HPMC_OK:
+            hip = self._lib.hpmc_last_hip_error(self._handle) if getattr(self, "_handle", None) else 0
+            raise _lib.HpmcError(rc, what, hip)
+
+    def sweep(self, n_sweeps, seed):
+        self._check(self._lib.hpmc_sweep(self._handle, int(n_sweeps), int(seed)), "hpmc_sweep")
+
+    def count_overlaps(self):
+        out = (ctypes.c_uint64 * self.n_replicas)()
+        self._check(self._lib.hpmc_count_overlaps(self._handle, out), "hpmc_count_overlaps")
+        return np.array(out[:], dtype=np.uint64)
+
+    def stats(self):
+        out = (_lib.Stats * self.n_replicas)()
+        self._check(self._lib.hpmc_get_stats(self._handle, out), "hpmc_get_stats")
+        return [{f: int(getattr(out[r], f)) for f in _lib.STAT_FIELDS}
+                for r in range(self.n_replicas)]
+
+    def reset_stats(self):
+        self._check(self._lib.hpmc_reset_stats(self._handle), "hpmc_reset_stats")
+
+    @property
+    def sweep_counter(self):
+        t = ctypes.c_uint64()
+        self._check(self._lib.hpmc_get_sweep(self._handle, ctypes.byref(t)), "hpmc_get_sweep")
+        return t.value
+
+    @sweep_counter.setter
+    def sweep_counter(self, t):
+        self._check(self._lib.hpmc_set_sweep(self._handle, int(t)), "hpmc_set_sweep")
+
+    def replica_info(self, r=0):
+        n, rounds, path = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.hpmc_replica_info(self._handle, r, ctypes.byref(n), ctypes.byref(rounds),
+                                                ctypes.byref(path)), "hpmc_replica_info")
+        return {"n": n.value, "rounds": rounds.value,
+                "path": {v: k for k, v in _lib.PATHS.items()}[path.value]}
+
+    def synchronize(self):
+        self._check(self._lib.hpmc_sync_to_canonical(self._handle), "hpmc_sync_to_canonical")
+
+    def positions(self, r=0):
+        """(dim, N) float64 numpy copy of replica r."""
+        self.synchronize()
+        sp, Nr = self.species[r], self.N[r]
+        o = self._pos_off[r]
+        return self.pos[o:o + sp["dim"] * Nr].view(sp["dim"], Nr).cpu().numpy()
+
+    def orientations(self, r=0):
+        self.synchronize()
+        sp, Nr = self.species[r], self.N[r]
+        k = _NCOMP[sp["shape"]]
+        if k == 0:
+            return None
+        o = self._ori_off[r]
+        return self.orient[o:o + k * Nr].view(k, Nr).cpu().numpy()
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            self._lib.hpmc_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

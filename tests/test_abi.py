@@ -1,0 +1,106 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/hpmc.h declares, and its host-side argument validation (grid rule,
+shape checks) behaves as documented.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1509_04692_amd import _lib, inputs
+from paper_1509_04692_amd.build import LIB_PATH
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "hpmc.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB_PATH):
+        pytest.fail("libhpmc.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpmc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_documented_entry_points():
+    names = declared_functions()
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror(lib):
+    assert lib.hpmc_strerror(0) == b"ok"
+    assert b"overlap" in lib.hpmc_strerror(-3)
+    assert lib.hpmc_strerror(-99) == b"unknown error"
+
+
+def _args(species_list, Ns, Ls, precision=0, path=0):
+    n = len(species_list)
+    keep = []
+    sp_arr = (_lib.Species * n)()
+    for r, sp in enumerate(species_list):
+        s = sp_arr[r]
+        s.dim, s.shape = sp["dim"], _lib.SHAPES[sp["shape"]]
+        if sp["shape"] != "disk":
+            v = np.ascontiguousarray(sp["verts"], dtype=np.float64)
+            keep.append(v)
+            s.n_verts = v.shape[0]
+            s.verts = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.diameter = sp.get("diameter", 0.0)
+        s.d, s.a, s.p_rot, s.rounds = sp["d"], sp["a"], sp["p_rot"], sp.get("rounds", 0)
+    a = _lib.InitArgs()
+    a.n_replicas = n
+    a.species = sp_arr
+    Narr = (ctypes.c_int32 * n)(*Ns)
+    Larr = (ctypes.c_double * n)(*Ls)
+    a.N, a.L = Narr, Larr
+    a.precision, a.path = precision, path
+    return a, (keep, sp_arr, Narr, Larr)
+
+
+def ws_bytes(lib, *args, **kw):
+    a, keep = _args(*args, **kw)
+    out = ctypes.c_size_t()
+    rc = lib.hpmc_workspace_bytes(ctypes.byref(a), ctypes.byref(out))
+    return rc, out.value
+
+
+def test_workspace_size_grows_with_the_system(lib):
+    sp = inputs.pentagon_species()
+    rc1, b1 = ws_bytes(lib, [sp], [4096], [63.70118630129784])
+    rc2, b2 = ws_bytes(lib, [sp], [4194304], [2038.438])
+    assert rc1 == rc2 == 0
+    assert b2 > b1 > 0
+    # global cell list: >= 4 B x (cells + 1) + 12 B per particle
+    assert b2 >= 4 * (2038 * 2038 + 1) + 12 * 4194304
+
+
+def test_box_too_small_and_invalid_shapes(lib):
+    disk = inputs.disk_species()
+    assert ws_bytes(lib, [disk], [9], [3.9])[0] == -2
+    assert ws_bytes(lib, [disk], [16], [4.1])[0] == 0
+    cw = dict(inputs.pentagon_species(), verts=inputs.pentagon_species()["verts"][::-1].copy())
+    assert ws_bytes(lib, [cw], [100], [20.0])[0] == -1  # clockwise polygon
+    bad_rot = dict(disk, p_rot=0.5)
+    assert ws_bytes(lib, [bad_rot], [100], [20.0])[0] == -1  # disks do not rotate
+    nine = dict(inputs.pentagon_species(), verts=inputs.regular_polygon_vertices(9, 0.5))
+    assert ws_bytes(lib, [nine], [100], [20.0])[0] == -1  # more than 8 polygon vertices
+    assert ws_bytes(lib, [disk], [0], [20.0])[0] == -1
+    assert ws_bytes(lib, [disk], [10], [20.0], precision=5)[0] == -1
+
+
+def test_persistent_path_limits(lib):
+    sp = inputs.pentagon_species()
+    # N beyond the 16-bit LDS member index cannot use the persistent path
+    assert ws_bytes(lib, [sp], [70000], [400.0], path=2)[0] == -7
+    assert ws_bytes(lib, [sp, sp], [4096, 4096], [63.7, 63.7], path=2)[0] == 0

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP sweep against the FP64 reference oracle.
+
+Both sides run the same checkerboard sweep with the same Philox streams from
+the same seeded initial state.  FP64 runs must agree bit for bit in the final
+positions and orientations and in every parity counter (attempted, rotations,
+cell rejects, overlap rejects, accepts) -- a single differing accept decision
+changes the trajectory and fails the comparison.  MIXED runs must agree bit
+for bit with the FP64 oracle as well: their binary32 decisions are certified
+and uncertain pairs are re-evaluated in binary64.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_04692_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+PARITY = ("attempted", "attempted_rot", "cell_reject", "overlap_reject", "accept")
+
+
+def _system(*a, **kw):
+    from paper_1509_04692_amd.system import System
+    return System(*a, **kw)
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(sp, L, pos, orient, n_sweeps, seed, precision="fp64", path="grid", t0=0):
+    N = pos.shape[1]
+    announce(f"{sp['shape']} N={N} L={L:.4f} sweeps={n_sweeps} seed={seed} {precision} {path}")
+    system = _system(sp, N, L, pos, orient, precision=precision, path=path)
+    if t0:
+        system.sweep_counter = t0
+    system.sweep(n_sweeps, seed)
+    gpu_pos, gpu_ori = system.positions(), system.orientations()
+    gpu_stats = system.stats()[0]
+    ref_pos, ref_ori = pos.copy(), orient.copy()
+    ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=seed, n_sweeps=n_sweeps, t0=t0)
+    return system, (gpu_pos, gpu_ori, gpu_stats), (ref_pos, ref_ori, ref_stats)
+
+
+def assert_parity(gpu, ref, sp):
+    gpu_pos, gpu_ori, gpu_stats = gpu
+    ref_pos, ref_ori, ref_stats = ref
+    assert [gpu_stats[k] for k in PARITY] == [int(x) for x in ref_stats], (gpu_stats, ref_stats)
+    assert np.array_equal(gpu_pos, ref_pos), np.argwhere(gpu_pos != ref_pos)[:5]
+    if sp["shape"] != "disk":
+        assert np.array_equal(gpu_ori, ref_ori), np.argwhere(gpu_ori != ref_ori)[:5]
+
+
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_disks_256_thousand_sweeps(path):
+    """2D hard disks, N=256, phi=0.50, d=0.1, seed 1, 1000 sweeps."""
+    sp, N, L, pos, orient = inputs.workload_disks_256()
+    system, gpu, ref = run_pair(sp, L, pos, orient, 1000, seed=1, path=path)
+    assert_parity(gpu, ref, sp)
+    assert system.count_overlaps()[0] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_pentagons_4096(precision, path):
+    """Regular pentagons, N=4096, phi=0.60, translation d=0.1 / rotation a=0.2, p_rot=0.5."""
+    sp, N, L, pos, orient = inputs.workload_pentagons(4096, 0.60)
+    system, gpu, ref = run_pair(sp, L, pos, orient, 40, seed=1, precision=precision, path=path)
+    assert_parity(gpu, ref, sp)
+    st = gpu[2]
+    assert st["pair_tests"] > 0
+    if precision == "mixed":
+        frac = st["pair_fp64"] / st["pair_tests"]
+        print(f"re-checked fraction {frac:.3e} of {st['pair_tests']} pair tests", flush=True)
+        assert frac < 0.01
+    else:
+        assert st["pair_fp64"] == st["pair_tests"]
+    assert system.count_overlaps()[0] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pentagons_dense_interlocked(precision):
+    """phi=0.70 from the interlocked up/down lattice, ragged N (not a lattice square)."""
+    sp, N, L, pos, orient = inputs.workload_pentagons(1000, 0.70)
+    system, gpu, ref = run_pair(sp, L, pos, orient, 30, seed=7, precision=precision, path="grid")
+    assert_parity(gpu, ref, sp)
+
+
+@pytest.mark.parametrize("shape", ["cube", "trunc_oct"])
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_polyhedra(shape, path):
+    if shape == "cube":
+        sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
+    else:
+        sp, N, L, pos, orient = inputs.workload_truncated_octahedra(343, 0.45)
+    system, gpu, ref = run_pair(sp, L, pos, orient, 10, seed=3, path=path)
+    assert_parity(gpu, ref, sp)
+    assert system.count_overlaps()[0] == 0
+
+
+def test_batched_heterogeneous_replicas():
+    """Disk and pentagon replicas of different N and phi in one persistent launch;
+    each must equal the oracle run with its own replica word."""
+    batch = inputs.screening_batch(n_replicas=6, seed=2026, n_lo=64, n_hi=700)
+    species = [b[0] for b in batch]
+    Ns = [b[1] for b in batch]
+    Ls = [b[2] for b in batch]
+    announce(f"batch N={Ns}")
+    system = _system(species, Ns, Ls, [b[3] for b in batch], [b[4] for b in batch],
+                     precision="mixed", path="persistent")
+    system.sweep(25, seed=11)
+    stats = system.stats()
+    for r, (sp, N, L, pos, orient) in enumerate(batch):
+        ref_pos, ref_ori = pos.copy(), orient.copy()
+        ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=11, n_sweeps=25, replica=r)
+        assert [stats[r][k] for k in PARITY] == [int(x) for x in ref_stats], r
+        assert np.array_equal(system.positions(r), ref_pos), r
+        if sp["shape"] != "disk":
+            assert np.array_equal(system.orientations(r), ref_ori), r
+    assert np.all(system.count_overlaps() == 0)
+
+
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_resume_equals_one_long_run(path):
+    sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.60)
+    announce(f"resume {path}")
+    a = _system(sp, N, L, pos, orient, path=path)
+    a.sweep(9, seed=5)
+    b = _system(sp, N, L, pos, orient, path=path)
+    b.sweep(4, seed=5)
+    b.sweep(5, seed=5)
+    assert a.sweep_counter == b.sweep_counter == 9
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.orientations(), b.orientations())
+    # restart from a saved state and counter
+    c = _system(sp, N, L, b.positions(), b.orientations(), path=path)
+    c.sweep_counter = 9
+    c.sweep(3, seed=5)
+    a.sweep(3, seed=5)
+    assert np.array_equal(a.positions(), c.positions())
+
+
+@pytest.mark.parametrize("kind", ["disk", "pentagon", "cube"])
+def test_count_overlaps_matches_oracle_on_overlapping_states(kind):
+    """Random (overlapping) states cannot be initialised, so the count is
+    checked after placing particles by a sweep-free route: a valid state is
+    created and its positions then overwritten on the device."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(41))
+    if kind == "disk":
+        sp, N, L, pos, orient = inputs.workload_disks_256()
+    elif kind == "pentagon":
+        sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.5)
+    else:
+        sp, N, L, pos, orient = inputs.workload_cubes(512, 0.3)
+    announce(f"count {kind}")
+    system = _system(sp, N, L, pos, orient)
+    rnd_pos = np.ascontiguousarray(rng.uniform(0, L, size=pos.shape))
+    rnd_ori = orient.copy()
+    if kind == "pentagon":
+        t = rng.uniform(-np.pi, np.pi, size=N)
+        rnd_ori = np.ascontiguousarray(np.stack([np.cos(t), np.sin(t)]))
+    elif kind == "cube":
+        q = rng.normal(size=(4, N))
+        rnd_ori = np.ascontiguousarray(q / np.linalg.norm(q, axis=0))
+    system.pos.copy_(torch.from_numpy(rnd_pos.ravel()))
+    if kind != "disk":
+        system.orient.copy_(torch.from_numpy(rnd_ori.ravel()))
+    want = oracle.count_overlaps(sp, L, rnd_pos, rnd_ori)
+    assert want > 0
+    assert int(system.count_overlaps()[0]) == want
+
+
+def test_initial_overlap_and_box_errors():
+    from paper_1509_04692_amd._lib import HpmcError
+    sp, N, L, pos, orient = inputs.workload_disks_256()
+    bad = pos.copy()
+    bad[:, 1] = bad[:, 0] + 0.3  # particle 1 on top of particle 0
+    announce("error paths")
+    with pytest.raises(HpmcError) as e:
+        _system(sp, N, L, bad, orient)
+    assert e.value.code == -3
+    outside = pos.copy()
+    outside[0, 0] = L + 1.0
+    with pytest.raises(HpmcError) as e:
+        _system(sp, N, L, outside, orient)
+    assert e.value.code == -1
+    with pytest.raises(HpmcError) as e:
+        _system(sp, 4, 3.9, pos[:, :4] * (3.9 / L), None)
+    assert e.value.code == -2
+
+
+def test_single_particle_and_sparse_cells():
+    """N=1 (every move in the only occupied cell) and a dilute system in which
+    most cells are empty."""
+    sp = inputs.disk_species(d=0.3)
+    pos = np.array([[2.5], [3.5]])
+    system, gpu, ref = run_pair(sp, 10.0, pos, np.zeros((1, 1)), 200, seed=2)
+    assert_parity(gpu, ref, sp)
+    sp2, N2, L2, pos2, ori2 = inputs.workload_pentagons(64, 0.05)
+    system, gpu, ref = run_pair(sp2, L2, pos2, ori2, 100, seed=2)
+    assert_parity(gpu, ref, sp2)
+
+
+def test_full_size_large_pentagons_one_sweep():
+    """N=4,194,304 pentagons at phi=0.60 (the large single-GPU share) in the
+    grid-path launch configuration the benchmark times: one sweep, FP64 and
+    MIXED, bitwise against the oracle."""
+    sp, N, L, pos, orient = inputs.workload_pentagons(4194304, 0.60)
+    for precision in ("fp64", "mixed"):
+        system, gpu, ref = run_pair(sp, L, pos, orient, 1, seed=1, precision=precision, path="grid")
+        assert_parity(gpu, ref, sp)
+        del system
+
+
+def test_full_size_cubes_and_truncated_octahedra():
+    """N=32768 cubes (2 rounds per sweep) and truncated octahedra at phi=0.45."""
+    for sp, N, L, pos, orient in (inputs.workload_cubes(32768, 0.45),
+                                  inputs.workload_truncated_octahedra(32768, 0.45)):
+        system, gpu, ref = run_pair(sp, L, pos, orient, 2, seed=1, path="grid")
+        assert_parity(gpu, ref, sp)
