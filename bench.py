@@ -1,0 +1,271 @@
+#!/usr/bin/env python3
+"""Trial moves per second of the checkerboard hard-shape sweep on one MI355X.
+
+Default workload (the headline metric): 512 independent replicas of 4096
+regular pentagons (circumradius 0.5, packing fraction 0.60, d = 0.1,
+a = 0.2, p_rot = 0.5) in one persistent launch with the certified
+mixed-precision overlap test, against the plain FP64 single-system path on
+the same GPU.  One step is one sweep (N trial moves per replica) of every
+replica.  Inputs are resident on the GPU before the timed region; trial
+moves are counted on the device (attempted moves, cell rejects included).
+
+Prints one JSON line.  Extra fields: the other three precision x batching
+combinations, the re-checked pair fraction, a roofline object for the
+timed kernel and the reference oracle timed on one host core.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# One VALU operation per lane per clock: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# (non-packed fp32 and fp64 run at this rate; an FMA counts as one operation,
+# i.e. this is half the 78.6 TFLOP/s fp64 figure, which counts FMA as two).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+PERSISTENT_SWEEPS_PER_LAUNCH = 64  # HPMC_PERSISTENT_SWEEPS_PER_LAUNCH
+
+
+def op_costs(nv):
+    """Operations (+ - * / sqrt rint min max compare) of each counted event,
+    from the pinned formulas of the sweep; nv = vertices of the shape."""
+    return {
+        "translate": 12,            # per axis; multiplied by dim below
+        "rotate2": 43,              # angle 5 + sin/cos polynomial 32 + complex product 6
+        "rotate3": 55,              # vector 15 + quaternion product 28 + norm 8 + 4 divisions
+        "cand2": 14,                # 2 x min-image (5) + |r|^2 (3) + compare
+        "cand3": 21,                # 3 x min-image (5) + |r|^2 (5) + compare
+        "sat_setup": 12 + 8 * nv,   # relative rotation 6 + offset 6 + nv vertex maps
+        "sat_axis": 5 * nv,         # nv projections (3) + min/max (2 (nv-1)) + 2 compares
+        "sat_frame_b": 8 * nv,      # nv vertex maps into B's frame
+        "mpr_setup": 169,           # relative rotation, two matrices, offset, first portal
+        "mpr_support": 34 + 12 * nv,
+        "mpr_iter": 55,
+    }
+
+
+def ops_per_move(events, attempted, dim, nv):
+    c = op_costs(nv)
+    total = 0
+    for k, v in events.items():
+        total += v * c[k] * (dim if k == "translate" else 1)
+    return total / max(attempted, 1)
+
+
+def workload(name):
+    from paper_1509_04692_amd import inputs
+    if name == "pentagons":
+        sp, N, L, pos, ori = inputs.workload_pentagons(4096, 0.60)
+        return {"desc": "regular pentagons N=4096 R=0.5 phi=0.60 d=0.1 a=0.2 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 512}
+    if name == "disks":
+        sp, N, L, pos, ori = inputs.workload_disks_256()
+        return {"desc": "hard disks N=256 sigma=1 phi=0.50 d=0.1",
+                "items": [(sp, N, L, pos, ori)], "replicas": 512}
+    if name == "cubes":
+        sp, N, L, pos, ori = inputs.workload_cubes(32768, 0.45)
+        return {"desc": "cubes N=32768 edge 1 phi=0.45 d=0.08 a=0.1 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 1}
+    if name == "trunc_oct":
+        sp, N, L, pos, ori = inputs.workload_truncated_octahedra(32768, 0.45)
+        return {"desc": "truncated octahedra N=32768 edge 1 phi=0.45 d=0.08 a=0.1 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 1}
+    if name == "large":
+        sp, N, L, pos, ori = inputs.workload_pentagons(4194304, 0.60)
+        return {"desc": "regular pentagons N=4194304 R=0.5 phi=0.60 d=0.1 a=0.2 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 1}
+    if name == "screening":
+        batch = inputs.screening_batch(512, seed=2026)
+        return {"desc": "512 replicas: even disks / odd pentagons, N ~ U[64,4096], "
+                        "phi ~ U[0.30,0.70] (PCG64 seed 2026)",
+                "items": batch, "replicas": None}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def make_system(wl, precision, path, batched):
+    from paper_1509_04692_amd.system import System
+    items = wl["items"]
+    if wl["replicas"] is None:  # heterogeneous batch
+        chosen = items if batched else items[:1]
+    else:
+        chosen = items * (wl["replicas"] if batched else 1)
+    return System([c[0] for c in chosen], [c[1] for c in chosen], [c[2] for c in chosen],
+                  [c[3] for c in chosen], [c[4] for c in chosen], precision=precision, path=path)
+
+
+def timed_run(system, steps, warmup, seed):
+    """Warm up, then time exactly `steps` sweeps with HIP events on the
+    library's stream, synchronised on both sides."""
+    import torch
+    system.sweep(warmup, seed)
+    torch.cuda.synchronize()
+    before = system.stats()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(system.stream):
+        start.record(system.stream)
+        system.sweep(steps, seed)
+        end.record(system.stream)
+    torch.cuda.synchronize()
+    after = system.stats()
+    ms = start.elapsed_time(end)
+    diff = {k: sum(a[k] - b[k] for a, b in zip(after, before)) for k in after[0] if k != "sweeps"}
+    return ms, diff
+
+
+def cpu_baseline(wl, warmup, steps, budget_s=12.0):
+    """The FP64 reference oracle on one host core, timed on replica 0 of the
+    workload from its initial state, plus an event-counting run over the same
+    sweeps the GPU timed (for the work-per-move figure)."""
+    import oracle
+    sp, N, L, pos, ori = wl["items"][0]
+    p, o = pos.copy(), ori.copy()
+    moves = 0
+    t_sweep = 0
+    t0 = time.perf_counter()
+    chunk = max(1, int(2e5 // N))
+    while time.perf_counter() - t0 < budget_s:
+        st = oracle.sweep(sp, L, p, o, seed=1, n_sweeps=chunk, t0=t_sweep)
+        moves += int(st[0])
+        t_sweep += chunk
+    dt = time.perf_counter() - t0
+    lib = oracle.load_counting()
+    p, o = pos.copy(), ori.copy()
+    oracle.sweep(sp, L, p, o, seed=1, n_sweeps=warmup, lib=lib)
+    oracle.reset_events(lib)
+    n_count = min(steps, max(1, int(2e6 // N)))
+    st = oracle.sweep(sp, L, p, o, seed=1, n_sweeps=n_count, t0=warmup, lib=lib)
+    ev = oracle.event_counts(lib)
+    nv = len(sp["verts"]) if "verts" in sp else 0
+    opm = ops_per_move(ev, int(st[0]), sp["dim"], nv)
+    cpu = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        cpu = next((l.split(":", 1)[1].strip() for l in out.splitlines() if "Model name" in l), cpu)
+    except OSError:
+        pass
+    return {
+        "value": moves / dt, "unit": "trial moves/s", "cores": 1, "kind": "oracle",
+        "sample": f"replica 0 ({N} particles), sweeps 0..{t_sweep} from the initial state, "
+                  f"{dt:.1f} s on one core of {cpu} (nproc {os.cpu_count()})",
+    }, opm, {k: v / max(int(st[0]), 1) for k, v in ev.items()}, n_count
+
+
+def _device_info():
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    keys = ("name", "gcnArchName", "multi_processor_count", "shared_memory_per_block",
+            "shared_memory_per_block_optin", "shared_memory_per_multiprocessor", "L2_cache_size")
+    return {k: getattr(p, k) for k in keys if hasattr(p, k)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed sweeps first")
+    ap.add_argument("--workload", default="pentagons",
+                    choices=["pentagons", "disks", "cubes", "trunc_oct", "large", "screening"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None,
+                    help="comma list of runs: mixed_batched,fp64_single,fp64_batched,mixed_single")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(replicas shard across GPUs without communication; see the design notes).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    wl = workload(args.workload)
+    batched_ok = wl["replicas"] is None or wl["replicas"] > 1
+    runs = ["mixed_batched", "fp64_single", "fp64_batched", "mixed_single"]
+    if not batched_ok:
+        runs = ["mixed_single", "fp64_single"]
+    if args.only:
+        runs = [r for r in args.only.split(",") if r]
+    results = {}
+    for name in runs:
+        precision, mode = name.split("_")
+        batched = mode == "batched"
+        path = "persistent" if batched else "grid"
+        system = make_system(wl, precision, path, batched)
+        ms, diff = timed_run(system, args.steps, args.warmup, args.seed)
+        n_launch = (math.ceil(args.steps / PERSISTENT_SWEEPS_PER_LAUNCH) if path == "persistent"
+                    else None)
+        results[name] = {
+            "value": diff["attempted"] / (ms * 1e-3),
+            "ms_per_step": ms / args.steps,
+            "replicas": system.n_replicas,
+            "path": path,
+            "acceptance": diff["accept"] / max(diff["attempted"], 1),
+            "recheck_fraction": (diff["pair_fp64"] / diff["pair_tests"]
+                                 if precision == "mixed" and diff["pair_tests"] else None),
+            "moves": diff["attempted"],
+            "launches": n_launch,
+            "ms_total": ms,
+        }
+        del system
+        torch.cuda.synchronize()
+        print(f"# {name}: {results[name]['value']:.4e} trial moves/s, "
+              f"{results[name]['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+
+    head = "mixed_batched" if "mixed_batched" in results else runs[0]
+    h = results[head]
+    cpu, opm, ev_per_move, n_count = (None, None, None, 0)
+    if not args.no_cpu_baseline:
+        cpu, opm, ev_per_move, n_count = cpu_baseline(wl, args.warmup, args.steps)
+    roofline = None
+    if opm is not None:
+        if h["launches"]:
+            launch_s = h["ms_total"] * 1e-3 / h["launches"]
+            ops_per_launch = opm * h["moves"] / h["launches"]
+        else:
+            launch_s = h["ms_total"] * 1e-3
+            ops_per_launch = opm * h["moves"]
+        achieved = ops_per_launch / launch_s / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                    "ops_per_move": opm, "kernel": "k_persistent" if h["launches"] else "k_update",
+                    "avg_launch_ms": launch_s * 1e3, "events_per_move": ev_per_move,
+                    "events_counted_sweeps": n_count}
+    line = {
+        "metric": "trial moves/sec on 1 MI355X (4096 pentagons), mixed-prec+batched vs plain FP64",
+        "value": h["value"],
+        "unit": "trial moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head.startswith("mixed") else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "run": head, "replicas": h["replicas"],
+                   "path": h["path"], "sweeps_per_step": 1, "seed": args.seed},
+        "speedup_vs_fp64_single": (h["value"] / results["fp64_single"]["value"]
+                                   if "fp64_single" in results else None),
+        "runs": results,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "host": platform.node(),
+        "device": _device_info(),
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -51,6 +51,9 @@ extern "C" {
 #define HPMC_ERR_SWEEP_OVERFLOW (-6)      /* sweep counter would reach 2^32 */
 #define HPMC_ERR_UNSUPPORTED (-7)         /* valid request this build cannot run */
 
+/* The persistent path launches one kernel per this many sweeps. */
+#define HPMC_PERSISTENT_SWEEPS_PER_LAUNCH 64
+
 /* Opaque host-side handle of one set of replicas. */
 typedef struct hpmc_state hpmc_state;
 

@@ -13,15 +13,19 @@ Positions are (dim, N) float64 arrays (structure of arrays, canonical order),
 orientations (2, N) for polygons (c, s) and (4, N) for polyhedra (w, x, y, z).
 """
 from .oracle import (  # noqa: F401
+    EVENT_NAMES,
     N_STATS,
     STAT_NAMES,
     build,
     count_overlaps,
+    event_counts,
     grid,
     index,
+    load_counting,
     overlap_full,
     pair_overlaps,
     philox4x32_10,
+    reset_events,
     serial_metropolis,
     shape_info,
     sincos,

@@ -33,6 +33,24 @@
 #include <stdlib.h>
 #include <string.h>
 
+/*
+ * ORACLE_COUNT_OPS builds a variant that counts algorithmic events of the
+ * sweep (moves by kind, candidate pairs, separating-axis set-ups and axes
+ * evaluated, XenoCollide set-ups, support evaluations and iterations), all
+ * with early exit, for the benchmark's work-per-move figure.  The normal
+ * build compiles EVENT() to nothing.
+ */
+enum { EV_TRANSLATE, EV_ROTATE2, EV_ROTATE3, EV_CAND2, EV_CAND3, EV_SAT_SETUP, EV_SAT_AXIS,
+       EV_SAT_FRAME_B, EV_MPR_SETUP, EV_MPR_SUPPORT, EV_MPR_ITER, EV_COUNT };
+#ifdef ORACLE_COUNT_OPS
+static int64_t or_events[EV_COUNT];
+int64_t *or_event_counts(void) { return or_events; }
+int32_t or_n_events(void) { return EV_COUNT; }
+#define EVENT(k) (or_events[(k)] += 1)
+#else
+#define EVENT(k) ((void)0)
+#endif
+
 /* ------------------------------------------------------------------------ */
 /* Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).       */
 /* Counter-based, so every trial move has its own independent stream,       */
@@ -241,6 +259,7 @@ static int overlap_polygon(const shape_t *sh, const double r[2], const double qa
 {
     double cA = qa[0], sA = qa[1], cB = qb[0], sB = qb[1];
     /* relative orientation z = conj(zA) zB and B's centre in A's frame */
+    EVENT(EV_SAT_SETUP);
     double zc = cA * cB + sA * sB;
     double zs = cA * sB - sA * cB;
     double tx = cA * r[0] + sA * r[1];
@@ -260,6 +279,8 @@ static int overlap_polygon(const shape_t *sh, const double r[2], const double qa
         double lo = 0.0, hi = 0.0;
         for (int j = 0; j < sh->nv; ++j) {
             double p = sh->nrm[k][0] * bx[j] + sh->nrm[k][1] * by[j];
+            if (j == 0)
+                EVENT(EV_SAT_AXIS);
             if (j == 0 || p < lo) lo = p;
             if (j == 0 || p > hi) hi = p;
         }
@@ -271,6 +292,7 @@ static int overlap_polygon(const shape_t *sh, const double r[2], const double qa
 #endif
     /* axes of B, in B's frame: A's vertices mapped into B's frame */
     double ax[OR_MAXV], ay[OR_MAXV];
+    EVENT(EV_SAT_FRAME_B);
     for (int j = 0; j < sh->nv; ++j) {
         double ux = sh->v[j][0] - tx;
         double uy = sh->v[j][1] - ty;
@@ -281,6 +303,8 @@ static int overlap_polygon(const shape_t *sh, const double r[2], const double qa
         double lo = 0.0, hi = 0.0;
         for (int j = 0; j < sh->nv; ++j) {
             double p = sh->nrm[k][0] * ax[j] + sh->nrm[k][1] * ay[j];
+            if (j == 0)
+                EVENT(EV_SAT_AXIS);
             if (j == 0 || p < lo) lo = p;
             if (j == 0 || p > hi) hi = p;
         }
@@ -347,6 +371,7 @@ static void support(const mink_t *mk, const double n[3], double out[3])
 {
     const shape_t *sh = mk->sh;
     double nb[3];
+    EVENT(EV_MPR_SUPPORT);
     for (int a = 0; a < 3; ++a)
 #ifdef ORACLE_PLANT_MPR_TRANSPOSE
         nb[a] = (mk->m[a][0] * n[0] + mk->m[a][1] * n[1]) + mk->m[a][2] * n[2];
@@ -391,6 +416,7 @@ static int overlap_polyhedron(const shape_t *sh, const double r[3], const double
 {
     mink_t mk;
     mk.sh = sh;
+    EVENT(EV_MPR_SETUP);
     double qac[4] = { qa[0], -qa[1], -qa[2], -qa[3] };
     double q[4], ma[3][3];
     quat_mul(qac, qb, q);
@@ -432,6 +458,7 @@ static int overlap_polyhedron(const shape_t *sh, const double r[3], const double
     for (;;) {
         if (++iter > MPR_MAX_ITER)
             return 1; /* cap reached: conservative */
+        EVENT(EV_MPR_ITER);
         support(&mk, n, v3);
         if (dot3(v3, n) <= 0.0)
             return 0;
@@ -460,6 +487,7 @@ static int overlap_polyhedron(const shape_t *sh, const double r[3], const double
     for (;;) {
         if (++iter > MPR_MAX_ITER)
             return 1;
+        EVENT(EV_MPR_ITER);
         sub3(v2, v1, e1);
         sub3(v3, v1, e2);
         cross3(e1, e2, n);
@@ -727,17 +755,20 @@ static int propose(const or_species *sp, const shape_t *sh, const grid_t *g, con
     for (int k = 0; k < 4; ++k)
         qn[k] = q[k];
     if (!rotate) {
+        EVENT(EV_TRANSLATE);
         for (int a = 0; a < sh->dim; ++a) {
             double u = 2.0 * or_u01(m[1 + a]) - 1.0;
             xn[a] = wrap(x[a] + sp->d * u, g->L);
         }
     } else if (sh->kind == OR_POLYGON) {
+        EVENT(EV_ROTATE2);
         double delta = sp->a * (2.0 * or_u01(m[1]) - 1.0);
         double cd, sd;
         or_sincos(delta, &cd, &sd);
         qn[0] = q[0] * cd - q[1] * sd;
         qn[1] = q[1] * cd + q[0] * sd;
     } else {
+        EVENT(EV_ROTATE3);
         double dq[4] = { 1.0, 0.0, 0.0, 0.0 };
         for (int a = 0; a < 3; ++a)
             dq[1 + a] = sp->a * (2.0 * or_u01(m[1 + a]) - 1.0);
@@ -770,6 +801,7 @@ static int trial_overlaps(const shape_t *sh, const grid_t *g, const cells_t *cl,
                     int k = cl->members[p];
                     if (k == i)
                         continue;
+                    EVENT(g->dim == 2 ? EV_CAND2 : EV_CAND3);
                     double r[3] = { 0.0, 0.0, 0.0 }, qk[4];
                     for (int a = 0; a < g->dim; ++a)
                         r[a] = min_image(g, pos[a * N + k] - xn[a]);

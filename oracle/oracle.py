@@ -21,6 +21,12 @@ N_STATS = len(STAT_NAMES)
 _SHAPES = {"disk": 0, "polygon": 1, "polyhedron": 2}
 
 _lib = None
+_lib_ops = None
+_LIB_OPS_PATH = os.path.join(_HERE, "liboracle_ops.so")
+
+# Event counters of the ORACLE_COUNT_OPS build, in the order of hpmc_oracle.c.
+EVENT_NAMES = ("translate", "rotate2", "rotate3", "cand2", "cand3", "sat_setup", "sat_axis",
+               "sat_frame_b", "mpr_setup", "mpr_support", "mpr_iter")
 
 
 def build(extra_flags=(), out_path=None):
@@ -96,6 +102,33 @@ def load(path=None):
         _lib = ctypes.CDLL(_LIB_PATH)
         _declare(_lib)
     return _lib
+
+
+def load_counting():
+    """The event-counting build (ORACLE_COUNT_OPS), built on first use."""
+    global _lib_ops
+    if _lib_ops is None:
+        if not os.path.exists(_LIB_OPS_PATH):
+            build(extra_flags=["-DORACLE_COUNT_OPS"], out_path=_LIB_OPS_PATH)
+        lib = ctypes.CDLL(_LIB_OPS_PATH)
+        _declare(lib)
+        lib.or_event_counts.restype = ctypes.POINTER(ctypes.c_int64)
+        lib.or_n_events.restype = ctypes.c_int32
+        assert lib.or_n_events() == len(EVENT_NAMES)
+        _lib_ops = lib
+    return _lib_ops
+
+
+def event_counts(lib):
+    """Copy of the event counters of a counting build, as a dict."""
+    ptr = lib.or_event_counts()
+    return {name: int(ptr[k]) for k, name in enumerate(EVENT_NAMES)}
+
+
+def reset_events(lib):
+    ptr = lib.or_event_counts()
+    for k in range(len(EVENT_NAMES)):
+        ptr[k] = 0
 
 
 def _species(sp):

@@ -19,7 +19,6 @@ struct hpmc_state {
     int n_replicas = 0;
     int precision = HPMC_FP64;
     int path = HPMC_PATH_GRID;
-    int block = 256;
     hipStream_t stream = nullptr;
     double* pos = nullptr;
     double* orient = nullptr;
@@ -27,7 +26,7 @@ struct hpmc_state {
     std::vector<ReplicaHost> rep;
     std::vector<SysDev> sys;
     std::vector<SpeciesDev> spc;
-    size_t lds_bytes = 0;
+    std::vector<BatchGroup> groups;
     uint64_t t = 0;
     uint64_t sweeps_done = 0;
     int last_hip = 0;
@@ -37,8 +36,16 @@ namespace {
 
 constexpr uint64_t kSweepLimit = 1ull << 32;
 constexpr size_t kAlign = 256;
-constexpr size_t kPersistentLdsMax = 64 * 1024;
-constexpr uint32_t kPersistentChunk = 64;  // sweeps per persistent launch
+// LDS per work-group available to the persistent path (gfx950: 160 KiB;
+// the device attribute is queried at init).
+size_t device_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 64 * 1024;
+    return (size_t)v;
+}
+constexpr uint32_t kPersistentChunk = HPMC_PERSISTENT_SWEEPS_PER_LAUNCH;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -163,11 +170,22 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
 }
 
 struct Layout {
-    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, partial, total;
+    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, partial, list,
+        total;
 };
 
+// Lanes per active cell on the grid path: enough waves to cover the chip
+// (256 CUs x 8 waves) when a pass has few active cells.
+int choose_lanes_per_cell(int64_t n_act) {
+    const int64_t target_waves = 256 * 8;
+    int g = 1;
+    while (g < 8 && n_act * g / 64 < target_waves) g *= 2;
+    return g;
+}
+
 int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<SysDev>& sys,
-         std::vector<SpeciesDev>& spc, Layout& lay, int& path, size_t& lds_bytes) {
+         std::vector<SpeciesDev>& spc, Layout& lay, int& path, std::vector<BatchGroup>& groups,
+         std::vector<int32_t>& list, size_t lds_limit) {
     if (a == nullptr || a->n_replicas < 1 || a->species == nullptr || a->N == nullptr ||
         a->L == nullptr)
         return HPMC_ERR_INVALID_ARG;
@@ -180,7 +198,6 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     int64_t pos_off = 0, ori_off = 0;
     int64_t nc_max = 1, n_max = 1;
     bool fits_lds = true;
-    lds_bytes = 0;
     for (int r = 0; r < R; ++r) {
         int rc = build_species(a->species[r], spc[r]);
         if (rc) return rc;
@@ -197,9 +214,11 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         ori_off += (int64_t)ncomp * sys[r].N;
         nc_max = std::max<int64_t>(nc_max, sys[r].ncells);
         n_max = std::max<int64_t>(n_max, sys[r].N);
-        const size_t lb = persistent_lds_bytes(sys[r].ncells, sys[r].N);
-        lds_bytes = std::max(lds_bytes, lb);
-        if (sys[r].N > 65535 || lb > kPersistentLdsMax) fits_lds = false;
+        const size_t lb = persistent_lds_bytes(sys[r].dim, sys[r].ncells, sys[r].N, false);
+        if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
+        const int half = sys[r].n / 2;
+        const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
+        rep[r].lanes_per_cell = choose_lanes_per_cell(n_act);
     }
     if (a->path == HPMC_PATH_PERSISTENT && !fits_lds) return HPMC_ERR_UNSUPPORTED;
     if (a->path == HPMC_PATH_AUTO)
@@ -209,6 +228,27 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     for (int r = 0; r < R; ++r) {
         sys[r].path = path;
         rep[r].path = path;
+    }
+    // persistent path: one launch per shape kind; positions held in LDS when
+    // every replica of the kind fits
+    groups.clear();
+    list.clear();
+    if (path == HPMC_PATH_PERSISTENT) {
+        for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
+            BatchGroup g{kind, (int32_t)list.size(), 0, 1, 0};
+            size_t res = 0, nonres = 0;
+            for (int r = 0; r < R; ++r) {
+                if (spc[r].kind != kind) continue;
+                list.push_back(r);
+                g.count++;
+                res = std::max(res, persistent_lds_bytes(sys[r].dim, sys[r].ncells, sys[r].N, true));
+                nonres = std::max(nonres, persistent_lds_bytes(sys[r].dim, sys[r].ncells, sys[r].N, false));
+            }
+            if (g.count == 0) continue;
+            g.resident = res <= lds_limit ? 1 : 0;
+            g.lds_bytes = g.resident ? res : nonres;
+            groups.push_back(g);
+        }
     }
     const int64_t ntiles = (nc_max + kScanTile - 1) / kScanTile;
     size_t off = 0;
@@ -227,6 +267,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.slot_of = take(4 * (size_t)n_max);
     lay.members = take(4 * (size_t)n_max);
     lay.partial = take(4 * (size_t)ntiles);
+    lay.list = take(4 * (size_t)R);
     lay.total = off;
     return HPMC_OK;
 }
@@ -257,8 +298,9 @@ int hpmc_workspace_bytes(const hpmc_init_args* args, size_t* out_bytes) {
     std::vector<SpeciesDev> spc;
     Layout lay{};
     int path = 0;
-    size_t lds = 0;
-    const int rc = plan(args, rep, sys, spc, lay, path, lds);
+    std::vector<BatchGroup> groups;
+    std::vector<int32_t> list;
+    const int rc = plan(args, rep, sys, spc, lay, path, groups, list, device_lds_limit());
     if (rc) return rc;
     *out_bytes = lay.total;
     return HPMC_OK;
@@ -270,7 +312,9 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     hpmc_state* st = new (std::nothrow) hpmc_state();
     if (st == nullptr) return HPMC_ERR_INVALID_ARG;
     Layout lay{};
-    int rc = plan(args, st->rep, st->sys, st->spc, lay, st->path, st->lds_bytes);
+    std::vector<int32_t> list;
+    int rc = plan(args, st->rep, st->sys, st->spc, lay, st->path, st->groups, list,
+                  device_lds_limit());
     if (rc == HPMC_OK && (args->pos == nullptr || args->workspace == nullptr)) rc = HPMC_ERR_INVALID_ARG;
     if (rc == HPMC_OK && args->orient == nullptr) {
         for (const auto& s : st->spc)
@@ -298,12 +342,16 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->ws.slot_of = (uint32_t*)(base + lay.slot_of);
     st->ws.members = (uint32_t*)(base + lay.members);
     st->ws.partial = (uint32_t*)(base + lay.partial);
+    st->ws.batch_list = (int32_t*)(base + lay.list);
 
     rc = check_hip(st, hipMemcpyAsync(st->ws.species, st->spc.data(),
                                       sizeof(SpeciesDev) * st->n_replicas, hipMemcpyHostToDevice,
                                       st->stream));
     if (!rc)
         rc = check_hip(st, hipMemcpyAsync(st->ws.sys, st->sys.data(), sizeof(SysDev) * st->n_replicas,
+                                          hipMemcpyHostToDevice, st->stream));
+    if (!rc && !list.empty())
+        rc = check_hip(st, hipMemcpyAsync(st->ws.batch_list, list.data(), sizeof(int32_t) * list.size(),
                                           hipMemcpyHostToDevice, st->stream));
     if (!rc)
         rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kNumStats * st->n_replicas, st->stream));
@@ -347,10 +395,12 @@ int hpmc_sweep(hpmc_state* st, uint64_t n_sweeps, uint64_t seed) {
         uint64_t done = 0;
         while (done < n_sweeps && !rc) {
             const uint32_t chunk = (uint32_t)std::min<uint64_t>(kPersistentChunk, n_sweeps - done);
-            rc = check_hip(st, persistent_sweeps(st->ws, st->n_replicas, st->lds_bytes, st->pos,
-                                                 st->orient, st->precision,
-                                                 (uint32_t)(st->t + done), chunk, k0, k1, st->block,
-                                                 st->stream));
+            for (const BatchGroup& g : st->groups) {
+                if (rc) break;
+                rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision,
+                                                     (uint32_t)(st->t + done), chunk, k0, k1,
+                                                     st->stream));
+            }
             done += chunk;
         }
     } else {

@@ -1,0 +1,379 @@
+// One colour pass over a tile of active cells, executed by one wave64.
+//
+// The paper's block queue (Sec. 2.5.3) restricted to a wave, so that no
+// work-group barrier is needed inside a pass:
+//   1. the leader lane of each group of G lanes proposes the trial move of
+//      its cell (uniform occupant, Philox stream, translation or rotation,
+//      reject when it leaves the cell) and broadcasts it to its group;
+//   2. the group's lanes scan the 3^dim neighbour cells in a strided fashion
+//      and only run the circumsphere test; hits are compacted with a wave
+//      ballot and prefix count into an LDS ring of (owner lane, neighbour);
+//   3. whenever 64 entries are queued, every lane takes one entry and runs a
+//      full overlap test; an overlap sets the owner cell's flag, and flagged
+//      cells queue no further work (early exit);
+//   4. leaders of unflagged live cells write the move back.
+// The accept decision is the OR over all neighbours, so it does not depend on
+// the order in which the tests run.
+#pragma once
+
+#include "device_common.hpp"
+#include "overlap32.hpp"
+#include "overlap64.hpp"
+#include "types.hpp"
+
+namespace hpmc {
+
+template <int KIND>
+struct Traits {
+    static constexpr int dim = KIND == kPolyhedron ? 3 : 2;
+    static constexpr int ncomp = KIND == kDisk ? 0 : (KIND == kPolygon ? 2 : 4);
+    static constexpr int nbrs = KIND == kPolyhedron ? 27 : 9;
+};
+
+// Per-lane counters, named fields (an array indexed on two branches gets its
+// increments merged through a selected address and lands in scratch).
+struct Counters {
+    uint32_t attempted, attempted_rot, cell_reject, overlap_reject, accept, pair_tests, pair_fp64;
+};
+
+__device__ __forceinline__ void flush_one(uint32_t v, unsigned long long* p) {
+    const uint32_t s = wave_sum(v);
+    if (__lane_id() == 0 && s != 0) atomicAdd(p, (unsigned long long)s);
+}
+
+// One 64-bit atomic per wave and counter.  Every lane of the wave must call.
+__device__ __forceinline__ void flush(const Counters& c, unsigned long long* stats) {
+    flush_one(c.attempted, stats + kAttempted);
+    flush_one(c.attempted_rot, stats + kAttemptedRot);
+    flush_one(c.cell_reject, stats + kCellReject);
+    flush_one(c.overlap_reject, stats + kOverlapReject);
+    flush_one(c.accept, stats + kAccept);
+    flush_one(c.pair_tests, stats + kPairTests);
+    flush_one(c.pair_fp64, stats + kPairFp64);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// Views of particle positions (tag order, structure of arrays) and of the
+// cell list.
+// ---------------------------------------------------------------------------
+struct PosView {
+    double* p;  // global or LDS
+    int N;
+    __device__ __forceinline__ double get(int a, uint32_t k) const { return p[a * N + k]; }
+    __device__ __forceinline__ void set(int a, uint32_t k, double v) const { p[a * N + k] = v; }
+};
+
+struct GlobalCells {
+    const uint32_t* __restrict__ start;
+    const uint32_t* __restrict__ members;
+    __device__ __forceinline__ uint32_t begin(uint32_t c) const { return start[c]; }
+    __device__ __forceinline__ uint32_t end(uint32_t c) const { return start[c + 1]; }
+    __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
+};
+
+// LDS cell list: inclusive ends[ncells] and members (16-bit tags).
+struct LdsCells {
+    const uint16_t* ends;
+    const uint16_t* members;
+    __device__ __forceinline__ uint32_t begin(uint32_t c) const { return c ? ends[c - 1] : 0u; }
+    __device__ __forceinline__ uint32_t end(uint32_t c) const { return ends[c]; }
+    __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
+};
+
+template <int KIND>
+__device__ __forceinline__ void load_orient(const double* __restrict__ ori, int N, uint32_t i,
+                                            double (&q)[4]) {
+    q[0] = 1.0;
+    q[1] = q[2] = q[3] = 0.0;
+    if constexpr (KIND == kPolygon) {
+        q[0] = ori[i];
+        q[1] = ori[N + i];
+    } else if constexpr (KIND == kPolyhedron) {
+        q[0] = ori[i];
+        q[1] = ori[N + i];
+        q[2] = ori[2 * N + i];
+        q[3] = ori[3 * N + i];
+    }
+}
+
+// Full overlap test of a pair that passed the circumsphere test.
+template <int KIND, int PREC>
+__device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)[3],
+                                          const double (&qi)[4], const double (&qk)[4],
+                                          Counters& ct) {
+    if constexpr (KIND == kDisk) {
+        return true;
+    } else if constexpr (KIND == kPolygon) {
+        ct.pair_tests++;
+        if constexpr (PREC == 1) {
+            const int d = polygon_overlap32(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
+            if (d != kUncertain) return d == kOverlap;
+        }
+        ct.pair_fp64++;
+        return polygon_overlap64(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
+    } else {
+        ct.pair_tests++;
+        ct.pair_fp64++;
+        return polyhedron_overlap64(P, V3{r[0], r[1], r[2]}, Quat{qi[0], qi[1], qi[2], qi[3]},
+                                    Quat{qk[0], qk[1], qk[2], qk[3]});
+    }
+}
+
+__device__ __forceinline__ void grid_shift(const SysDev& S, uint32_t t, uint32_t k0, uint32_t k1,
+                                           int shifted, double (&sh)[3]) {
+    sh[0] = sh[1] = sh[2] = 0.0;
+    if (shifted) {
+        const uint4 w = draw(t, kShift, 0u, 0u, (uint32_t)S.replica, k0, k1);
+        sh[0] = S.w * u01(w.x);
+        sh[1] = S.w * u01(w.y);
+        sh[2] = S.w * u01(w.z);
+    }
+}
+
+template <int D, class POS>
+__device__ __forceinline__ uint32_t particle_cell(const SysDev& S, const POS& pos, uint32_t i,
+                                                  const double (&sh)[3]) {
+    const int n = S.n;
+    const int cx = cell_coord(pos.get(0, i), sh[0], S.L, S.inv_w, n);
+    const int cy = cell_coord(pos.get(1, i), sh[1], S.L, S.inv_w, n);
+    int cz = 0;
+    if constexpr (D == 3) cz = cell_coord(pos.get(2, i), sh[2], S.L, S.inv_w, n);
+    return (uint32_t)(cx + n * (cy + n * cz));
+}
+
+__device__ __forceinline__ void active_cell(const SysDev& S, int D, uint32_t colour, int a,
+                                            int (&cc)[3], uint32_t& c) {
+    const int half = S.n / 2;
+    cc[0] = 2 * (a % half) + (int)(colour & 1u);
+    cc[1] = 2 * ((a / half) % half) + (int)((colour >> 1) & 1u);
+    cc[2] = D == 3 ? 2 * (a / (half * half)) + (int)((colour >> 2) & 1u) : 0;
+    c = (uint32_t)(cc[0] + S.n * (cc[1] + S.n * cc[2]));
+}
+
+__device__ __forceinline__ int wrap_cell(int x, int n) {
+    x += x < 0 ? n : 0;
+    return x - (x >= n ? n : 0);
+}
+
+// Linear index of neighbour j (0 .. 3^dim - 1) of cell cc.
+template <int D>
+__device__ __forceinline__ uint32_t neighbour_cell(const int (&cc)[3], int j, int n) {
+    const int x = wrap_cell(cc[0] + (j % 3) - 1, n);
+    const int y = wrap_cell(cc[1] + ((j / 3) % 3) - 1, n);
+    const int z = D == 3 ? wrap_cell(cc[2] + (j / 9) - 1, n) : 0;
+    return (uint32_t)(x + n * (y + n * z));
+}
+
+// Per-wave LDS scratch: a 128-entry ring of queued pair tests and one flag per
+// group (cell) of the tile.
+struct WaveScratch {
+    uint32_t* q;     // 128 entries: owner lane << 26 | neighbour tag
+    uint32_t* flag;  // 64 entries
+};
+constexpr int kQueueWords = 128;
+constexpr int kFlagWords = 64;
+constexpr uint32_t kTagMask = (1u << 26) - 1u;
+
+// ---------------------------------------------------------------------------
+// Drain n (<= 64) queued pair tests: lane L takes entry L, fetches the owner
+// cell's trial state from the owner lane and runs the full test.  All lanes
+// must call (contains cross-lane shuffles).
+// ---------------------------------------------------------------------------
+template <int KIND, int PREC, int G, class POS>
+__device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, const POS& pos,
+                                      const double* __restrict__ ori, const double (&xn)[3],
+                                      const double (&qn)[4], uint32_t n, WaveScratch ws,
+                                      Counters& ct) {
+    constexpr int D = Traits<KIND>::dim;
+    const uint32_t lane = __lane_id();
+    wave_sync();
+    const uint32_t e = lane < n ? ws.q[lane] : 0u;
+    const int owner = lane < n ? (int)(e >> 26) : (int)lane;
+    double tx[3], tq[4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) tx[a] = a < D ? __shfl(xn[a], owner, 64) : 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tq[c] = c < Traits<KIND>::ncomp ? __shfl(qn[c], owner, 64) : qn[c];
+    if (lane < n && ws.flag[owner / G] == 0u) {
+        const uint32_t k = e & kTagMask;
+        double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) r[a] = min_image(pos.get(a, k) - tx[a], S.L, S.inv_L);
+        double qk[4];
+        load_orient<KIND>(ori, S.N, k, qk);
+        if (full_test<KIND, PREC>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
+    }
+    wave_sync();
+}
+
+template <int KIND, int PREC, int G, class POS, class CELLS>
+__device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, const POS& pos,
+                                          double* __restrict__ ori, const CELLS& cl,
+                                          uint32_t colour, uint32_t select, uint32_t t,
+                                          uint32_t k0, uint32_t k1, const double (&sh)[3], int a0,
+                                          int n_act, WaveScratch ws, Counters& ct) {
+    constexpr int D = Traits<KIND>::dim;
+    constexpr int NB = Traits<KIND>::nbrs;
+    const int lane = (int)__lane_id();
+    const int grp = lane / G, sub = lane % G;
+    const int leader = grp * G;
+    const int a = a0 + grp;
+    const int n = S.n, N = S.N;
+
+    // ---- 1. propose (group leaders)
+    int cc[3] = {0, 0, 0};
+    uint32_t c = 0, i = 0;
+    bool live = false;
+    double xn[3] = {0.0, 0.0, 0.0};
+    double qn[4] = {1.0, 0.0, 0.0, 0.0};
+    bool c_rot = false, c_moved = false;  // rotation attempted / translation attempted
+    if (sub == 0 && a < n_act) {
+        active_cell(S, D, colour, a, cc, c);
+        const uint32_t beg = cl.begin(c), fin = cl.end(c);
+        if (beg != fin) {
+            ct.attempted++;
+            const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
+            i = cl.member(beg + index_below(wsel.x, fin - beg));
+            const uint4 m = draw(t, kMove, select, i, S.replica, k0, k1);
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) xn[ax] = pos.get(ax, i);
+            load_orient<KIND>(ori, N, i, qn);
+            const bool rotate = KIND != kDisk && P.p_rot > 0.0 && u01(m.x) < P.p_rot;
+            live = true;
+            c_rot = rotate;
+            c_moved = !rotate;
+            if (!rotate) {
+                const uint32_t mw[3] = {m.y, m.z, m.w};
+#pragma unroll
+                for (int ax = 0; ax < D; ++ax) {
+                    xn[ax] = wrap_periodic(xn[ax] + P.d * (2.0 * u01(mw[ax]) - 1.0), S.L);
+                    live &= cell_coord(xn[ax], sh[ax], S.L, S.inv_w, n) == cc[ax];
+                }
+            } else {
+                if constexpr (KIND == kPolygon) {
+                    const double delta = P.a * (2.0 * u01(m.y) - 1.0);
+                    double cd, sd;
+                    small_angle_sincos(delta, cd, sd);
+                    const double c0 = qn[0], s0 = qn[1];
+                    qn[0] = c0 * cd - s0 * sd;
+                    qn[1] = s0 * cd + c0 * sd;
+                } else if constexpr (KIND == kPolyhedron) {
+                    const Quat dq{1.0, P.a * (2.0 * u01(m.y) - 1.0), P.a * (2.0 * u01(m.z) - 1.0),
+                                  P.a * (2.0 * u01(m.w) - 1.0)};
+                    const Quat p = qmul(Quat{qn[0], qn[1], qn[2], qn[3]}, dq);
+                    const double nrm = sqrt(((p.w * p.w + p.x * p.x) + p.y * p.y) + p.z * p.z);
+                    qn[0] = p.w / nrm;
+                    qn[1] = p.x / nrm;
+                    qn[2] = p.y / nrm;
+                    qn[3] = p.z / nrm;
+                }
+            }
+        }
+    }
+    ct.attempted_rot += (sub == 0 && a < n_act && c_rot) ? 1u : 0u;
+    ct.cell_reject += (sub == 0 && a < n_act && c_moved && !live) ? 1u : 0u;
+    if (lane < 64 / G) ws.flag[lane] = 0u;
+    if constexpr (G > 1) {
+        live = __shfl((int)live, leader, 64) != 0;
+        i = (uint32_t)__shfl((int)i, leader, 64);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            cc[ax] = __shfl(cc[ax], leader, 64);
+            if (ax < D) xn[ax] = __shfl(xn[ax], leader, 64);
+        }
+    }
+    wave_sync();
+
+    // ---- 2 + 3. strided circumsphere scan, queued full tests
+    int j = sub;
+    uint32_t p = 0, e = 0;
+    if (live) {
+        for (; j < NB; j += G) {
+            const uint32_t cn = neighbour_cell<D>(cc, j, n);
+            p = cl.begin(cn);
+            e = cl.end(cn);
+            if (p != e) break;
+        }
+    }
+    bool work = live && j < NB;
+    uint32_t queued = 0;  // wave-uniform
+    for (;;) {
+        bool hit = false;
+        uint32_t k = 0;
+        if (work) {
+            if (ws.flag[grp] != 0u) {
+                work = false;  // early exit: an overlap was already found
+            } else {
+                k = cl.member(p);
+                if (k != i) {
+                    double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) r[ax] = min_image(pos.get(ax, k) - xn[ax], S.L, S.inv_L);
+                    double r2 = r[0] * r[0] + r[1] * r[1];
+                    if constexpr (D == 3) r2 = r2 + r[2] * r[2];
+                    hit = r2 < P.circ2;
+                }
+                if (++p == e) {
+                    for (j += G; j < NB; j += G) {
+                        const uint32_t cn = neighbour_cell<D>(cc, j, n);
+                        p = cl.begin(cn);
+                        e = cl.end(cn);
+                        if (p != e) break;
+                    }
+                    work = j < NB;
+                }
+            }
+        }
+        if constexpr (KIND == kDisk) {
+            if (hit) ws.flag[grp] = 1u;  // the circumsphere test is the disk test
+            wave_sync();
+        } else {
+            const uint64_t hm = __ballot(hit);
+            if (hit) {
+                const uint32_t below = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
+                ws.q[queued + below] = ((uint32_t)leader << 26) | k;
+            }
+            queued += (uint32_t)__popcll(hm);
+            if (queued >= 64u) {
+                drain<KIND, PREC, G>(S, P, pos, ori, xn, qn, 64u, ws, ct);
+                queued -= 64u;
+                const uint32_t moved = (uint32_t)lane < queued ? ws.q[64 + lane] : 0u;
+                wave_sync();
+                if ((uint32_t)lane < queued) ws.q[lane] = moved;
+                wave_sync();
+            }
+        }
+        if (__ballot(work) == 0ull) break;
+    }
+    if constexpr (KIND != kDisk) {
+        if (queued) drain<KIND, PREC, G>(S, P, pos, ori, xn, qn, queued, ws, ct);
+    }
+
+    // ---- 4. write back (counters updated arithmetically, not per branch)
+    const bool rejected = live && ws.flag[grp] != 0u;
+    ct.overlap_reject += (sub == 0 && rejected) ? 1u : 0u;
+    ct.accept += (sub == 0 && live && !rejected) ? 1u : 0u;
+    if (sub == 0 && live) {
+        if (!rejected) {
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) pos.set(ax, i, xn[ax]);
+            if constexpr (KIND == kPolygon) {
+                ori[i] = qn[0];
+                ori[N + i] = qn[1];
+            } else if constexpr (KIND == kPolyhedron) {
+                ori[i] = qn[0];
+                ori[N + i] = qn[1];
+                ori[2 * N + i] = qn[2];
+                ori[3 * N + i] = qn[3];
+            }
+        }
+    }
+    wave_sync();
+}
+
+}  // namespace hpmc

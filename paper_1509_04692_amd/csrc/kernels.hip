@@ -10,237 +10,10 @@
 // passes are separated by work-group barriers, so no grid-wide
 // synchronisation is needed.
 #include "device_common.hpp"
+#include "engine.hpp"
 #include "launch.hpp"
-#include "overlap32.hpp"
-#include "overlap64.hpp"
 
 namespace hpmc {
-
-template <int KIND>
-struct Traits {
-    static constexpr int dim = KIND == kPolyhedron ? 3 : 2;
-    static constexpr int ncomp = KIND == kDisk ? 0 : (KIND == kPolygon ? 2 : 4);
-};
-
-struct Counters {
-    uint32_t v[kNumStats];
-};
-
-// One 64-bit atomic per wave and counter.  Every lane of the wave must call.
-__device__ __forceinline__ void flush(const Counters& c, unsigned long long* stats) {
-#pragma unroll
-    for (int k = 0; k < kNumStats; ++k) {
-        const uint32_t s = wave_sum(c.v[k]);
-        if (__lane_id() == 0 && s != 0) atomicAdd(stats + k, (unsigned long long)s);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Cell-list views: global (start[ncells + 1], members u32) and LDS
-// (inclusive ends[ncells], members u16).
-// ---------------------------------------------------------------------------
-struct GlobalCells {
-    const uint32_t* __restrict__ start;
-    const uint32_t* __restrict__ members;
-    __device__ __forceinline__ uint32_t begin(uint32_t c) const { return start[c]; }
-    __device__ __forceinline__ uint32_t end(uint32_t c) const { return start[c + 1]; }
-    __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
-};
-
-struct LdsCells {
-    const uint32_t* ends;
-    const uint16_t* members;
-    __device__ __forceinline__ uint32_t begin(uint32_t c) const { return c ? ends[c - 1] : 0u; }
-    __device__ __forceinline__ uint32_t end(uint32_t c) const { return ends[c]; }
-    __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
-};
-
-template <int KIND>
-__device__ __forceinline__ void load_orient(const double* __restrict__ ori, int N, uint32_t i,
-                                            double (&q)[4]) {
-    q[0] = 1.0;
-    q[1] = q[2] = q[3] = 0.0;
-    if constexpr (KIND == kPolygon) {
-        q[0] = ori[i];
-        q[1] = ori[N + i];
-    } else if constexpr (KIND == kPolyhedron) {
-        q[0] = ori[i];
-        q[1] = ori[N + i];
-        q[2] = ori[2 * N + i];
-        q[3] = ori[3 * N + i];
-    }
-}
-
-// Full overlap test of a pair that passed the circumsphere test; for disks
-// that test is the whole predicate.
-template <int KIND, int PREC>
-__device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)[3],
-                                          const double (&qi)[4], const double (&qk)[4],
-                                          Counters& ct) {
-    if constexpr (KIND == kDisk) {
-        return true;
-    } else if constexpr (KIND == kPolygon) {
-        ct.v[kPairTests]++;
-        if constexpr (PREC == 1) {
-            const int d = polygon_overlap32(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
-            if (d != kUncertain) return d == kOverlap;
-        }
-        ct.v[kPairFp64]++;
-        return polygon_overlap64(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
-    } else {
-        ct.v[kPairTests]++;
-        ct.v[kPairFp64]++;
-        return polyhedron_overlap64(P, V3{r[0], r[1], r[2]}, Quat{qi[0], qi[1], qi[2], qi[3]},
-                                    Quat{qk[0], qk[1], qk[2], qk[3]});
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One trial move in cell c (coordinates cc) of the grid shifted by sh:
-// uniform occupant, Philox move stream keyed on its tag, translation or
-// rotation, reject if it leaves the cell, reject on the first overlap with
-// an occupant of the 3^dim cells around c, otherwise write back (Sec. 2.1,
-// Sec. 2.5.2).
-// ---------------------------------------------------------------------------
-template <int KIND, int PREC, class CL>
-__device__ __forceinline__ void trial_move(const SysDev& S, const SpeciesDev& P,
-                                           double* __restrict__ pos, double* __restrict__ ori,
-                                           const CL& cl, uint32_t c, const int (&cc)[3],
-                                           uint32_t select, uint32_t t, uint32_t k0, uint32_t k1,
-                                           const double (&sh)[3], Counters& ct) {
-    constexpr int D = Traits<KIND>::dim;
-    const uint32_t beg = cl.begin(c), fin = cl.end(c);
-    if (beg == fin) return;
-    ct.v[kAttempted]++;
-    const uint4 ws = draw(t, kSelect, select, c, S.replica, k0, k1);
-    const uint32_t i = cl.member(beg + index_below(ws.x, fin - beg));
-    const uint4 m = draw(t, kMove, select, i, S.replica, k0, k1);
-    const int N = S.N;
-
-    double xn[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < D; ++a) xn[a] = pos[a * N + i];
-    double qn[4];
-    load_orient<KIND>(ori, N, i, qn);
-
-    const bool rotate = KIND != kDisk && P.p_rot > 0.0 && u01(m.x) < P.p_rot;
-    if (!rotate) {
-        const uint32_t mw[3] = {m.y, m.z, m.w};
-        bool leaves = false;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            xn[a] = wrap_periodic(xn[a] + P.d * (2.0 * u01(mw[a]) - 1.0), S.L);
-            leaves |= cell_coord(xn[a], sh[a], S.L, S.inv_w, S.n) != cc[a];
-        }
-        if (leaves) {
-            ct.v[kCellReject]++;
-            return;
-        }
-    } else {
-        ct.v[kAttemptedRot]++;
-        if constexpr (KIND == kPolygon) {
-            const double delta = P.a * (2.0 * u01(m.y) - 1.0);
-            double cd, sd;
-            small_angle_sincos(delta, cd, sd);
-            const double c0 = qn[0], s0 = qn[1];
-            qn[0] = c0 * cd - s0 * sd;
-            qn[1] = s0 * cd + c0 * sd;
-        } else if constexpr (KIND == kPolyhedron) {
-            const Quat dq{1.0, P.a * (2.0 * u01(m.y) - 1.0), P.a * (2.0 * u01(m.z) - 1.0),
-                          P.a * (2.0 * u01(m.w) - 1.0)};
-            const Quat p = qmul(Quat{qn[0], qn[1], qn[2], qn[3]}, dq);
-            const double nrm = sqrt(((p.w * p.w + p.x * p.x) + p.y * p.y) + p.z * p.z);
-            qn[0] = p.w / nrm;
-            qn[1] = p.x / nrm;
-            qn[2] = p.y / nrm;
-            qn[3] = p.z / nrm;
-        }
-    }
-
-    const int n = S.n;
-    bool hit = false;
-    constexpr int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
-    for (int oz = zlo; oz <= zhi && !hit; ++oz) {
-        int z = cc[2] + oz;
-        z += z < 0 ? n : 0;
-        z -= z >= n ? n : 0;
-        for (int oy = -1; oy <= 1 && !hit; ++oy) {
-            int y = cc[1] + oy;
-            y += y < 0 ? n : 0;
-            y -= y >= n ? n : 0;
-            for (int ox = -1; ox <= 1 && !hit; ++ox) {
-                int x = cc[0] + ox;
-                x += x < 0 ? n : 0;
-                x -= x >= n ? n : 0;
-                const uint32_t cn = (uint32_t)(x + n * (y + n * z));
-                const uint32_t e = cl.end(cn);
-                for (uint32_t p = cl.begin(cn); p < e; ++p) {
-                    const uint32_t k = cl.member(p);
-                    if (k == i) continue;
-                    double r[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int a = 0; a < D; ++a) r[a] = min_image(pos[a * N + k] - xn[a], S.L, S.inv_L);
-                    double r2 = r[0] * r[0] + r[1] * r[1];
-                    if constexpr (D == 3) r2 = r2 + r[2] * r[2];
-                    if (!(r2 < P.circ2)) continue;
-                    double qk[4];
-                    load_orient<KIND>(ori, N, k, qk);
-                    if (full_test<KIND, PREC>(P, r, qn, qk, ct)) {
-                        hit = true;
-                        break;
-                    }
-                }
-            }
-        }
-    }
-    if (hit) {
-        ct.v[kOverlapReject]++;
-        return;
-    }
-#pragma unroll
-    for (int a = 0; a < D; ++a) pos[a * N + i] = xn[a];
-    if constexpr (KIND == kPolygon) {
-        ori[i] = qn[0];
-        ori[N + i] = qn[1];
-    } else if constexpr (KIND == kPolyhedron) {
-        ori[i] = qn[0];
-        ori[N + i] = qn[1];
-        ori[2 * N + i] = qn[2];
-        ori[3 * N + i] = qn[3];
-    }
-    ct.v[kAccept]++;
-}
-
-__device__ __forceinline__ void grid_shift(const SysDev& S, uint32_t t, uint32_t k0, uint32_t k1,
-                                           int shifted, double (&sh)[3]) {
-    sh[0] = sh[1] = sh[2] = 0.0;
-    if (shifted) {
-        const uint4 w = draw(t, kShift, 0u, 0u, (uint32_t)S.replica, k0, k1);
-        sh[0] = S.w * u01(w.x);
-        sh[1] = S.w * u01(w.y);
-        sh[2] = S.w * u01(w.z);
-    }
-}
-
-template <int D>
-__device__ __forceinline__ uint32_t particle_cell(const SysDev& S, const double* __restrict__ pos,
-                                                  int i, const double (&sh)[3]) {
-    const int N = S.N, n = S.n;
-    const int cx = cell_coord(pos[i], sh[0], S.L, S.inv_w, n);
-    const int cy = cell_coord(pos[N + i], sh[1], S.L, S.inv_w, n);
-    int cz = 0;
-    if constexpr (D == 3) cz = cell_coord(pos[2 * N + i], sh[2], S.L, S.inv_w, n);
-    return (uint32_t)(cx + n * (cy + n * cz));
-}
-
-__device__ __forceinline__ void active_cell(const SysDev& S, int D, uint32_t colour, int a,
-                                            int (&cc)[3], uint32_t& c) {
-    const int half = S.n / 2;
-    cc[0] = 2 * (a % half) + (int)(colour & 1u);
-    cc[1] = 2 * ((a / half) % half) + (int)((colour >> 1) & 1u);
-    cc[2] = D == 3 ? 2 * (a / (half * half)) + (int)((colour >> 2) & 1u) : 0;
-    c = (uint32_t)(cc[0] + S.n * (cc[1] + S.n * cc[2]));
-}
 
 // ---------------------------------------------------------------------------
 // Work-group scans (blockDim.x a multiple of 64, at most 1024).
@@ -298,7 +71,7 @@ __global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys, 
     if (i >= S.N) return;
     double sh[3];
     grid_shift(S, t, k0, k1, shifted, sh);
-    const uint32_t c = particle_cell<D>(S, pos_base + S.pos_off, i, sh);
+    const uint32_t c = particle_cell<D>(S, PosView{const_cast<double*>(pos_base) + S.pos_off, S.N}, (uint32_t)i, sh);
     cell_of[i] = c;
     slot_of[i] = atomicAdd(count + c, 1u);
 }
@@ -401,7 +174,9 @@ __global__ void __launch_bounds__(256) k_sort_cells(const uint32_t* __restrict__
     }
 }
 
-template <int KIND, int PREC>
+// One colour pass of the grid path: one wave per tile of 64/G active cells,
+// four waves per work-group.
+template <int KIND, int PREC, int G>
 __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                                 const SpeciesDev* __restrict__ spc, int r,
                                                 double* __restrict__ pos_base,
@@ -412,21 +187,22 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                                 uint32_t k0, uint32_t k1,
                                                 unsigned long long* __restrict__ stats) {
     constexpr int D = Traits<KIND>::dim;
+    __shared__ uint32_t qbuf[4][kQueueWords];
+    __shared__ uint32_t fbuf[4][kFlagWords];
     const SysDev S = sys[r];
     const SpeciesDev& P = spc[S.species];
     Counters ct = {};
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
-    const int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a < n_act) {
+    const int wave = threadIdx.x >> 6;
+    const int a0 = (blockIdx.x * 4 + wave) * (64 / G);
+    if (a0 < n_act) {
         double sh[3];
         grid_shift(S, t, k0, k1, 1, sh);
-        int cc[3];
-        uint32_t c;
-        active_cell(S, D, colour, a, cc, c);
-        GlobalCells cl{start, members};
-        trial_move<KIND, PREC>(S, P, pos_base + S.pos_off, ori_base + S.orient_off, cl, c, cc,
-                               select, t, k0, k1, sh, ct);
+        const PosView pos{pos_base + S.pos_off, S.N};
+        const GlobalCells cl{start, members};
+        pass_tile<KIND, PREC, G>(S, P, pos, ori_base + S.orient_off, cl, colour, select, t, k0, k1,
+                                 sh, a0, n_act, WaveScratch{qbuf[wave], fbuf[wave]}, ct);
     }
     flush(ct, stats + (size_t)r * kNumStats);
 }
@@ -484,49 +260,104 @@ __global__ void __launch_bounds__(256) k_count(const SysDev* __restrict__ sys,
 }
 
 // ---------------------------------------------------------------------------
-// Persistent path: whole sweeps per work-group, cell list in LDS.
-// LDS: ends[ncells] u32, 16 scan words, members[N] u16.
+// Persistent path: one work-group owns one replica and runs whole sweeps.
+// LDS (dynamic): [positions D*N f64, when resident] [members N u16]
+// [ends ncells u16] [union: counts ncells u32 while building the cell list /
+// wave queues and flags during the passes] [16 scan words].
 // ---------------------------------------------------------------------------
-template <int KIND, int PREC>
-__device__ void persistent_body(const SysDev& S, const SpeciesDev& P, double* __restrict__ pos,
-                                double* __restrict__ ori, uint32_t* ends, uint32_t* sm,
-                                uint16_t* mem, uint32_t t0, uint32_t n_sweeps, uint32_t k0,
-                                uint32_t k1, Counters& ct) {
+struct BatchLds {
+    double* pos;
+    uint16_t* mem;
+    uint16_t* ends;
+    uint32_t* uni;
+    uint32_t* scan;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t batch_lds_bytes(int dim, int N, int ncells, int nwaves,
+                                                  bool resident, size_t* off) {
+    size_t o = 0;
+    off[0] = o;
+    o += resident ? align16((size_t)dim * N * 8) : 0;
+    off[1] = o;
+    o += align16((size_t)N * 2);
+    off[2] = o;
+    o += align16((size_t)ncells * 2);
+    off[3] = o;
+    const size_t uni_words = (size_t)ncells > (size_t)nwaves * (kQueueWords + kFlagWords)
+                                 ? (size_t)ncells
+                                 : (size_t)nwaves * (kQueueWords + kFlagWords);
+    o += align16(uni_words * 4);
+    off[4] = o;
+    o += 16 * 4;
+    return o;
+}
+
+template <int KIND, int PREC, bool RESIDENT>
+__global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict__ sys,
+                                                       const SpeciesDev* __restrict__ spc,
+                                                       const int32_t* __restrict__ list,
+                                                       double* __restrict__ pos_base,
+                                                       double* __restrict__ ori_base,
+                                                       unsigned long long* __restrict__ stats,
+                                                       uint32_t t0, uint32_t n_sweeps, uint32_t k0,
+                                                       uint32_t k1) {
     constexpr int D = Traits<KIND>::dim;
-    const int tid = threadIdx.x, B = blockDim.x;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int r = list[blockIdx.x];
+    const SysDev S = sys[r];
+    const SpeciesDev& P = spc[S.species];
+    const int tid = threadIdx.x, B = blockDim.x, nwaves = B >> 6, wave = tid >> 6;
     const int N = S.N, nc = S.ncells;
+    size_t off[5];
+    batch_lds_bytes(D, N, nc, nwaves, RESIDENT, off);
+    double* gpos = pos_base + S.pos_off;
+    double* ori = ori_base + S.orient_off;
+    const PosView pos{RESIDENT ? reinterpret_cast<double*>(lds + off[0]) : gpos, N};
+    uint16_t* mem = reinterpret_cast<uint16_t*>(lds + off[1]);
+    uint16_t* ends = reinterpret_cast<uint16_t*>(lds + off[2]);
+    uint32_t* uni = reinterpret_cast<uint32_t*>(lds + off[3]);
+    uint32_t* sm = reinterpret_cast<uint32_t*>(lds + off[4]);
+    if constexpr (RESIDENT) {
+        for (int k = tid; k < D * N; k += B) pos.p[k] = gpos[k];
+    }
+    __syncthreads();
+    Counters ct = {};
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
     const int chunk = (nc + B - 1) / B;
+    const WaveScratch wscr{uni + wave * (kQueueWords + kFlagWords),
+                           uni + wave * (kQueueWords + kFlagWords) + kQueueWords};
     for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
         const uint32_t t = t0 + sw;
         double sh[3];
         grid_shift(S, t, k0, k1, 1, sh);
-        // counting sort of the shifted grid into LDS
-        for (int c = tid; c < nc; c += B) ends[c] = 0u;
+        // counting sort of the shifted grid (ascending tags within a cell)
+        uint32_t* count = uni;
+        for (int c = tid; c < nc; c += B) count[c] = 0u;
         __syncthreads();
-        for (int i = tid; i < N; i += B) atomicAdd(ends + particle_cell<D>(S, pos, i, sh), 1u);
+        for (int i = tid; i < N; i += B) atomicAdd(count + particle_cell<D>(S, pos, (uint32_t)i, sh), 1u);
         __syncthreads();
         {
             const int c0 = tid * chunk, c1 = min(nc, c0 + chunk);
             uint32_t s = 0;
-            for (int c = c0; c < c1; ++c) s += ends[c];
+            for (int c = c0; c < c1; ++c) s += count[c];
             uint32_t total;
             uint32_t run = block_exclusive_scan(s, sm, total);
             for (int c = c0; c < c1; ++c) {
-                const uint32_t v = ends[c];
-                ends[c] = run;
+                const uint32_t v = count[c];
+                count[c] = run;
                 run += v;
             }
         }
         __syncthreads();
-        for (int i = tid; i < N; i += B) {
-            const uint32_t p = atomicAdd(ends + particle_cell<D>(S, pos, i, sh), 1u);
-            mem[p] = (uint16_t)i;
-        }
+        for (int i = tid; i < N; i += B)
+            mem[atomicAdd(count + particle_cell<D>(S, pos, (uint32_t)i, sh), 1u)] = (uint16_t)i;
         __syncthreads();
         for (int c = tid; c < nc; c += B) {
-            const uint32_t b = c ? ends[c - 1] : 0u, e = ends[c];
+            const uint32_t b = c ? count[c - 1] : 0u, e = count[c];
+            ends[c] = (uint16_t)e;
             for (uint32_t p = b + 1; p < e; ++p) {
                 const uint16_t v = mem[p];
                 uint32_t q = p;
@@ -543,43 +374,16 @@ __device__ void persistent_body(const SysDev& S, const SpeciesDev& P, double* __
         for (int rnd = 0; rnd < S.rounds; ++rnd) {
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
-                for (int a = tid; a < n_act; a += B) {
-                    int cc[3];
-                    uint32_t c;
-                    active_cell(S, D, colour, a, cc, c);
-                    trial_move<KIND, PREC>(S, P, pos, ori, cl, c, cc, select, t, k0, k1, sh, ct);
-                }
+                for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64)
+                    pass_tile<KIND, PREC, 1>(S, P, pos, ori, cl, colour, select, t, k0, k1, sh, a0,
+                                             n_act, wscr, ct);
                 __syncthreads();
             }
         }
     }
-}
-
-template <int PREC>
-__global__ void __launch_bounds__(256) k_persistent(const SysDev* __restrict__ sys,
-                                                    const SpeciesDev* __restrict__ spc,
-                                                    double* __restrict__ pos_base,
-                                                    double* __restrict__ ori_base,
-                                                    unsigned long long* __restrict__ stats,
-                                                    uint32_t t0, uint32_t n_sweeps, uint32_t k0,
-                                                    uint32_t k1) {
-    extern __shared__ uint32_t lds[];
-    const int r = blockIdx.x;
-    const SysDev S = sys[r];
-    const SpeciesDev& P = spc[S.species];
-    uint32_t* ends = lds;
-    uint32_t* sm = lds + S.ncells;
-    uint16_t* mem = reinterpret_cast<uint16_t*>(sm + 16);
-    double* pos = pos_base + S.pos_off;
-    double* ori = ori_base + S.orient_off;
-    Counters ct = {};
-    const int kind = P.kind;
-    if (kind == kDisk)
-        persistent_body<kDisk, PREC>(S, P, pos, ori, ends, sm, mem, t0, n_sweeps, k0, k1, ct);
-    else if (kind == kPolygon)
-        persistent_body<kPolygon, PREC>(S, P, pos, ori, ends, sm, mem, t0, n_sweeps, k0, k1, ct);
-    else
-        persistent_body<kPolyhedron, PREC>(S, P, pos, ori, ends, sm, mem, t0, n_sweeps, k0, k1, ct);
+    if constexpr (RESIDENT) {
+        for (int k = tid; k < D * N; k += B) gpos[k] = pos.p[k];
+    }
     flush(ct, stats + (size_t)r * kNumStats);
 }
 
@@ -588,8 +392,9 @@ __global__ void __launch_bounds__(256) k_persistent(const SysDev* __restrict__ s
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
-size_t persistent_lds_bytes(int ncells, int N) {
-    return (size_t)ncells * 4 + 16 * 4 + (size_t)((N + 1) & ~1) * 2;
+size_t persistent_lds_bytes(int dim, int ncells, int N, bool resident) {
+    size_t off[5];
+    return batch_lds_bytes(dim, N, ncells, kBatchBlock / 64, resident, off);
 }
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream) {
@@ -618,18 +423,31 @@ hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const 
     return hipGetLastError();
 }
 
+template <int KIND, int PREC, int G>
+static void launch_passes_g(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
+                            double* orient, uint32_t t, uint32_t k0, uint32_t k1,
+                            hipStream_t stream) {
+    const int half = rh.n / 2;
+    const long n_act = rh.dim == 3 ? (long)half * half * half : (long)half * half;
+    const int cells_per_block = 4 * (64 / G);
+    const uint32_t ncol = 1u << rh.dim;
+    for (int rnd = 0; rnd < rh.rounds; ++rnd)
+        for (uint32_t colour = 0; colour < ncol; ++colour)
+            k_update<KIND, PREC, G><<<blocks_for(n_act, cells_per_block), 256, 0, stream>>>(
+                ws.sys, ws.species, r, pos, orient, ws.start, ws.members, colour,
+                (uint32_t)rnd * ncol + colour, t, k0, k1, ws.stats);
+}
+
 template <int KIND, int PREC>
 static void launch_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
                           double* orient, uint32_t t, uint32_t k0, uint32_t k1,
                           hipStream_t stream) {
-    const int half = rh.n / 2;
-    const long n_act = rh.dim == 3 ? (long)half * half * half : (long)half * half;
-    const uint32_t ncol = 1u << rh.dim;
-    for (int rnd = 0; rnd < rh.rounds; ++rnd)
-        for (uint32_t colour = 0; colour < ncol; ++colour)
-            k_update<KIND, PREC><<<blocks_for(n_act, 256), 256, 0, stream>>>(
-                ws.sys, ws.species, r, pos, orient, ws.start, ws.members, colour,
-                (uint32_t)rnd * ncol + colour, t, k0, k1, ws.stats);
+    switch (rh.lanes_per_cell) {
+        case 8: launch_passes_g<KIND, PREC, 8>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
+        case 4: launch_passes_g<KIND, PREC, 4>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
+        case 2: launch_passes_g<KIND, PREC, 2>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
+        default: launch_passes_g<KIND, PREC, 1>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
+    }
 }
 
 hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
@@ -646,16 +464,34 @@ hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double
     return hipGetLastError();
 }
 
-hipError_t persistent_sweeps(const Workspace& ws, int n_replicas, size_t lds_bytes, double* pos,
-                             double* orient, int precision, uint32_t t0, uint32_t n_sweeps,
-                             uint32_t k0, uint32_t k1, int block, hipStream_t stream) {
-    if (precision == 1)
-        k_persistent<1><<<n_replicas, block, lds_bytes, stream>>>(ws.sys, ws.species, pos, orient,
-                                                                  ws.stats, t0, n_sweeps, k0, k1);
-    else
-        k_persistent<0><<<n_replicas, block, lds_bytes, stream>>>(ws.sys, ws.species, pos, orient,
-                                                                  ws.stats, t0, n_sweeps, k0, k1);
+template <int KIND, int PREC, bool RESIDENT>
+static hipError_t launch_batch(const Workspace& ws, const int32_t* list, int n, size_t lds,
+                               double* pos, double* orient, uint32_t t0, uint32_t n_sweeps,
+                               uint32_t k0, uint32_t k1, hipStream_t stream) {
+    auto kern = k_batch<KIND, PREC, RESIDENT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    kern<<<n, kBatchBlock, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats, t0,
+                                          n_sweeps, k0, k1);
     return hipGetLastError();
+}
+
+hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* pos,
+                             double* orient, int precision, uint32_t t0, uint32_t n_sweeps,
+                             uint32_t k0, uint32_t k1, hipStream_t stream) {
+    const int32_t* list = ws.batch_list + g.first;
+    const bool res = g.resident != 0;
+#define HPMC_LAUNCH(K, PR)                                                                     \
+    return res ? launch_batch<K, PR, true>(ws, list, g.count, g.lds_bytes, pos, orient, t0,    \
+                                           n_sweeps, k0, k1, stream)                            \
+               : launch_batch<K, PR, false>(ws, list, g.count, g.lds_bytes, pos, orient, t0,   \
+                                            n_sweeps, k0, k1, stream)
+    if (g.kind == kDisk) HPMC_LAUNCH(kDisk, 0);
+    if (g.kind == kPolygon && precision == 1) HPMC_LAUNCH(kPolygon, 1);
+    if (g.kind == kPolygon) HPMC_LAUNCH(kPolygon, 0);
+    HPMC_LAUNCH(kPolyhedron, 0);
+#undef HPMC_LAUNCH
 }
 
 hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,

@@ -9,6 +9,8 @@
 
 namespace hpmc {
 
+constexpr int kBatchBlock = 1024;  // lanes per persistent work-group (16 waves)
+
 struct Workspace {
     SpeciesDev* species;              // one per replica
     SysDev* sys;                      // one per replica
@@ -21,11 +23,19 @@ struct Workspace {
     uint32_t* slot_of;  // N
     uint32_t* members;  // N
     uint32_t* partial;  // scan tiles
+    int32_t* batch_list;  // replica indices of the persistent path, grouped by kind
 };
 
 struct ReplicaHost {
     int32_t kind, dim, N, n, ncells, rounds, path;
+    int32_t lanes_per_cell;  // grid path: lanes per active cell (1, 2, 4, 8)
     int64_t pos_off, orient_off;
+};
+
+// Replicas of one shape kind launched together on the persistent path.
+struct BatchGroup {
+    int32_t kind, first, count, resident;
+    size_t lds_bytes;
 };
 
 constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
@@ -40,11 +50,11 @@ hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double
                        double* orient, int precision, uint32_t t, uint32_t k0, uint32_t k1,
                        hipStream_t stream);
 
-// n_sweeps whole sweeps of every replica, one work-group of `block` lanes
-// each (all replicas must be on the persistent path).
-hipError_t persistent_sweeps(const Workspace& ws, int n_replicas, size_t lds_bytes, double* pos,
+// n_sweeps whole sweeps of the replicas of one batch group, one work-group
+// each.
+hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* pos,
                              double* orient, int precision, uint32_t t0, uint32_t n_sweeps,
-                             uint32_t k0, uint32_t k1, int block, hipStream_t stream);
+                             uint32_t k0, uint32_t k1, hipStream_t stream);
 
 // Overlapping pairs of replica r (after build_cells with shifted = 0), added
 // to ws.overlap_out[r].
@@ -58,6 +68,7 @@ hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, con
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream);
 
-size_t persistent_lds_bytes(int ncells, int N);
+// Dynamic LDS of a persistent work-group (positions resident or not).
+size_t persistent_lds_bytes(int dim, int ncells, int N, bool resident);
 
 }  // namespace hpmc

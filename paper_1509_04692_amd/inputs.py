@@ -160,15 +160,43 @@ def pentagon_interlocked_lattice(sp, N, L, seed=INIT_SEED):
     return np.ascontiguousarray(pos), orient
 
 
+def disk_triangular_lattice(sp, N, L, seed=INIT_SEED):
+    """Disks on a staggered (triangular) lattice: rows alternately shifted by
+    half a column pitch, an even number of rows so the stagger is periodic;
+    every neighbour distance at least 1.0001 sigma."""
+    sig = sp["diameter"] * 1.0001
+    mx = int(L // sig)
+    px = L / mx
+    if px / 2 >= sig:
+        raise ValueError("use the square lattice")
+    py_min = math.sqrt(sig * sig - (px / 2) ** 2)
+    my = int(L // py_min)
+    my -= my % 2
+    if my < 2 or mx * my < N:
+        raise ValueError("packing fraction too high for a triangular disk lattice")
+    ix, iy = np.meshgrid(np.arange(mx), np.arange(my), indexing="ij")
+    ix, iy = ix.ravel(order="F"), iy.ravel(order="F")
+    if mx * my > N:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        keep = np.sort(rng.choice(mx * my, size=N, replace=False))
+        ix, iy = ix[keep], iy[keep]
+    x = (ix + 0.25 + 0.5 * (iy % 2)) * px
+    pos = np.stack([x, (iy + 0.5) * (L / my)], axis=0)
+    return np.ascontiguousarray(pos), identity_orientations(sp, N)
+
+
 def initial_state(sp, N, phi, seed=INIT_SEED):
     """(L, pos, orient) of a valid starting configuration at packing fraction phi."""
     L = box_length(N, sp["volume"], phi, sp["dim"])
     try:
         pos, orient = simple_lattice(sp, N, L, seed)
     except ValueError:
-        if sp["shape"] != "polygon" or len(sp["verts"]) != 5:
+        if sp["shape"] == "disk":
+            pos, orient = disk_triangular_lattice(sp, N, L, seed)
+        elif sp["shape"] == "polygon" and len(sp["verts"]) == 5:
+            pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
+        else:
             raise
-        pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
     return L, pos, orient
 
 
