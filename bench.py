@@ -157,6 +157,33 @@ def cpu_baseline(wl, warmup, steps, budget_s=12.0):
     }, opm, {k: v / max(int(st[0]), 1) for k, v in ev.items()}, n_count
 
 
+def _csrc_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1509_04692_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_sweeps):
+    """HBM bytes per launch of the timed kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs recorded under profiles/, each scaled by the same counter's
+    reading for a plain copy of known size; None when the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_batch_pentagons.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("csrc_sha256") != _csrc_hash() or d.get("launch_sweeps") != kernel_sweeps:
+        return None
+    return (d["fetch_kib"] * d["fetch_factor"] + d["write_kib"] * d["write_factor"]) * 1024.0
+
+
 def _device_info():
     import torch
     p = torch.cuda.get_device_properties(0)
@@ -168,12 +195,14 @@ def _device_info():
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed sweeps")
-    ap.add_argument("--warmup", type=int, default=20, help="untimed sweeps first")
+    ap.add_argument("--steps", type=int, default=256, help="timed sweeps (multiple of 64: whole launches)")
+    ap.add_argument("--warmup", type=int, default=64, help="untimed sweeps first")
     ap.add_argument("--workload", default="pentagons",
                     choices=["pentagons", "disks", "cubes", "trunc_oct", "large", "screening"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized buffer once (calibrates HBM byte counters)")
     ap.add_argument("--only", default=None,
                     help="comma list of runs: mixed_batched,fp64_single,fp64_batched,mixed_single")
     args = ap.parse_args()
@@ -188,6 +217,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 8
+        a = torch.arange(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "ok": bool(b[-1].item() == n - 1)}))
+        return 0
     wl = workload(args.workload)
     batched_ok = wl["replicas"] is None or wl["replicas"] > 1
     runs = ["mixed_batched", "fp64_single", "fp64_batched", "mixed_single"]
@@ -213,6 +251,7 @@ def main():
             "recheck_fraction": (diff["pair_fp64"] / diff["pair_tests"]
                                  if precision == "mixed" and diff["pair_tests"] else None),
             "moves": diff["attempted"],
+            "pair_tests_per_move": diff["pair_tests"] / max(diff["attempted"], 1),
             "launches": n_launch,
             "ms_total": ms,
         }
@@ -235,9 +274,14 @@ def main():
             launch_s = h["ms_total"] * 1e-3
             ops_per_launch = opm * h["moves"]
         achieved = ops_per_launch / launch_s / 1e12
+        traffic = None
+        if head == "mixed_batched" and args.workload == "pentagons" and h["launches"]:
+            if args.steps % PERSISTENT_SWEEPS_PER_LAUNCH == 0:
+                traffic = measured_traffic(PERSISTENT_SWEEPS_PER_LAUNCH)
         roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                    "ops_per_move": opm, "kernel": "k_persistent" if h["launches"] else "k_update",
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                    "traffic_unit": "bytes per launch",
+                    "ops_per_move": opm, "kernel": "k_batch" if h["launches"] else "k_update",
                     "avg_launch_ms": launch_s * 1e3, "events_per_move": ev_per_move,
                     "events_counted_sweeps": n_count}
     line = {
