@@ -201,6 +201,7 @@ def main():
                     choices=["pentagons", "disks", "cubes", "trunc_oct", "large", "screening"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer once (calibrates HBM byte counters)")
     ap.add_argument("--only", default=None,
@@ -239,6 +240,7 @@ def main():
         batched = mode == "batched"
         path = "persistent" if batched else "grid"
         system = make_system(wl, precision, path, batched)
+        tuned = system.autotune(trial_sweeps=8) if not args.no_autotune else None
         ms, diff = timed_run(system, args.steps, args.warmup, args.seed)
         n_launch = (math.ceil(args.steps / PERSISTENT_SWEEPS_PER_LAUNCH) if path == "persistent"
                     else None)
@@ -253,6 +255,8 @@ def main():
             "moves": diff["attempted"],
             "pair_tests_per_move": diff["pair_tests"] / max(diff["attempted"], 1),
             "launches": n_launch,
+            "autotuned": tuned,
+            "graph": system.uses_graph,
             "ms_total": ms,
         }
         del system

@@ -54,6 +54,9 @@ extern "C" {
 /* The persistent path launches one kernel per this many sweeps. */
 #define HPMC_PERSISTENT_SWEEPS_PER_LAUNCH 64
 
+/* hpmc_init_args.flags */
+#define HPMC_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a hipGraph */
+
 /* Opaque host-side handle of one set of replicas. */
 typedef struct hpmc_state hpmc_state;
 
@@ -105,6 +108,7 @@ typedef struct {
     void *workspace;               /* device, caller-owned, 256-byte aligned */
     size_t workspace_bytes;
     void *stream;                  /* hipStream_t or NULL */
+    int32_t flags;                 /* HPMC_FLAG_* */
 } hpmc_init_args;
 
 /* Per-replica counters since init or the last hpmc_reset_stats. */
@@ -133,6 +137,15 @@ int hpmc_init(hpmc_state **out, const hpmc_init_args *args);
  * sweeps equal one call of a + b).  Asynchronous on the state's stream. */
 int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
 
+/* Time the launch configurations this state can use (grid path: lanes per
+ * active cell 1, 2, 4, 8; persistent path: which particle data stays in LDS)
+ * over trial_sweeps sweeps each, keep the fastest, and restore positions,
+ * orientations, counters and the sweep counter exactly.  The trajectory does
+ * not depend on the configuration.  Synchronising.  *out_config (may be
+ * NULL) receives the chosen lanes per cell (grid) or residency level
+ * (persistent). */
+int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
+
 /* Unordered overlapping pairs per replica under the exact FP64 predicate
  * (circumsphere test and full test, the paper's system-level check, Sec. 4).
  * out_per_replica: host, n_replicas entries.  Synchronising. */
@@ -154,6 +167,9 @@ int hpmc_set_sweep(hpmc_state *st, uint64_t t);
 /* Cells per side, rounds per sweep and path chosen for replica r. */
 int hpmc_replica_info(hpmc_state *st, int32_t r, int32_t *cells_per_side, int32_t *rounds,
                       int32_t *path);
+
+/* 1 if sweeps replay a captured hipGraph, 0 if kernels are launched directly. */
+int hpmc_uses_graph(hpmc_state *st);
 
 /* The hipError_t of the last failed HIP call of this state (0 if none). */
 int hpmc_last_hip_error(hpmc_state *st);

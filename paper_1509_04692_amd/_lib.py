@@ -26,10 +26,11 @@ STAT_FIELDS = ("attempted", "attempted_rot", "cell_reject", "overlap_reject", "a
                "pair_tests", "pair_fp64", "sweeps")
 
 # Every symbol include/hpmc.h declares.
-EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_count_overlaps",
-           "hpmc_get_stats", "hpmc_reset_stats", "hpmc_sync_to_canonical", "hpmc_get_sweep",
-           "hpmc_set_sweep", "hpmc_replica_info", "hpmc_last_hip_error", "hpmc_destroy",
-           "hpmc_strerror")
+EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune",
+           "hpmc_count_overlaps", "hpmc_get_stats", "hpmc_reset_stats", "hpmc_sync_to_canonical",
+           "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info", "hpmc_uses_graph",
+           "hpmc_last_hip_error", "hpmc_destroy", "hpmc_strerror")
+FLAG_NO_GRAPH = 1
 
 
 class HpmcError(RuntimeError):
@@ -68,6 +69,7 @@ class InitArgs(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
+        ("flags", ctypes.c_int32),
     ]
 
 
@@ -91,6 +93,8 @@ def load(path=None):
     lib.hpmc_workspace_bytes.argtypes = [ctypes.POINTER(InitArgs), ctypes.POINTER(ctypes.c_size_t)]
     lib.hpmc_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(InitArgs)]
     lib.hpmc_sweep.argtypes = [st, ctypes.c_uint64, ctypes.c_uint64]
+    lib.hpmc_autotune.argtypes = [st, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32)]
+    lib.hpmc_uses_graph.argtypes = [st]
     lib.hpmc_count_overlaps.argtypes = [st, ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_get_stats.argtypes = [st, ctypes.POINTER(Stats)]
     lib.hpmc_reset_stats.argtypes = [st]

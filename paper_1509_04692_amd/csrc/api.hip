@@ -30,6 +30,10 @@ struct hpmc_state {
     uint64_t t = 0;
     uint64_t sweeps_done = 0;
     int last_hip = 0;
+    int flags = 0;
+    size_t pos_total = 0, ori_total = 0;  // doubles in the caller's arrays
+    hipStream_t cap_stream = nullptr;     // private stream used only for capture
+    hipGraphExec_t graph = nullptr;       // one sweep (grid) / one chunk (persistent)
 };
 
 namespace {
@@ -171,7 +175,8 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
 
 struct Layout {
     size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, partial, list,
-        total;
+        clock, backup_pos, backup_ori, backup_stats, total;
+    size_t pos_total, ori_total;
 };
 
 // Lanes per active cell on the grid path: enough waves to cover the chip
@@ -214,11 +219,13 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         ori_off += (int64_t)ncomp * sys[r].N;
         nc_max = std::max<int64_t>(nc_max, sys[r].ncells);
         n_max = std::max<int64_t>(n_max, sys[r].N);
-        const size_t lb = persistent_lds_bytes(sys[r].dim, sys[r].ncells, sys[r].N, false);
+        const int ncomp_r = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
+        const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, sys[r].ncells, sys[r].N, 0);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
         const int half = sys[r].n / 2;
         const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
         rep[r].lanes_per_cell = choose_lanes_per_cell(n_act);
+        rep[r].nv = spc[r].nv;
     }
     if (a->path == HPMC_PATH_PERSISTENT && !fits_lds) return HPMC_ERR_UNSUPPORTED;
     if (a->path == HPMC_PATH_AUTO)
@@ -235,18 +242,28 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     list.clear();
     if (path == HPMC_PATH_PERSISTENT) {
         for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
-            BatchGroup g{kind, (int32_t)list.size(), 0, 1, 0};
-            size_t res = 0, nonres = 0;
+            BatchGroup g{kind, (int32_t)list.size(), 0, 0, -1, 0, {0, 0, 0}};
+            const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
+            size_t need[3] = {0, 0, 0};
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
                 list.push_back(r);
                 g.count++;
-                res = std::max(res, persistent_lds_bytes(sys[r].dim, sys[r].ncells, sys[r].N, true));
-                nonres = std::max(nonres, persistent_lds_bytes(sys[r].dim, sys[r].ncells, sys[r].N, false));
+                g.nv = (g.nv == -1 || g.nv == spc[r].nv) ? spc[r].nv : 0;
+                for (int lv = 0; lv < 3; ++lv)
+                    need[lv] = std::max(need[lv], persistent_lds_bytes(sys[r].dim, ncomp, sys[r].ncells,
+                                                                       sys[r].N, lv));
             }
             if (g.count == 0) continue;
-            g.resident = res <= lds_limit ? 1 : 0;
-            g.lds_bytes = g.resident ? res : nonres;
+            g.resident = 0;
+            for (int lv = (kind == kDisk ? 1 : 2); lv >= 1; --lv)
+                if (need[lv] <= lds_limit) {
+                    g.resident = lv;
+                    break;
+                }
+            g.lds_bytes = need[g.resident];
+            for (int lv = 0; lv < 3; ++lv) g.need[lv] = need[lv];
+            if (g.nv < 0) g.nv = 0;
             groups.push_back(g);
         }
     }
@@ -268,6 +285,12 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.members = take(4 * (size_t)n_max);
     lay.partial = take(4 * (size_t)ntiles);
     lay.list = take(4 * (size_t)R);
+    lay.clock = take(sizeof(Clock));
+    lay.pos_total = (size_t)pos_off;
+    lay.ori_total = (size_t)ori_off;
+    lay.backup_pos = take(8 * (size_t)pos_off);
+    lay.backup_ori = take(8 * (size_t)(ori_off > 0 ? ori_off : 1));
+    lay.backup_stats = take(sizeof(unsigned long long) * kNumStats * R);
     lay.total = off;
     return HPMC_OK;
 }
@@ -276,7 +299,7 @@ int count_all(hpmc_state* st, uint64_t* out) {
     int rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
     if (rc) return rc;
     for (int r = 0; r < st->n_replicas; ++r) {
-        rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, 0u, 0u, 0u, 0, st->stream));
+        rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, 0, st->stream));
         if (rc) return rc;
         rc = check_hip(st, count_pairs(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
         if (rc) return rc;
@@ -285,6 +308,86 @@ int count_all(hpmc_state* st, uint64_t* out) {
                                       hipMemcpyDeviceToHost, st->stream));
     if (rc) return rc;
     return check_hip(st, hipStreamSynchronize(st->stream));
+}
+
+// One sweep (grid path) or `chunk` sweeps (persistent path) of every replica
+// on stream s, ending with the device clock advanced accordingly.
+int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
+    int rc = HPMC_OK;
+    if (st->path == HPMC_PATH_PERSISTENT) {
+        for (const BatchGroup& g : st->groups) {
+            rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, chunk,
+                                                 false, s));
+            if (rc) return rc;
+        }
+        return check_hip(st, advance_clock(st->ws, chunk, s));
+    }
+    for (int r = 0; r < st->n_replicas && !rc; ++r) {
+        rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, 1, s));
+        if (!rc) rc = check_hip(st, grid_passes(st->ws, st->rep[r], r, st->pos, st->orient, st->precision, s));
+    }
+    if (!rc) rc = check_hip(st, advance_clock(st->ws, 1, s));
+    return rc;
+}
+
+uint32_t sweep_unit(const hpmc_state* st) {
+    return st->path == HPMC_PATH_PERSISTENT ? kPersistentChunk : 1u;
+}
+
+void drop_graph(hpmc_state* st) {
+    if (st->graph) (void)hipGraphExecDestroy(st->graph);
+    st->graph = nullptr;
+}
+
+// Capture one sweep unit into a hipGraph on the private stream.  Failure
+// leaves the state in direct-launch mode (not an error).
+void capture_graph(hpmc_state* st) {
+    drop_graph(st);
+    if (st->flags & HPMC_FLAG_NO_GRAPH) return;
+    if (st->cap_stream == nullptr &&
+        hipStreamCreateWithFlags(&st->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        st->cap_stream = nullptr;
+        (void)hipGetLastError();
+        return;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(st->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const int last = st->last_hip;
+    const int rc = enqueue_sweeps(st, st->cap_stream, sweep_unit(st));
+    const hipError_t ec = hipStreamEndCapture(st->cap_stream, &g);
+    st->last_hip = last;
+    if (rc == HPMC_OK && ec == hipSuccess && g != nullptr) {
+        hipGraphExec_t ex = nullptr;
+        if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) st->graph = ex;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+}
+
+// Run n_sweeps from the current counter with key (k0, k1).
+int run_sweeps(hpmc_state* st, uint64_t n_sweeps, uint32_t k0, uint32_t k1) {
+    int rc = check_hip(st, set_clock(st->ws, (uint32_t)st->t, k0, k1, st->stream));
+    const uint32_t unit = sweep_unit(st);
+    uint64_t done = 0;
+    while (!rc && done + unit <= n_sweeps) {
+        if (st->graph) {
+            const hipError_t e = hipGraphLaunch(st->graph, st->stream);
+            if (e != hipSuccess) {  // fall back to direct launches from here on
+                (void)hipGetLastError();
+                drop_graph(st);
+                st->flags |= HPMC_FLAG_NO_GRAPH;
+                continue;
+            }
+        } else {
+            rc = enqueue_sweeps(st, st->stream, unit);
+        }
+        done += unit;
+    }
+    if (!rc && done < n_sweeps) rc = enqueue_sweeps(st, st->stream, (uint32_t)(n_sweeps - done));
+    return rc;
 }
 
 }  // namespace
@@ -343,6 +446,13 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->ws.members = (uint32_t*)(base + lay.members);
     st->ws.partial = (uint32_t*)(base + lay.partial);
     st->ws.batch_list = (int32_t*)(base + lay.list);
+    st->ws.clock = (Clock*)(base + lay.clock);
+    st->ws.backup_pos = (double*)(base + lay.backup_pos);
+    st->ws.backup_ori = (double*)(base + lay.backup_ori);
+    st->ws.backup_stats = (unsigned long long*)(base + lay.backup_stats);
+    st->pos_total = lay.pos_total;
+    st->ori_total = lay.ori_total;
+    st->flags = args->flags;
 
     rc = check_hip(st, hipMemcpyAsync(st->ws.species, st->spc.data(),
                                       sizeof(SpeciesDev) * st->n_replicas, hipMemcpyHostToDevice,
@@ -355,6 +465,10 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
                                           hipMemcpyHostToDevice, st->stream));
     if (!rc)
         rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kNumStats * st->n_replicas, st->stream));
+    if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
+    for (const BatchGroup& g : st->groups)
+        if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0,
+                                                      true, st->stream));
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
     if (!rc) {  // positions in [0, L) and finite orientations, before any cell lookup
         std::vector<uint64_t> bad(st->n_replicas, 0);
@@ -377,8 +491,9 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
             for (uint64_t c : counts)
                 if (c != 0) rc = HPMC_ERR_INITIAL_OVERLAP;
     }
+    if (!rc) capture_graph(st);
     if (rc) {
-        delete st;
+        hpmc_destroy(st);
         return rc;
     }
     *out = st;
@@ -389,31 +504,7 @@ int hpmc_sweep(hpmc_state* st, uint64_t n_sweeps, uint64_t seed) {
     if (st == nullptr) return HPMC_ERR_INVALID_ARG;
     if (n_sweeps == 0) return HPMC_OK;
     if (n_sweeps > kSweepLimit || st->t + n_sweeps > kSweepLimit) return HPMC_ERR_SWEEP_OVERFLOW;
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    int rc = HPMC_OK;
-    if (st->path == HPMC_PATH_PERSISTENT) {
-        uint64_t done = 0;
-        while (done < n_sweeps && !rc) {
-            const uint32_t chunk = (uint32_t)std::min<uint64_t>(kPersistentChunk, n_sweeps - done);
-            for (const BatchGroup& g : st->groups) {
-                if (rc) break;
-                rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision,
-                                                     (uint32_t)(st->t + done), chunk, k0, k1,
-                                                     st->stream));
-            }
-            done += chunk;
-        }
-    } else {
-        for (uint64_t s = 0; s < n_sweeps && !rc; ++s) {
-            const uint32_t t = (uint32_t)(st->t + s);
-            for (int r = 0; r < st->n_replicas && !rc; ++r) {
-                rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, t, k0, k1, 1, st->stream));
-                if (!rc)
-                    rc = check_hip(st, grid_passes(st->ws, st->rep[r], r, st->pos, st->orient,
-                                                   st->precision, t, k0, k1, st->stream));
-            }
-        }
-    }
+    const int rc = run_sweeps(st, n_sweeps, (uint32_t)seed, (uint32_t)(seed >> 32));
     if (rc) return rc;
     st->t += n_sweeps;
     st->sweeps_done += n_sweeps;
@@ -484,7 +575,84 @@ int hpmc_last_hip_error(hpmc_state* st) { return st ? st->last_hip : 0; }
 void hpmc_destroy(hpmc_state* st) {
     if (st == nullptr) return;
     (void)hipStreamSynchronize(st->stream);
+    drop_graph(st);
+    if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
     delete st;
+}
+
+int hpmc_uses_graph(hpmc_state* st) { return (st && st->graph) ? 1 : 0; }
+
+int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
+    if (st == nullptr || trial_sweeps == 0) return HPMC_ERR_INVALID_ARG;
+    const size_t nstat = (size_t)kNumStats * st->n_replicas;
+    // snapshot the caller's state
+    int rc = check_hip(st, hipMemcpyAsync(st->ws.backup_pos, st->pos, 8 * st->pos_total,
+                                          hipMemcpyDeviceToDevice, st->stream));
+    if (!rc && st->ori_total)
+        rc = check_hip(st, hipMemcpyAsync(st->ws.backup_ori, st->orient, 8 * st->ori_total,
+                                          hipMemcpyDeviceToDevice, st->stream));
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(st->ws.backup_stats, st->ws.stats, 8 * nstat,
+                                          hipMemcpyDeviceToDevice, st->stream));
+    if (rc) return rc;
+    std::vector<int> cands;
+    if (st->path == HPMC_PATH_PERSISTENT) {
+        int top = 0;
+        for (const BatchGroup& g : st->groups) top = std::max(top, (int)g.resident);
+        for (int lv = top; lv >= 0; --lv) cands.push_back(lv);
+    } else {
+        cands = {1, 2, 4, 8};
+    }
+    const std::vector<BatchGroup> groups0 = st->groups;
+    auto apply = [&](int c) {
+        if (st->path == HPMC_PATH_PERSISTENT) {
+            for (size_t i = 0; i < st->groups.size(); ++i) {
+                BatchGroup& g = st->groups[i];
+                g.resident = std::min<int>(c, groups0[i].resident);
+                g.lds_bytes = g.need[g.resident];
+                (void)persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0, true,
+                                        st->stream);
+            }
+        } else {
+            for (ReplicaHost& rh : st->rep) rh.lanes_per_cell = c;
+        }
+        capture_graph(st);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc) rc = check_hip(st, hipEventCreate(&e0));
+    if (!rc) rc = check_hip(st, hipEventCreate(&e1));
+    float best_ms = 0.f;
+    int best = cands.empty() ? 0 : cands[0];
+    for (size_t ci = 0; ci < cands.size() && !rc; ++ci) {
+        apply(cands[ci]);
+        rc = run_sweeps(st, 1, 0xA5A5u, 0x5A5Au);  // warm-up
+        if (!rc) rc = check_hip(st, hipEventRecord(e0, st->stream));
+        if (!rc) rc = run_sweeps(st, trial_sweeps, 0xA5A5u, 0x5A5Au);
+        if (!rc) rc = check_hip(st, hipEventRecord(e1, st->stream));
+        if (!rc) rc = check_hip(st, hipEventSynchronize(e1));
+        float ms = 0.f;
+        if (!rc) rc = check_hip(st, hipEventElapsedTime(&ms, e0, e1));
+        if (!rc && (ci == 0 || ms < best_ms)) {
+            best_ms = ms;
+            best = cands[ci];
+        }
+        // restore the snapshot after every trial
+        if (!rc)
+            rc = check_hip(st, hipMemcpyAsync(st->pos, st->ws.backup_pos, 8 * st->pos_total,
+                                              hipMemcpyDeviceToDevice, st->stream));
+        if (!rc && st->ori_total)
+            rc = check_hip(st, hipMemcpyAsync(st->orient, st->ws.backup_ori, 8 * st->ori_total,
+                                              hipMemcpyDeviceToDevice, st->stream));
+        if (!rc)
+            rc = check_hip(st, hipMemcpyAsync(st->ws.stats, st->ws.backup_stats, 8 * nstat,
+                                              hipMemcpyDeviceToDevice, st->stream));
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (!rc) apply(best);
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    if (!rc && out_config) *out_config = best;
+    return rc;
 }
 
 const char* hpmc_strerror(int code) {

@@ -102,7 +102,7 @@ __device__ __forceinline__ void load_orient(const double* __restrict__ ori, int 
 }
 
 // Full overlap test of a pair that passed the circumsphere test.
-template <int KIND, int PREC>
+template <int KIND, int PREC, int NV>
 __device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)[3],
                                           const double (&qi)[4], const double (&qk)[4],
                                           Counters& ct) {
@@ -111,11 +111,11 @@ __device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)
     } else if constexpr (KIND == kPolygon) {
         ct.pair_tests++;
         if constexpr (PREC == 1) {
-            const int d = polygon_overlap32(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
+            const int d = polygon_overlap32<NV>(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
             if (d != kUncertain) return d == kOverlap;
         }
         ct.pair_fp64++;
-        return polygon_overlap64(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
+        return polygon_overlap64<NV>(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
     } else {
         ct.pair_tests++;
         ct.pair_fp64++;
@@ -169,6 +169,40 @@ __device__ __forceinline__ uint32_t neighbour_cell(const int (&cc)[3], int j, in
     return (uint32_t)(x + n * (y + n * z));
 }
 
+// The 3^dim neighbour cells of cell cc, as member ranges of the cell-sorted
+// list: the three cells of a neighbour row (fixed y, z) are consecutive in
+// the linear cell index, so each row is one contiguous range -- except at the
+// periodic edge, where the wrapped cell is a second range.  Range ri:
+// row ri / 2 (dy = row % 3 - 1, dz = row / 3 - 1), segment ri % 2 (0: main,
+// 1: wrapped cell or empty).
+template <int D>
+struct Neighbourhood {
+    static constexpr int ranges = D == 3 ? 18 : 6;
+};
+
+template <int D, class CELLS>
+__device__ __forceinline__ void neighbour_range(const CELLS& cl, const int (&cc)[3], int n, int ri,
+                                                uint32_t& b, uint32_t& e) {
+    const int row = ri >> 1;
+    const int y = wrap_cell(cc[1] + (row % 3) - 1, n);
+    const int z = D == 3 ? wrap_cell(cc[2] + (row / 3) - 1, n) : 0;
+    const int base = n * (y + n * z);
+    int x0, x1;
+    if ((ri & 1) == 0) {
+        x0 = cc[0] > 0 ? cc[0] - 1 : 0;
+        x1 = cc[0] < n - 1 ? cc[0] + 1 : n - 1;
+    } else if (cc[0] == 0) {
+        x0 = x1 = n - 1;
+    } else if (cc[0] == n - 1) {
+        x0 = x1 = 0;
+    } else {
+        b = e = 0;
+        return;
+    }
+    b = cl.begin((uint32_t)(base + x0));
+    e = cl.end((uint32_t)(base + x1));
+}
+
 // Per-wave LDS scratch: a 128-entry ring of queued pair tests and one flag per
 // group (cell) of the tile.
 struct WaveScratch {
@@ -184,7 +218,7 @@ constexpr uint32_t kTagMask = (1u << 26) - 1u;
 // cell's trial state from the owner lane and runs the full test.  All lanes
 // must call (contains cross-lane shuffles).
 // ---------------------------------------------------------------------------
-template <int KIND, int PREC, int G, class POS>
+template <int KIND, int PREC, int G, int NV, class POS>
 __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                       const double* __restrict__ ori, const double (&xn)[3],
                                       const double (&qn)[4], uint32_t n, WaveScratch ws,
@@ -206,19 +240,18 @@ __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, cons
         for (int a = 0; a < D; ++a) r[a] = min_image(pos.get(a, k) - tx[a], S.L, S.inv_L);
         double qk[4];
         load_orient<KIND>(ori, S.N, k, qk);
-        if (full_test<KIND, PREC>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
+        if (full_test<KIND, PREC, NV>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
     }
     wave_sync();
 }
 
-template <int KIND, int PREC, int G, class POS, class CELLS>
+template <int KIND, int PREC, int G, int NV, class POS, class CELLS>
 __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                           double* __restrict__ ori, const CELLS& cl,
                                           uint32_t colour, uint32_t select, uint32_t t,
                                           uint32_t k0, uint32_t k1, const double (&sh)[3], int a0,
                                           int n_act, WaveScratch ws, Counters& ct) {
     constexpr int D = Traits<KIND>::dim;
-    constexpr int NB = Traits<KIND>::nbrs;
     const int lane = (int)__lane_id();
     const int grp = lane / G, sub = lane % G;
     const int leader = grp * G;
@@ -289,24 +322,24 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     }
     wave_sync();
 
-    // ---- 2 + 3. strided circumsphere scan, queued full tests
+    // ---- 2 + 3. strided circumsphere scan over neighbour ranges, queued full tests
+    constexpr int NR = Neighbourhood<D>::ranges;
     int j = sub;
     uint32_t p = 0, e = 0;
     if (live) {
-        for (; j < NB; j += G) {
-            const uint32_t cn = neighbour_cell<D>(cc, j, n);
-            p = cl.begin(cn);
-            e = cl.end(cn);
+        for (; j < NR; j += G) {
+            neighbour_range<D>(cl, cc, n, j, p, e);
             if (p != e) break;
         }
     }
-    bool work = live && j < NB;
+    bool work = live && j < NR;
+    bool flagged = false;  // this lane's cell already has an overlap (register copy)
     uint32_t queued = 0;  // wave-uniform
     for (;;) {
         bool hit = false;
         uint32_t k = 0;
         if (work) {
-            if (ws.flag[grp] != 0u) {
+            if (flagged) {
                 work = false;  // early exit: an overlap was already found
             } else {
                 k = cl.member(p);
@@ -319,19 +352,18 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                     hit = r2 < P.circ2;
                 }
                 if (++p == e) {
-                    for (j += G; j < NB; j += G) {
-                        const uint32_t cn = neighbour_cell<D>(cc, j, n);
-                        p = cl.begin(cn);
-                        e = cl.end(cn);
+                    for (j += G; j < NR; j += G) {
+                        neighbour_range<D>(cl, cc, n, j, p, e);
                         if (p != e) break;
                     }
-                    work = j < NB;
+                    work = j < NR;
                 }
             }
         }
         if constexpr (KIND == kDisk) {
             if (hit) ws.flag[grp] = 1u;  // the circumsphere test is the disk test
             wave_sync();
+            flagged = ws.flag[grp] != 0u;
         } else {
             const uint64_t hm = __ballot(hit);
             if (hit) {
@@ -340,9 +372,10 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
             }
             queued += (uint32_t)__popcll(hm);
             if (queued >= 64u) {
-                drain<KIND, PREC, G>(S, P, pos, ori, xn, qn, 64u, ws, ct);
+                drain<KIND, PREC, G, NV>(S, P, pos, ori, xn, qn, 64u, ws, ct);
                 queued -= 64u;
                 const uint32_t moved = (uint32_t)lane < queued ? ws.q[64 + lane] : 0u;
+                flagged = ws.flag[grp] != 0u;
                 wave_sync();
                 if ((uint32_t)lane < queued) ws.q[lane] = moved;
                 wave_sync();
@@ -351,7 +384,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         if (__ballot(work) == 0ull) break;
     }
     if constexpr (KIND != kDisk) {
-        if (queued) drain<KIND, PREC, G>(S, P, pos, ori, xn, qn, queued, ws, ct);
+        if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, xn, qn, queued, ws, ct);
     }
 
     // ---- 4. write back (counters updated arithmetically, not per branch)

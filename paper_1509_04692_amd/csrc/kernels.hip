@@ -59,18 +59,27 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, unsigned long lon
     if (i < n) p[i] = v;
 }
 
+__global__ void k_set_clock(Clock* __restrict__ clock, uint32_t t, uint32_t k0, uint32_t k1) {
+    if (threadIdx.x == 0) *clock = Clock{t, k0, k1, 0u};
+}
+
+__global__ void k_advance_clock(Clock* __restrict__ clock, uint32_t n) {
+    if (threadIdx.x == 0) clock->t += n;
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys, int r,
-                                                const double* __restrict__ pos_base, uint32_t t,
-                                                uint32_t k0, uint32_t k1, int shifted,
+                                                const double* __restrict__ pos_base,
+                                                const Clock* __restrict__ clock, int shifted,
                                                 uint32_t* __restrict__ count,
                                                 uint32_t* __restrict__ cell_of,
                                                 uint32_t* __restrict__ slot_of) {
     const SysDev S = sys[r];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N) return;
+    const Clock ck = *clock;
     double sh[3];
-    grid_shift(S, t, k0, k1, shifted, sh);
+    grid_shift(S, ck.t, ck.k0, ck.k1, shifted, sh);
     const uint32_t c = particle_cell<D>(S, PosView{const_cast<double*>(pos_base) + S.pos_off, S.N}, (uint32_t)i, sh);
     cell_of[i] = c;
     slot_of[i] = atomicAdd(count + c, 1u);
@@ -176,15 +185,15 @@ __global__ void __launch_bounds__(256) k_sort_cells(const uint32_t* __restrict__
 
 // One colour pass of the grid path: one wave per tile of 64/G active cells,
 // four waves per work-group.
-template <int KIND, int PREC, int G>
+template <int KIND, int PREC, int G, int NV>
 __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                                 const SpeciesDev* __restrict__ spc, int r,
                                                 double* __restrict__ pos_base,
                                                 double* __restrict__ ori_base,
                                                 const uint32_t* __restrict__ start,
                                                 const uint32_t* __restrict__ members,
-                                                uint32_t colour, uint32_t select, uint32_t t,
-                                                uint32_t k0, uint32_t k1,
+                                                uint32_t colour, uint32_t select,
+                                                const Clock* __restrict__ clock,
                                                 unsigned long long* __restrict__ stats) {
     constexpr int D = Traits<KIND>::dim;
     __shared__ uint32_t qbuf[4][kQueueWords];
@@ -197,11 +206,13 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
     const int wave = threadIdx.x >> 6;
     const int a0 = (blockIdx.x * 4 + wave) * (64 / G);
     if (a0 < n_act) {
+        const Clock ck = *clock;
+        const uint32_t t = ck.t, k0 = ck.k0, k1 = ck.k1;
         double sh[3];
         grid_shift(S, t, k0, k1, 1, sh);
         const PosView pos{pos_base + S.pos_off, S.N};
         const GlobalCells cl{start, members};
-        pass_tile<KIND, PREC, G>(S, P, pos, ori_base + S.orient_off, cl, colour, select, t, k0, k1,
+        pass_tile<KIND, PREC, G, NV>(S, P, pos, ori_base + S.orient_off, cl, colour, select, t, k0, k1,
                                  sh, a0, n_act, WaveScratch{qbuf[wave], fbuf[wave]}, ct);
     }
     flush(ct, stats + (size_t)r * kNumStats);
@@ -251,7 +262,7 @@ __global__ void __launch_bounds__(256) k_count(const SysDev* __restrict__ sys,
                         if (!(r2 < P.circ2)) continue;
                         double qk[4];
                         load_orient<KIND>(ori, N, k, qk);
-                        found += full_test<KIND, 0>(P, rr, qi, qk, dummy) ? 1u : 0u;
+                        found += full_test<KIND, 0, 0>(P, rr, qi, qk, dummy) ? 1u : 0u;
                     }
                 }
     }
@@ -275,11 +286,15 @@ struct BatchLds {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t batch_lds_bytes(int dim, int N, int ncells, int nwaves,
-                                                  bool resident, size_t* off) {
+// Residency level: 0 = particle data in global memory, 1 = positions in LDS,
+// 2 = positions and orientations in LDS.
+__host__ __device__ inline size_t batch_lds_bytes(int dim, int ncomp, int N, int ncells,
+                                                  int nwaves, int res, size_t* off) {
     size_t o = 0;
     off[0] = o;
-    o += resident ? align16((size_t)dim * N * 8) : 0;
+    o += res >= 1 ? align16((size_t)dim * N * 8) : 0;
+    off[5] = o;
+    o += res >= 2 ? align16((size_t)ncomp * N * 8) : 0;
     off[1] = o;
     o += align16((size_t)N * 2);
     off[2] = o;
@@ -294,15 +309,15 @@ __host__ __device__ inline size_t batch_lds_bytes(int dim, int N, int ncells, in
     return o;
 }
 
-template <int KIND, int PREC, bool RESIDENT>
+template <int KIND, int PREC, int RES, int NV>
 __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict__ sys,
                                                        const SpeciesDev* __restrict__ spc,
                                                        const int32_t* __restrict__ list,
                                                        double* __restrict__ pos_base,
                                                        double* __restrict__ ori_base,
                                                        unsigned long long* __restrict__ stats,
-                                                       uint32_t t0, uint32_t n_sweeps, uint32_t k0,
-                                                       uint32_t k1) {
+                                                       const Clock* __restrict__ clock,
+                                                       uint32_t n_sweeps) {
     constexpr int D = Traits<KIND>::dim;
     extern __shared__ __align__(16) unsigned char lds[];
     const int r = list[blockIdx.x];
@@ -310,20 +325,27 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     const SpeciesDev& P = spc[S.species];
     const int tid = threadIdx.x, B = blockDim.x, nwaves = B >> 6, wave = tid >> 6;
     const int N = S.N, nc = S.ncells;
-    size_t off[5];
-    batch_lds_bytes(D, N, nc, nwaves, RESIDENT, off);
+    constexpr int NC = Traits<KIND>::ncomp;
+    size_t off[6];
+    batch_lds_bytes(D, NC, N, nc, nwaves, RES, off);
     double* gpos = pos_base + S.pos_off;
-    double* ori = ori_base + S.orient_off;
-    const PosView pos{RESIDENT ? reinterpret_cast<double*>(lds + off[0]) : gpos, N};
+    double* gori = ori_base + S.orient_off;
+    const PosView pos{RES >= 1 ? reinterpret_cast<double*>(lds + off[0]) : gpos, N};
+    double* ori = RES >= 2 ? reinterpret_cast<double*>(lds + off[5]) : gori;
     uint16_t* mem = reinterpret_cast<uint16_t*>(lds + off[1]);
     uint16_t* ends = reinterpret_cast<uint16_t*>(lds + off[2]);
     uint32_t* uni = reinterpret_cast<uint32_t*>(lds + off[3]);
     uint32_t* sm = reinterpret_cast<uint32_t*>(lds + off[4]);
-    if constexpr (RESIDENT) {
+    if constexpr (RES >= 1) {
         for (int k = tid; k < D * N; k += B) pos.p[k] = gpos[k];
+    }
+    if constexpr (RES >= 2) {
+        for (int k = tid; k < NC * N; k += B) ori[k] = gori[k];
     }
     __syncthreads();
     Counters ct = {};
+    const Clock ck = *clock;
+    const uint32_t t0 = ck.t, k0 = ck.k0, k1 = ck.k1;
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
     const int chunk = (nc + B - 1) / B;
@@ -375,14 +397,18 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
                 for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64)
-                    pass_tile<KIND, PREC, 1>(S, P, pos, ori, cl, colour, select, t, k0, k1, sh, a0,
-                                             n_act, wscr, ct);
+                    pass_tile<KIND, PREC, 1, NV>(S, P, pos, ori, cl, colour, select, t, k0, k1, sh,
+                                                 a0, n_act, wscr, ct);
                 __syncthreads();
             }
         }
     }
-    if constexpr (RESIDENT) {
+    __syncthreads();
+    if constexpr (RES >= 1) {
         for (int k = tid; k < D * N; k += B) gpos[k] = pos.p[k];
+    }
+    if constexpr (RES >= 2) {
+        for (int k = tid; k < NC * N; k += B) gori[k] = ori[k];
     }
     flush(ct, stats + (size_t)r * kNumStats);
 }
@@ -392,9 +418,9 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
-size_t persistent_lds_bytes(int dim, int ncells, int N, bool resident) {
-    size_t off[5];
-    return batch_lds_bytes(dim, N, ncells, kBatchBlock / 64, resident, off);
+size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res) {
+    size_t off[6];
+    return batch_lds_bytes(dim, ncomp, N, ncells, kBatchBlock / 64, res, off);
 }
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream) {
@@ -403,16 +429,26 @@ hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipSt
     return hipGetLastError();
 }
 
+hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, hipStream_t stream) {
+    k_set_clock<<<1, 64, 0, stream>>>(ws.clock, t, k0, k1);
+    return hipGetLastError();
+}
+
+hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream) {
+    k_advance_clock<<<1, 64, 0, stream>>>(ws.clock, n);
+    return hipGetLastError();
+}
+
 hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
-                       uint32_t t, uint32_t k0, uint32_t k1, int shifted, hipStream_t stream) {
+                       int shifted, hipStream_t stream) {
     const int nc = rh.ncells, N = rh.N;
     const int ntiles = blocks_for(nc, kScanTile);
     k_fill_u32<<<blocks_for(nc, 256), 256, 0, stream>>>(ws.count, 0u, nc);
     if (rh.dim == 3)
-        k_assign<3><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, t, k0, k1, shifted,
+        k_assign<3><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock, shifted,
                                                              ws.count, ws.cell_of, ws.slot_of);
     else
-        k_assign<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, t, k0, k1, shifted,
+        k_assign<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock, shifted,
                                                              ws.count, ws.cell_of, ws.slot_of);
     k_scan_tiles<<<ntiles, 256, 0, stream>>>(ws.count, nc, ws.partial);
     k_scan_partials<<<1, 256, 0, stream>>>(ws.partial, ntiles);
@@ -423,75 +459,94 @@ hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const 
     return hipGetLastError();
 }
 
-template <int KIND, int PREC, int G>
+template <int KIND, int PREC, int G, int NV>
 static void launch_passes_g(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                            double* orient, uint32_t t, uint32_t k0, uint32_t k1,
-                            hipStream_t stream) {
+                            double* orient, hipStream_t stream) {
     const int half = rh.n / 2;
     const long n_act = rh.dim == 3 ? (long)half * half * half : (long)half * half;
     const int cells_per_block = 4 * (64 / G);
     const uint32_t ncol = 1u << rh.dim;
     for (int rnd = 0; rnd < rh.rounds; ++rnd)
         for (uint32_t colour = 0; colour < ncol; ++colour)
-            k_update<KIND, PREC, G><<<blocks_for(n_act, cells_per_block), 256, 0, stream>>>(
+            k_update<KIND, PREC, G, NV><<<blocks_for(n_act, cells_per_block), 256, 0, stream>>>(
                 ws.sys, ws.species, r, pos, orient, ws.start, ws.members, colour,
-                (uint32_t)rnd * ncol + colour, t, k0, k1, ws.stats);
+                (uint32_t)rnd * ncol + colour, ws.clock, ws.stats);
+}
+
+template <int KIND, int PREC, int NV>
+static void launch_passes_nv(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
+                             double* orient, hipStream_t stream) {
+    switch (rh.lanes_per_cell) {
+        case 8: launch_passes_g<KIND, PREC, 8, NV>(ws, rh, r, pos, orient, stream); break;
+        case 4: launch_passes_g<KIND, PREC, 4, NV>(ws, rh, r, pos, orient, stream); break;
+        case 2: launch_passes_g<KIND, PREC, 2, NV>(ws, rh, r, pos, orient, stream); break;
+        default: launch_passes_g<KIND, PREC, 1, NV>(ws, rh, r, pos, orient, stream); break;
+    }
 }
 
 template <int KIND, int PREC>
 static void launch_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                          double* orient, uint32_t t, uint32_t k0, uint32_t k1,
-                          hipStream_t stream) {
-    switch (rh.lanes_per_cell) {
-        case 8: launch_passes_g<KIND, PREC, 8>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
-        case 4: launch_passes_g<KIND, PREC, 4>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
-        case 2: launch_passes_g<KIND, PREC, 2>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
-        default: launch_passes_g<KIND, PREC, 1>(ws, rh, r, pos, orient, t, k0, k1, stream); break;
-    }
+                          double* orient, hipStream_t stream) {
+    if (KIND == kPolygon && rh.nv == 5)
+        launch_passes_nv<KIND, PREC, 5>(ws, rh, r, pos, orient, stream);
+    else
+        launch_passes_nv<KIND, PREC, 0>(ws, rh, r, pos, orient, stream);
 }
 
 hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                       double* orient, int precision, uint32_t t, uint32_t k0, uint32_t k1,
-                       hipStream_t stream) {
+                       double* orient, int precision, hipStream_t stream) {
     if (rh.kind == kDisk)
-        launch_passes<kDisk, 0>(ws, rh, r, pos, orient, t, k0, k1, stream);
+        launch_passes<kDisk, 0>(ws, rh, r, pos, orient, stream);
     else if (rh.kind == kPolygon && precision == 1)
-        launch_passes<kPolygon, 1>(ws, rh, r, pos, orient, t, k0, k1, stream);
+        launch_passes<kPolygon, 1>(ws, rh, r, pos, orient, stream);
     else if (rh.kind == kPolygon)
-        launch_passes<kPolygon, 0>(ws, rh, r, pos, orient, t, k0, k1, stream);
+        launch_passes<kPolygon, 0>(ws, rh, r, pos, orient, stream);
     else
-        launch_passes<kPolyhedron, 0>(ws, rh, r, pos, orient, t, k0, k1, stream);
+        launch_passes<kPolyhedron, 0>(ws, rh, r, pos, orient, stream);
     return hipGetLastError();
 }
 
-template <int KIND, int PREC, bool RESIDENT>
+template <int KIND, int PREC, int RES, int NV>
 static hipError_t launch_batch(const Workspace& ws, const int32_t* list, int n, size_t lds,
-                               double* pos, double* orient, uint32_t t0, uint32_t n_sweeps,
-                               uint32_t k0, uint32_t k1, hipStream_t stream) {
-    auto kern = k_batch<KIND, PREC, RESIDENT>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    kern<<<n, kBatchBlock, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats, t0,
-                                          n_sweeps, k0, k1);
+                               double* pos, double* orient, uint32_t n_sweeps, bool prepare,
+                               hipStream_t stream) {
+    auto kern = k_batch<KIND, PREC, RES, NV>;
+    if (prepare)  // raise the dynamic-LDS limit (not a stream operation; done before capture)
+        return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds);
+    kern<<<n, kBatchBlock, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats,
+                                          ws.clock, n_sweeps);
     return hipGetLastError();
+}
+
+template <int KIND, int PREC, int NV>
+static hipError_t launch_batch_res(const Workspace& ws, const BatchGroup& g, double* pos,
+                                   double* orient, uint32_t n_sweeps, bool prepare,
+                                   hipStream_t stream) {
+    const int32_t* list = ws.batch_list + g.first;
+    if (g.resident >= 2 && KIND != kDisk)
+        return launch_batch<KIND, PREC, 2, NV>(ws, list, g.count, g.lds_bytes, pos, orient,
+                                               n_sweeps, prepare, stream);
+    if (g.resident >= 1)
+        return launch_batch<KIND, PREC, 1, NV>(ws, list, g.count, g.lds_bytes, pos, orient,
+                                               n_sweeps, prepare, stream);
+    return launch_batch<KIND, PREC, 0, NV>(ws, list, g.count, g.lds_bytes, pos, orient,
+                                           n_sweeps, prepare, stream);
 }
 
 hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* pos,
-                             double* orient, int precision, uint32_t t0, uint32_t n_sweeps,
-                             uint32_t k0, uint32_t k1, hipStream_t stream) {
-    const int32_t* list = ws.batch_list + g.first;
-    const bool res = g.resident != 0;
-#define HPMC_LAUNCH(K, PR)                                                                     \
-    return res ? launch_batch<K, PR, true>(ws, list, g.count, g.lds_bytes, pos, orient, t0,    \
-                                           n_sweeps, k0, k1, stream)                            \
-               : launch_batch<K, PR, false>(ws, list, g.count, g.lds_bytes, pos, orient, t0,   \
-                                            n_sweeps, k0, k1, stream)
-    if (g.kind == kDisk) HPMC_LAUNCH(kDisk, 0);
-    if (g.kind == kPolygon && precision == 1) HPMC_LAUNCH(kPolygon, 1);
-    if (g.kind == kPolygon) HPMC_LAUNCH(kPolygon, 0);
-    HPMC_LAUNCH(kPolyhedron, 0);
-#undef HPMC_LAUNCH
+                             double* orient, int precision, uint32_t n_sweeps, bool prepare,
+                             hipStream_t stream) {
+    if (g.kind == kDisk)
+        return launch_batch_res<kDisk, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+    if (g.kind == kPolygon) {
+        if (precision == 1)
+            return g.nv == 5 ? launch_batch_res<kPolygon, 1, 5>(ws, g, pos, orient, n_sweeps, prepare, stream)
+                             : launch_batch_res<kPolygon, 1, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+        return g.nv == 5 ? launch_batch_res<kPolygon, 0, 5>(ws, g, pos, orient, n_sweeps, prepare, stream)
+                         : launch_batch_res<kPolygon, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+    }
+    return launch_batch_res<kPolyhedron, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
 }
 
 hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,

@@ -24,18 +24,26 @@ struct Workspace {
     uint32_t* members;  // N
     uint32_t* partial;  // scan tiles
     int32_t* batch_list;  // replica indices of the persistent path, grouped by kind
+    Clock* clock;         // sweep counter and key read by the kernels
+    double* backup_pos;   // autotuning snapshot of the caller's arrays
+    double* backup_ori;
+    unsigned long long* backup_stats;
 };
 
 struct ReplicaHost {
     int32_t kind, dim, N, n, ncells, rounds, path;
     int32_t lanes_per_cell;  // grid path: lanes per active cell (1, 2, 4, 8)
+    int32_t nv;              // polygon vertex count (compile-time fast path for 5)
     int64_t pos_off, orient_off;
 };
 
 // Replicas of one shape kind launched together on the persistent path.
 struct BatchGroup {
-    int32_t kind, first, count, resident;
+    int32_t kind, first, count;
+    int32_t resident;  // 0 none, 1 positions, 2 positions + orientations in LDS
+    int32_t nv;        // common polygon vertex count, 0 when mixed or not a polygon
     size_t lds_bytes;
+    size_t need[3];    // dynamic LDS per residency level
 };
 
 constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
@@ -43,18 +51,23 @@ constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
 // Cell list of replica r in global memory: shifted grid of sweep t when
 // shifted != 0, the unshifted grid otherwise.
 hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
-                       uint32_t t, uint32_t k0, uint32_t k1, int shifted, hipStream_t stream);
+                       int shifted, hipStream_t stream);
+
+// Device clock: set {t, key}; advance t by n.
+hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, hipStream_t stream);
+hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream);
 
 // All colour passes of sweep t for replica r on the global cell list.
 hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                       double* orient, int precision, uint32_t t, uint32_t k0, uint32_t k1,
-                       hipStream_t stream);
+                       double* orient, int precision, hipStream_t stream);
 
 // n_sweeps whole sweeps of the replicas of one batch group, one work-group
 // each.
+// prepare = true only raises the kernel's dynamic-LDS limit (call before
+// launching or capturing).
 hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* pos,
-                             double* orient, int precision, uint32_t t0, uint32_t n_sweeps,
-                             uint32_t k0, uint32_t k1, hipStream_t stream);
+                             double* orient, int precision, uint32_t n_sweeps, bool prepare,
+                             hipStream_t stream);
 
 // Overlapping pairs of replica r (after build_cells with shifted = 0), added
 // to ws.overlap_out[r].
@@ -69,6 +82,6 @@ hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, con
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream);
 
 // Dynamic LDS of a persistent work-group (positions resident or not).
-size_t persistent_lds_bytes(int dim, int ncells, int N, bool resident);
+size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res);
 
 }  // namespace hpmc

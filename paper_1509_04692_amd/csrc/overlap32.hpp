@@ -22,9 +22,12 @@ namespace hpmc {
 
 enum : int { kNoOverlap = 0, kOverlap = 1, kUncertain = 2 };
 
+template <int NV>
 __device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd,
                                                  double cAd, double sAd, double cBd, double sBd) {
-    const int nv = P.nv;
+    // NV > 0: vertex count known at compile time; NV == 0: P.nv at run time
+    constexpr int MV = NV > 0 ? NV : kMaxPolyVerts;
+    const int nv = NV > 0 ? NV : P.nv;
     const float M = P.sat_margin_scale;
     const float rx = (float)rxd, ry = (float)ryd;
     const float cA = (float)cAd, sA = (float)sAd, cB = (float)cBd, sB = (float)sBd;
@@ -34,22 +37,22 @@ __device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd
     const float ty = fmaf(cA, ry, -(sA * rx));
 
     bool unsure = false;
-    float px[kMaxPolyVerts], py[kMaxPolyVerts];
+    float px[MV], py[MV];
 #pragma unroll
-    for (int j = 0; j < kMaxPolyVerts; ++j) {
+    for (int j = 0; j < MV; ++j) {
         if (j < nv) {
             px[j] = fmaf(zc, P.vx32[j], fmaf(-zs, P.vy32[j], tx));
             py[j] = fmaf(zs, P.vx32[j], fmaf(zc, P.vy32[j], ty));
         }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPolyVerts; ++k) {
+    for (int k = 0; k < MV; ++k) {
         if (k < nv) {
             const float nx = P.nx32[k], ny = P.ny32[k];
             float lo = fmaf(nx, px[0], ny * py[0]);
             float hi = lo;
 #pragma unroll
-            for (int j = 1; j < kMaxPolyVerts; ++j) {
+            for (int j = 1; j < MV; ++j) {
                 if (j < nv) {
                     const float p = fmaf(nx, px[j], ny * py[j]);
                     lo = fminf(lo, p);
@@ -62,7 +65,7 @@ __device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd
         }
     }
 #pragma unroll
-    for (int j = 0; j < kMaxPolyVerts; ++j) {
+    for (int j = 0; j < MV; ++j) {
         if (j < nv) {
             const float ux = P.vx32[j] - tx;
             const float uy = P.vy32[j] - ty;
@@ -71,13 +74,13 @@ __device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd
         }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPolyVerts; ++k) {
+    for (int k = 0; k < MV; ++k) {
         if (k < nv) {
             const float nx = P.nx32[k], ny = P.ny32[k];
             float lo = fmaf(nx, px[0], ny * py[0]);
             float hi = lo;
 #pragma unroll
-            for (int j = 1; j < kMaxPolyVerts; ++j) {
+            for (int j = 1; j < MV; ++j) {
                 if (j < nv) {
                     const float p = fmaf(nx, px[j], ny * py[j]);
                     lo = fminf(lo, p);

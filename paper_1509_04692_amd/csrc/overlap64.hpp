@@ -16,30 +16,33 @@ namespace hpmc {
 // their own normals are per-shape constants.  An axis separates when the
 // projection intervals are disjoint or touch.
 // ---------------------------------------------------------------------------
+template <int NV>
 __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx, double ry,
                                                   double cA, double sA, double cB, double sB) {
-    const int nv = P.nv;
+    // NV > 0: vertex count known at compile time; NV == 0: P.nv at run time
+    constexpr int MV = NV > 0 ? NV : kMaxPolyVerts;
+    const int nv = NV > 0 ? NV : P.nv;
     const double zc = cA * cB + sA * sB;
     const double zs = cA * sB - sA * cB;
     const double tx = cA * rx + sA * ry;
     const double ty = cA * ry - sA * rx;
 
-    double px[kMaxPolyVerts], py[kMaxPolyVerts];
+    double px[MV], py[MV];
 #pragma unroll
-    for (int j = 0; j < kMaxPolyVerts; ++j) {
+    for (int j = 0; j < MV; ++j) {
         if (j < nv) {
             px[j] = (zc * P.vx[j] - zs * P.vy[j]) + tx;
             py[j] = (zs * P.vx[j] + zc * P.vy[j]) + ty;
         }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPolyVerts; ++k) {
+    for (int k = 0; k < MV; ++k) {
         if (k < nv) {
             const double nx = P.nx[k], ny = P.ny[k];
             double lo = nx * px[0] + ny * py[0];
             double hi = lo;
 #pragma unroll
-            for (int j = 1; j < kMaxPolyVerts; ++j) {
+            for (int j = 1; j < MV; ++j) {
                 if (j < nv) {
                     const double p = nx * px[j] + ny * py[j];
                     lo = fmin(lo, p);
@@ -50,7 +53,7 @@ __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx
         }
     }
 #pragma unroll
-    for (int j = 0; j < kMaxPolyVerts; ++j) {
+    for (int j = 0; j < MV; ++j) {
         if (j < nv) {
             const double ux = P.vx[j] - tx;
             const double uy = P.vy[j] - ty;
@@ -59,13 +62,13 @@ __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx
         }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxPolyVerts; ++k) {
+    for (int k = 0; k < MV; ++k) {
         if (k < nv) {
             const double nx = P.nx[k], ny = P.ny[k];
             double lo = nx * px[0] + ny * py[0];
             double hi = lo;
 #pragma unroll
-            for (int j = 1; j < kMaxPolyVerts; ++j) {
+            for (int j = 1; j < MV; ++j) {
                 if (j < nv) {
                     const double p = nx * px[j] + ny * py[j];
                     lo = fmin(lo, p);

@@ -34,6 +34,13 @@ struct alignas(16) SpeciesDev {
     float pad1[3];
 };
 
+// Sweep counter and Philox key, read by the kernels from device memory so that
+// a captured sweep can be replayed: set once per hpmc_sweep call, advanced by
+// a kernel at the end of every sweep (or persistent chunk).
+struct alignas(16) Clock {
+    uint32_t t, k0, k1, pad;
+};
+
 // One replica (independent system) and its grid.
 struct alignas(16) SysDev {
     double L, inv_L, w, inv_w;

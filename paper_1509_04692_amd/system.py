@@ -29,7 +29,7 @@ def _as_list(x, n):
 
 class System:
     def __init__(self, species, N, L, pos, orient=None, precision="fp64", path="auto",
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, graphs=True):
         import torch
 
         self._torch = torch
@@ -106,6 +106,7 @@ class System:
         args.pos = self.pos.data_ptr()
         args.orient = self.orient.data_ptr()
         args.stream = stream.cuda_stream
+        args.flags = 0 if graphs else _lib.FLAG_NO_GRAPH
         nbytes = ctypes.c_size_t()
         self._check(self._lib.hpmc_workspace_bytes(ctypes.byref(args), ctypes.byref(nbytes)),
                     "hpmc_workspace_bytes")
@@ -128,6 +129,19 @@ class System:
 
     def sweep(self, n_sweeps, seed):
         self._check(self._lib.hpmc_sweep(self._handle, int(n_sweeps), int(seed)), "hpmc_sweep")
+
+    def autotune(self, trial_sweeps=8):
+        """Time the launch configurations, keep the fastest; the state is
+        restored exactly.  Returns the chosen lanes per cell (grid path) or
+        LDS residency level (persistent path)."""
+        cfg = ctypes.c_int32()
+        self._check(self._lib.hpmc_autotune(self._handle, int(trial_sweeps), ctypes.byref(cfg)),
+                    "hpmc_autotune")
+        return cfg.value
+
+    @property
+    def uses_graph(self):
+        return bool(self._lib.hpmc_uses_graph(self._handle))
 
     def count_overlaps(self):
         out = (ctypes.c_uint64 * self.n_replicas)()

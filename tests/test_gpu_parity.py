@@ -143,6 +143,32 @@ def test_resume_equals_one_long_run(path):
     assert np.array_equal(a.positions(), c.positions())
 
 
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_graph_replay_direct_launch_and_autotune_agree(path):
+    """The captured hipGraph, direct launches and every autotuned configuration
+    give the same trajectory bit for bit; autotuning restores the state."""
+    sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.60)
+    announce(f"graph vs direct vs autotune {path}")
+    g = _system(sp, N, L, pos, orient, precision="mixed", path=path)
+    d = _system(sp, N, L, pos, orient, precision="mixed", path=path, graphs=False)
+    assert g.uses_graph and not d.uses_graph
+    g.sweep(70, seed=9)  # 70 = one 64-sweep persistent chunk + a remainder
+    d.sweep(70, seed=9)
+    assert np.array_equal(g.positions(), d.positions())
+    assert np.array_equal(g.orientations(), d.orientations())
+    before = (g.positions().copy(), g.orientations().copy(), g.stats(), g.sweep_counter)
+    cfg = g.autotune(trial_sweeps=4)
+    assert cfg in ((0, 1, 2) if path == "persistent" else (1, 2, 4, 8))
+    assert np.array_equal(g.positions(), before[0]) and np.array_equal(g.orientations(), before[1])
+    assert g.stats() == before[2] and g.sweep_counter == before[3]
+    g.sweep(30, seed=9)
+    d.sweep(30, seed=9)
+    assert np.array_equal(g.positions(), d.positions())
+    ref_pos, ref_ori = pos.copy(), orient.copy()
+    oracle.sweep(sp, L, ref_pos, ref_ori, seed=9, n_sweeps=100)
+    assert np.array_equal(g.positions(), ref_pos) and np.array_equal(g.orientations(), ref_ori)
+
+
 @pytest.mark.parametrize("kind", ["disk", "pentagon", "cube"])
 def test_count_overlaps_matches_oracle_on_overlapping_states(kind):
     """Random (overlapping) states cannot be initialised, so the count is
