@@ -93,7 +93,7 @@ typedef struct {
 typedef struct {
     int32_t n_replicas;            /* >= 1 independent systems */
     const hpmc_species *species;   /* host, n_replicas entries */
-    const int32_t *N;              /* host, particles per replica (>= 1) */
+    const int32_t *N;              /* host, particles per replica (1 .. 2^26 - 1) */
     const double *L;               /* host, periodic box side per replica */
     int32_t precision;             /* hpmc_precision */
     int32_t path;                  /* hpmc_path */

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "mpr32.hpp"
 #include "types.hpp"
 
 using namespace hpmc;
@@ -127,10 +128,31 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
     P.circ2 = dmax * dmax;
     const double tol = 1e-12 * dmax;
     P.tol2 = tol * tol;
+    if (s.shape == HPMC_POLYHEDRON) fill_mpr32_tables(P, tol);
     P.d = s.d;
     P.a = s.a;
     P.p_rot = s.p_rot;
     return HPMC_OK;
+}
+
+// Threshold of the binary32 circumsphere pre-filter.  The scan compares
+// |r32|^2 with it, where each component of r32 is a binary32 grid coordinate
+// (|y| <= L, cast from binary64) minus a binary32 reference point
+// (|ref| <= L + w).  Per axis r32 is within
+//   e = u32 (2L + 3w) + u64 (2L + 3w)
+// of the exact separation (two casts, one subtraction of a result below 2w +
+// 2R, and the binary64 roundings of the grid coordinates and of the min-image
+// separation), so a pair with binary64 |r|^2 < circ2 has |r| < sqrt(circ2)
+// (1 + 2 u64) and |r32| < that + sqrt(dim) e; three binary32 roundings of the
+// square sum add a factor (1 + u32)^3.  The bound is doubled and rounded up.
+float scan_threshold(double circ2, double L, double w, int dim) {
+    const double u32 = 0x1p-24, u64 = 0x1p-53;
+    const double e = 2.0 * (u32 + u64) * (2.0 * L + 3.0 * w);
+    const double rho = std::sqrt(circ2) * (1.0 + 4.0 * u64) + std::sqrt((double)dim) * e;
+    const double t = rho * rho * (1.0 + 8.0 * u32);
+    float f = (float)t;
+    if ((double)f < t) f = std::nextafter(f, INFINITY);
+    return f;
 }
 
 // Grid of Sec. 2.2.1 with the checkerboard constraint: the largest even n
@@ -138,6 +160,7 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
 int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, SysDev& S,
                ReplicaHost& rh) {
     if (!(L > 0.0) || !std::isfinite(L) || N < 1) return HPMC_ERR_INVALID_ARG;
+    if (N >= (1 << 26)) return HPMC_ERR_UNSUPPORTED;  // queue entries hold 26-bit slots
     const double dmax = P.R + P.R;
     const double nf = L / (dmax * (1.0 + 0x1p-30));
     if (nf > 65536.0) return HPMC_ERR_UNSUPPORTED;
@@ -164,6 +187,7 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
         S.rounds = r < 1 ? 1 : (int32_t)r;
     }
     if ((int64_t)S.rounds * (1 << s.dim) >= ((int64_t)1 << 28)) return HPMC_ERR_INVALID_ARG;
+    S.scan_t2 = scan_threshold(P.circ2, L, S.w, s.dim);
     rh.kind = s.shape;
     rh.dim = s.dim;
     rh.N = N;
@@ -174,7 +198,7 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
 }
 
 struct Layout {
-    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, partial, list,
+    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, xs, partial, list,
         clock, backup_pos, backup_ori, backup_stats, total;
     size_t pos_total, ori_total;
 };
@@ -201,7 +225,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     sys.assign(R, SysDev{});
     spc.assign(R, SpeciesDev{});
     int64_t pos_off = 0, ori_off = 0;
-    int64_t nc_max = 1, n_max = 1;
+    int64_t nc_max = 1, n_max = 1, xs_max = 16;
     bool fits_lds = true;
     for (int r = 0; r < R; ++r) {
         int rc = build_species(a->species[r], spc[r]);
@@ -219,6 +243,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         ori_off += (int64_t)ncomp * sys[r].N;
         nc_max = std::max<int64_t>(nc_max, sys[r].ncells);
         n_max = std::max<int64_t>(n_max, sys[r].N);
+        xs_max = std::max<int64_t>(xs_max, (int64_t)sys[r].N * xs_bytes(sys[r].dim));
         const int ncomp_r = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
         const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, sys[r].ncells, sys[r].N, 0);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
@@ -283,6 +308,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.cell_of = take(4 * (size_t)n_max);
     lay.slot_of = take(4 * (size_t)n_max);
     lay.members = take(4 * (size_t)n_max);
+    lay.xs = take((size_t)xs_max);
     lay.partial = take(4 * (size_t)ntiles);
     lay.list = take(4 * (size_t)R);
     lay.clock = take(sizeof(Clock));
@@ -444,6 +470,7 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->ws.cell_of = (uint32_t*)(base + lay.cell_of);
     st->ws.slot_of = (uint32_t*)(base + lay.slot_of);
     st->ws.members = (uint32_t*)(base + lay.members);
+    st->ws.xs = (float*)(base + lay.xs);
     st->ws.partial = (uint32_t*)(base + lay.partial);
     st->ws.batch_list = (int32_t*)(base + lay.list);
     st->ws.clock = (Clock*)(base + lay.clock);

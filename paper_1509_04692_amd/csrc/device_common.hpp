@@ -81,16 +81,23 @@ __device__ __forceinline__ void small_angle_sincos(double delta, double& c, doub
 }
 
 // ---------------------------------------------------------------------------
-// Grid geometry (Sec. 2.2.1): cell coordinate along one axis of the grid
-// shifted by s in (0, w); periodic wrap of a coordinate displaced by less
-// than L; minimum image of a separation.
+// Grid geometry (Sec. 2.2.1): coordinate in the frame of the grid shifted by
+// s in (0, w) and the cell it falls in; periodic wrap of a coordinate
+// displaced by less than L; minimum image of a separation.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int cell_coord(double x, double s, double L, double inv_w, int n) {
-    double y = x - s;
-    if (y < 0.0) y = y + L;
+__device__ __forceinline__ double grid_coord(double x, double s, double L) {
+    const double y = x - s;
+    return y < 0.0 ? y + L : y;
+}
+
+__device__ __forceinline__ int cell_of_coord(double y, double inv_w, int n) {
     int j = (int)(y * inv_w);
     j = j > n - 1 ? n - 1 : j;
     return j < 0 ? 0 : j;  // only reachable for positions outside [0, L)
+}
+
+__device__ __forceinline__ int cell_coord(double x, double s, double L, double inv_w, int n) {
+    return cell_of_coord(grid_coord(x, s, L), inv_w, n);
 }
 
 __device__ __forceinline__ double wrap_periodic(double x, double L) {
@@ -112,7 +119,7 @@ __device__ __forceinline__ double min_image(double r, double L, double inv_L) {
 // ---------------------------------------------------------------------------
 struct Quat { double w, x, y, z; };
 
-__device__ __forceinline__ Quat qmul(const Quat& p, const Quat& q) {
+__host__ __device__ inline Quat qmul(const Quat& p, const Quat& q) {
     Quat o;
     o.w = ((p.w * q.w - p.x * q.x) - p.y * q.y) - p.z * q.z;
     o.x = ((p.w * q.x + p.x * q.w) + p.y * q.z) - p.z * q.y;
@@ -123,7 +130,7 @@ __device__ __forceinline__ Quat qmul(const Quat& p, const Quat& q) {
 
 struct Mat3 { double m[3][3]; };
 
-__device__ __forceinline__ Mat3 rotation_matrix(const Quat& q) {
+__host__ __device__ inline Mat3 rotation_matrix(const Quat& q) {
     Mat3 r;
     r.m[0][0] = 1.0 - 2.0 * (q.y * q.y + q.z * q.z);
     r.m[0][1] = 2.0 * (q.x * q.y - q.w * q.z);

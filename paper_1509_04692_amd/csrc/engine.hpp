@@ -6,11 +6,13 @@
 //      its cell (uniform occupant, Philox stream, translation or rotation,
 //      reject when it leaves the cell) and broadcasts it to its group;
 //   2. the group's lanes scan the 3^dim neighbour cells in a strided fashion
-//      and only run the circumsphere test; hits are compacted with a wave
-//      ballot and prefix count into an LDS ring of (owner lane, neighbour);
-//   3. whenever 64 entries are queued, every lane takes one entry and runs a
-//      full overlap test; an overlap sets the owner cell's flag, and flagged
-//      cells queue no further work (early exit);
+//      and only run a binary32 circumsphere pre-filter on a cell-sorted copy
+//      of the grid coordinates; hits are compacted with a wave ballot and
+//      prefix count into an LDS ring of (owner lane, neighbour slot);
+//   3. whenever 64 entries are queued, every lane takes one entry and runs
+//      the binary64 circumsphere test and then the full overlap test; an
+//      overlap sets the owner cell's flag, and flagged cells queue no further
+//      work (early exit);
 //   4. leaders of unflagged live cells write the move back.
 // The accept decision is the OR over all neighbours, so it does not depend on
 // the order in which the tests run.
@@ -85,6 +87,33 @@ struct LdsCells {
     __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
 };
 
+// Cell-sorted binary32 copy of the grid coordinates: slot p of the cell list
+// holds the shifted-frame coordinates of its member (2D float2, 3D float4).
+// Only the pre-filter reads it; every decision uses the binary64 state.
+template <int D>
+struct XsView {
+    float* p;
+    __device__ __forceinline__ void load(uint32_t s, float (&v)[3]) const {
+        if constexpr (D == 2) {
+            const float2 f = reinterpret_cast<const float2*>(p)[s];
+            v[0] = f.x;
+            v[1] = f.y;
+            v[2] = 0.0f;
+        } else {
+            const float4 f = reinterpret_cast<const float4*>(p)[s];
+            v[0] = f.x;
+            v[1] = f.y;
+            v[2] = f.z;
+        }
+    }
+    __device__ __forceinline__ void store(uint32_t s, const double (&y)[3]) const {
+        if constexpr (D == 2)
+            reinterpret_cast<float2*>(p)[s] = make_float2((float)y[0], (float)y[1]);
+        else
+            reinterpret_cast<float4*>(p)[s] = make_float4((float)y[0], (float)y[1], (float)y[2], 0.0f);
+    }
+};
+
 template <int KIND>
 __device__ __forceinline__ void load_orient(const double* __restrict__ ori, int N, uint32_t i,
                                             double (&q)[4]) {
@@ -118,6 +147,12 @@ __device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)
         return polygon_overlap64<NV>(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
     } else {
         ct.pair_tests++;
+        if constexpr (PREC == 1) {
+            const int d = polyhedron_overlap_mixed(P, V3{r[0], r[1], r[2]}, Quat{qi[0], qi[1], qi[2], qi[3]},
+                                                   Quat{qk[0], qk[1], qk[2], qk[3]});
+            ct.pair_fp64 += (uint32_t)(d >> 1);
+            return (d & 1) != 0;
+        }
         ct.pair_fp64++;
         return polyhedron_overlap64(P, V3{r[0], r[1], r[2]}, Quat{qi[0], qi[1], qi[2], qi[3]},
                                     Quat{qk[0], qk[1], qk[2], qk[3]});
@@ -136,14 +171,28 @@ __device__ __forceinline__ void grid_shift(const SysDev& S, uint32_t t, uint32_t
 }
 
 template <int D, class POS>
+__device__ __forceinline__ void particle_grid(const SysDev& S, const POS& pos, uint32_t i,
+                                              const double (&sh)[3], double (&y)[3]) {
+    y[2] = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[a] = grid_coord(pos.get(a, i), sh[a], S.L);
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t cell_of_grid(const SysDev& S, const double (&y)[3]) {
+    const int n = S.n;
+    const int cx = cell_of_coord(y[0], S.inv_w, n);
+    const int cy = cell_of_coord(y[1], S.inv_w, n);
+    const int cz = D == 3 ? cell_of_coord(y[2], S.inv_w, n) : 0;
+    return (uint32_t)(cx + n * (cy + n * cz));
+}
+
+template <int D, class POS>
 __device__ __forceinline__ uint32_t particle_cell(const SysDev& S, const POS& pos, uint32_t i,
                                                   const double (&sh)[3]) {
-    const int n = S.n;
-    const int cx = cell_coord(pos.get(0, i), sh[0], S.L, S.inv_w, n);
-    const int cy = cell_coord(pos.get(1, i), sh[1], S.L, S.inv_w, n);
-    int cz = 0;
-    if constexpr (D == 3) cz = cell_coord(pos.get(2, i), sh[2], S.L, S.inv_w, n);
-    return (uint32_t)(cx + n * (cy + n * cz));
+    double y[3];
+    particle_grid<D>(S, pos, i, sh, y);
+    return cell_of_grid<D>(S, y);
 }
 
 __device__ __forceinline__ void active_cell(const SysDev& S, int D, uint32_t colour, int a,
@@ -174,7 +223,9 @@ __device__ __forceinline__ uint32_t neighbour_cell(const int (&cc)[3], int j, in
 // the linear cell index, so each row is one contiguous range -- except at the
 // periodic edge, where the wrapped cell is a second range.  Range ri:
 // row ri / 2 (dy = row % 3 - 1, dz = row / 3 - 1), segment ri % 2 (0: main,
-// 1: wrapped cell or empty).
+// 1: wrapped cell or empty).  ref is the trial point in the frame of the
+// range's periodic image: a neighbour across the edge at 0 holds coordinates
+// near L, so its separation is y_k - (y_n + L), and the other way round.
 template <int D>
 struct Neighbourhood {
     static constexpr int ranges = D == 3 ? 18 : 6;
@@ -182,21 +233,30 @@ struct Neighbourhood {
 
 template <int D, class CELLS>
 __device__ __forceinline__ void neighbour_range(const CELLS& cl, const int (&cc)[3], int n, int ri,
-                                                uint32_t& b, uint32_t& e) {
+                                                double L, const double (&yn)[3], uint32_t& b,
+                                                uint32_t& e, float (&ref)[3]) {
     const int row = ri >> 1;
-    const int y = wrap_cell(cc[1] + (row % 3) - 1, n);
-    const int z = D == 3 ? wrap_cell(cc[2] + (row / 3) - 1, n) : 0;
+    const int yy = cc[1] + (row % 3) - 1;
+    const int zz = D == 3 ? cc[2] + (row / 3) - 1 : 0;
+    const int y = wrap_cell(yy, n);
+    const int z = D == 3 ? wrap_cell(zz, n) : 0;
+    ref[1] = (float)(yy < 0 ? yn[1] + L : (yy >= n ? yn[1] - L : yn[1]));
+    ref[2] = D == 3 ? (float)(zz < 0 ? yn[2] + L : (zz >= n ? yn[2] - L : yn[2])) : 0.0f;
     const int base = n * (y + n * z);
     int x0, x1;
     if ((ri & 1) == 0) {
         x0 = cc[0] > 0 ? cc[0] - 1 : 0;
         x1 = cc[0] < n - 1 ? cc[0] + 1 : n - 1;
+        ref[0] = (float)yn[0];
     } else if (cc[0] == 0) {
         x0 = x1 = n - 1;
+        ref[0] = (float)(yn[0] + L);
     } else if (cc[0] == n - 1) {
         x0 = x1 = 0;
+        ref[0] = (float)(yn[0] - L);
     } else {
         b = e = 0;
+        ref[0] = 0.0f;
         return;
     }
     b = cl.begin((uint32_t)(base + x0));
@@ -206,7 +266,7 @@ __device__ __forceinline__ void neighbour_range(const CELLS& cl, const int (&cc)
 // Per-wave LDS scratch: a 128-entry ring of queued pair tests and one flag per
 // group (cell) of the tile.
 struct WaveScratch {
-    uint32_t* q;     // 128 entries: owner lane << 26 | neighbour tag
+    uint32_t* q;     // 128 entries: owner lane << 26 | neighbour slot
     uint32_t* flag;  // 64 entries
 };
 constexpr int kQueueWords = 128;
@@ -215,14 +275,15 @@ constexpr uint32_t kTagMask = (1u << 26) - 1u;
 
 // ---------------------------------------------------------------------------
 // Drain n (<= 64) queued pair tests: lane L takes entry L, fetches the owner
-// cell's trial state from the owner lane and runs the full test.  All lanes
-// must call (contains cross-lane shuffles).
+// cell's trial state from the owner lane, runs the binary64 circumsphere test
+// (the pre-filter only narrows the candidates) and then the full test.  All
+// lanes must call (contains cross-lane shuffles).
 // ---------------------------------------------------------------------------
-template <int KIND, int PREC, int G, int NV, class POS>
+template <int KIND, int PREC, int G, int NV, class POS, class CELLS>
 __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, const POS& pos,
-                                      const double* __restrict__ ori, const double (&xn)[3],
-                                      const double (&qn)[4], uint32_t n, WaveScratch ws,
-                                      Counters& ct) {
+                                      const double* __restrict__ ori, const CELLS& cl,
+                                      const double (&xn)[3], const double (&qn)[4], uint32_t n,
+                                      WaveScratch ws, Counters& ct) {
     constexpr int D = Traits<KIND>::dim;
     const uint32_t lane = __lane_id();
     wave_sync();
@@ -234,13 +295,17 @@ __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, cons
 #pragma unroll
     for (int c = 0; c < 4; ++c) tq[c] = c < Traits<KIND>::ncomp ? __shfl(qn[c], owner, 64) : qn[c];
     if (lane < n && ws.flag[owner / G] == 0u) {
-        const uint32_t k = e & kTagMask;
+        const uint32_t k = cl.member(e & kTagMask);
         double r[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < D; ++a) r[a] = min_image(pos.get(a, k) - tx[a], S.L, S.inv_L);
-        double qk[4];
-        load_orient<KIND>(ori, S.N, k, qk);
-        if (full_test<KIND, PREC, NV>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
+        double r2 = r[0] * r[0] + r[1] * r[1];
+        if constexpr (D == 3) r2 = r2 + r[2] * r[2];
+        if (r2 < P.circ2) {
+            double qk[4];
+            load_orient<KIND>(ori, S.N, k, qk);
+            if (full_test<KIND, PREC, NV>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
+        }
     }
     wave_sync();
 }
@@ -248,9 +313,10 @@ __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, cons
 template <int KIND, int PREC, int G, int NV, class POS, class CELLS>
 __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                           double* __restrict__ ori, const CELLS& cl,
-                                          uint32_t colour, uint32_t select, uint32_t t,
-                                          uint32_t k0, uint32_t k1, const double (&sh)[3], int a0,
-                                          int n_act, WaveScratch ws, Counters& ct) {
+                                          const XsView<Traits<KIND>::dim>& xs, uint32_t colour,
+                                          uint32_t select, uint32_t t, uint32_t k0, uint32_t k1,
+                                          const double (&sh)[3], int a0, int n_act, WaveScratch ws,
+                                          Counters& ct) {
     constexpr int D = Traits<KIND>::dim;
     const int lane = (int)__lane_id();
     const int grp = lane / G, sub = lane % G;
@@ -260,7 +326,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
 
     // ---- 1. propose (group leaders)
     int cc[3] = {0, 0, 0};
-    uint32_t c = 0, i = 0;
+    uint32_t c = 0, i = 0, pi = 0;  // active cell, moving tag, its slot in the cell list
     bool live = false;
     double xn[3] = {0.0, 0.0, 0.0};
     double qn[4] = {1.0, 0.0, 0.0, 0.0};
@@ -271,7 +337,8 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         if (beg != fin) {
             ct.attempted++;
             const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
-            i = cl.member(beg + index_below(wsel.x, fin - beg));
+            pi = beg + index_below(wsel.x, fin - beg);
+            i = cl.member(pi);
             const uint4 m = draw(t, kMove, select, i, S.replica, k0, k1);
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) xn[ax] = pos.get(ax, i);
@@ -313,66 +380,57 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     if (lane < 64 / G) ws.flag[lane] = 0u;
     if constexpr (G > 1) {
         live = __shfl((int)live, leader, 64) != 0;
-        i = (uint32_t)__shfl((int)i, leader, 64);
+        pi = (uint32_t)__shfl((int)pi, leader, 64);
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             cc[ax] = __shfl(cc[ax], leader, 64);
             if (ax < D) xn[ax] = __shfl(xn[ax], leader, 64);
         }
     }
+    double yn[3] = {0.0, 0.0, 0.0};  // trial point in the shifted frame
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) yn[ax] = grid_coord(xn[ax], sh[ax], S.L);
     wave_sync();
 
-    // ---- 2 + 3. strided circumsphere scan over neighbour ranges, queued full tests
+    // ---- 2 + 3. binary32 circumsphere pre-filter over the neighbour ranges
+    // (lane `sub` of a group takes ranges sub, sub + G, ...), queued exact
+    // tests.  The outer loop over ranges is uniform; each inner loop runs to
+    // the longest range of the wave.
     constexpr int NR = Neighbourhood<D>::ranges;
-    int j = sub;
-    uint32_t p = 0, e = 0;
-    if (live) {
-        for (; j < NR; j += G) {
-            neighbour_range<D>(cl, cc, n, j, p, e);
-            if (p != e) break;
-        }
-    }
-    bool work = live && j < NR;
+    constexpr int NK = (NR + G - 1) / G;
+    const float t2 = S.scan_t2;
     bool flagged = false;  // this lane's cell already has an overlap (register copy)
-    uint32_t queued = 0;  // wave-uniform
-    for (;;) {
-        bool hit = false;
-        uint32_t k = 0;
-        if (work) {
-            if (flagged) {
-                work = false;  // early exit: an overlap was already found
-            } else {
-                k = cl.member(p);
-                if (k != i) {
-                    double r[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int ax = 0; ax < D; ++ax) r[ax] = min_image(pos.get(ax, k) - xn[ax], S.L, S.inv_L);
-                    double r2 = r[0] * r[0] + r[1] * r[1];
-                    if constexpr (D == 3) r2 = r2 + r[2] * r[2];
-                    hit = r2 < P.circ2;
+    uint32_t queued = 0;   // wave-uniform
+    for (int kr = 0; kr < NK; ++kr) {
+        const int ri = sub + kr * G;
+        uint32_t p = 0, e = 0;
+        float ref[3] = {0.0f, 0.0f, 0.0f};
+        if (live && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
+        for (;;) {
+            const bool work = p < e && !flagged;
+            if (__ballot(work) == 0ull) break;
+            bool hit = false;
+            const uint32_t slot = p;
+            if (work) {
+                float v[3];
+                xs.load(slot, v);
+                const float rx = v[0] - ref[0], ry = v[1] - ref[1];
+                float r2 = fmaf(ry, ry, rx * rx);
+                if constexpr (D == 3) {
+                    const float rz = v[2] - ref[2];
+                    r2 = fmaf(rz, rz, r2);
                 }
-                if (++p == e) {
-                    for (j += G; j < NR; j += G) {
-                        neighbour_range<D>(cl, cc, n, j, p, e);
-                        if (p != e) break;
-                    }
-                    work = j < NR;
-                }
+                hit = r2 < t2 && slot != pi;
+                ++p;
             }
-        }
-        if constexpr (KIND == kDisk) {
-            if (hit) ws.flag[grp] = 1u;  // the circumsphere test is the disk test
-            wave_sync();
-            flagged = ws.flag[grp] != 0u;
-        } else {
             const uint64_t hm = __ballot(hit);
             if (hit) {
                 const uint32_t below = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
-                ws.q[queued + below] = ((uint32_t)leader << 26) | k;
+                ws.q[queued + below] = ((uint32_t)leader << 26) | slot;
             }
             queued += (uint32_t)__popcll(hm);
             if (queued >= 64u) {
-                drain<KIND, PREC, G, NV>(S, P, pos, ori, xn, qn, 64u, ws, ct);
+                drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
                 queued -= 64u;
                 const uint32_t moved = (uint32_t)lane < queued ? ws.q[64 + lane] : 0u;
                 flagged = ws.flag[grp] != 0u;
@@ -381,11 +439,8 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                 wave_sync();
             }
         }
-        if (__ballot(work) == 0ull) break;
     }
-    if constexpr (KIND != kDisk) {
-        if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, xn, qn, queued, ws, ct);
-    }
+    if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, ct);
 
     // ---- 4. write back (counters updated arithmetically, not per branch)
     const bool rejected = live && ws.flag[grp] != 0u;
@@ -395,6 +450,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         if (!rejected) {
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) pos.set(ax, i, xn[ax]);
+            if (c_moved) xs.store(pi, yn);
             if constexpr (KIND == kPolygon) {
                 ori[i] = qn[0];
                 ori[N + i] = qn[1];

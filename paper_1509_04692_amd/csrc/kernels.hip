@@ -183,6 +183,23 @@ __global__ void __launch_bounds__(256) k_sort_cells(const uint32_t* __restrict__
     }
 }
 
+// Cell-sorted binary32 copy of the shifted-frame coordinates (slot order).
+template <int D>
+__global__ void __launch_bounds__(256) k_gather_xs(const SysDev* __restrict__ sys, int r,
+                                                   const double* __restrict__ pos_base,
+                                                   const Clock* __restrict__ clock,
+                                                   const uint32_t* __restrict__ members,
+                                                   float* __restrict__ xs) {
+    const SysDev S = sys[r];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= S.N) return;
+    const Clock ck = *clock;
+    double sh[3], y[3];
+    grid_shift(S, ck.t, ck.k0, ck.k1, 1, sh);
+    particle_grid<D>(S, PosView{const_cast<double*>(pos_base) + S.pos_off, S.N}, members[p], sh, y);
+    XsView<D>{xs}.store((uint32_t)p, y);
+}
+
 // One colour pass of the grid path: one wave per tile of 64/G active cells,
 // four waves per work-group.
 template <int KIND, int PREC, int G, int NV>
@@ -192,6 +209,7 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                                 double* __restrict__ ori_base,
                                                 const uint32_t* __restrict__ start,
                                                 const uint32_t* __restrict__ members,
+                                                float* __restrict__ xs,
                                                 uint32_t colour, uint32_t select,
                                                 const Clock* __restrict__ clock,
                                                 unsigned long long* __restrict__ stats) {
@@ -212,8 +230,9 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
         grid_shift(S, t, k0, k1, 1, sh);
         const PosView pos{pos_base + S.pos_off, S.N};
         const GlobalCells cl{start, members};
-        pass_tile<KIND, PREC, G, NV>(S, P, pos, ori_base + S.orient_off, cl, colour, select, t, k0, k1,
-                                 sh, a0, n_act, WaveScratch{qbuf[wave], fbuf[wave]}, ct);
+        pass_tile<KIND, PREC, G, NV>(S, P, pos, ori_base + S.orient_off, cl, XsView<D>{xs}, colour,
+                                     select, t, k0, k1, sh, a0, n_act,
+                                     WaveScratch{qbuf[wave], fbuf[wave]}, ct);
     }
     flush(ct, stats + (size_t)r * kNumStats);
 }
@@ -272,41 +291,43 @@ __global__ void __launch_bounds__(256) k_count(const SysDev* __restrict__ sys,
 
 // ---------------------------------------------------------------------------
 // Persistent path: one work-group owns one replica and runs whole sweeps.
-// LDS (dynamic): [positions D*N f64, when resident] [members N u16]
-// [ends ncells u16] [union: counts ncells u32 while building the cell list /
-// wave queues and flags during the passes] [16 scan words].
+// LDS (dynamic), in this order: positions D*N f64 (residency >= 1),
+// orientations ncomp*N f64 (residency 2), the cell-sorted binary32
+// coordinates (N float2 / float4), members N u16, inclusive ends ncells u16,
+// a union (counts ncells u32 while building the cell list / wave queues and
+// flags during the passes) and 16 scan words.
 // ---------------------------------------------------------------------------
-struct BatchLds {
-    double* pos;
-    uint16_t* mem;
-    uint16_t* ends;
-    uint32_t* uni;
-    uint32_t* scan;
-};
-
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct BatchLayout {
+    size_t pos, ori, xs, mem, ends, uni, scan, total;
+};
 
 // Residency level: 0 = particle data in global memory, 1 = positions in LDS,
 // 2 = positions and orientations in LDS.
-__host__ __device__ inline size_t batch_lds_bytes(int dim, int ncomp, int N, int ncells,
-                                                  int nwaves, int res, size_t* off) {
+__host__ __device__ inline BatchLayout batch_layout(int dim, int ncomp, int N, int ncells,
+                                                    int nwaves, int res) {
+    BatchLayout b;
     size_t o = 0;
-    off[0] = o;
+    b.pos = o;
     o += res >= 1 ? align16((size_t)dim * N * 8) : 0;
-    off[5] = o;
+    b.ori = o;
     o += res >= 2 ? align16((size_t)ncomp * N * 8) : 0;
-    off[1] = o;
+    b.xs = o;
+    o += align16((size_t)N * (size_t)xs_bytes(dim));
+    b.mem = o;
     o += align16((size_t)N * 2);
-    off[2] = o;
+    b.ends = o;
     o += align16((size_t)ncells * 2);
-    off[3] = o;
+    b.uni = o;
     const size_t uni_words = (size_t)ncells > (size_t)nwaves * (kQueueWords + kFlagWords)
                                  ? (size_t)ncells
                                  : (size_t)nwaves * (kQueueWords + kFlagWords);
     o += align16(uni_words * 4);
-    off[4] = o;
+    b.scan = o;
     o += 16 * 4;
-    return o;
+    b.total = o;
+    return b;
 }
 
 template <int KIND, int PREC, int RES, int NV>
@@ -326,16 +347,16 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     const int tid = threadIdx.x, B = blockDim.x, nwaves = B >> 6, wave = tid >> 6;
     const int N = S.N, nc = S.ncells;
     constexpr int NC = Traits<KIND>::ncomp;
-    size_t off[6];
-    batch_lds_bytes(D, NC, N, nc, nwaves, RES, off);
+    const BatchLayout lay = batch_layout(D, NC, N, nc, nwaves, RES);
     double* gpos = pos_base + S.pos_off;
     double* gori = ori_base + S.orient_off;
-    const PosView pos{RES >= 1 ? reinterpret_cast<double*>(lds + off[0]) : gpos, N};
-    double* ori = RES >= 2 ? reinterpret_cast<double*>(lds + off[5]) : gori;
-    uint16_t* mem = reinterpret_cast<uint16_t*>(lds + off[1]);
-    uint16_t* ends = reinterpret_cast<uint16_t*>(lds + off[2]);
-    uint32_t* uni = reinterpret_cast<uint32_t*>(lds + off[3]);
-    uint32_t* sm = reinterpret_cast<uint32_t*>(lds + off[4]);
+    const PosView pos{RES >= 1 ? reinterpret_cast<double*>(lds + lay.pos) : gpos, N};
+    double* ori = RES >= 2 ? reinterpret_cast<double*>(lds + lay.ori) : gori;
+    const XsView<D> xs{reinterpret_cast<float*>(lds + lay.xs)};
+    uint16_t* mem = reinterpret_cast<uint16_t*>(lds + lay.mem);
+    uint16_t* ends = reinterpret_cast<uint16_t*>(lds + lay.ends);
+    uint32_t* uni = reinterpret_cast<uint32_t*>(lds + lay.uni);
+    uint32_t* sm = reinterpret_cast<uint32_t*>(lds + lay.scan);
     if constexpr (RES >= 1) {
         for (int k = tid; k < D * N; k += B) pos.p[k] = gpos[k];
     }
@@ -391,14 +412,20 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             }
         }
         __syncthreads();
+        for (int p = tid; p < N; p += B) {
+            double y[3];
+            particle_grid<D>(S, pos, mem[p], sh, y);
+            xs.store((uint32_t)p, y);
+        }
+        __syncthreads();
         const LdsCells cl{ends, mem};
         const uint32_t ncol = 1u << D;
         for (int rnd = 0; rnd < S.rounds; ++rnd) {
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
                 for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64)
-                    pass_tile<KIND, PREC, 1, NV>(S, P, pos, ori, cl, colour, select, t, k0, k1, sh,
-                                                 a0, n_act, wscr, ct);
+                    pass_tile<KIND, PREC, 1, NV>(S, P, pos, ori, cl, xs, colour, select, t, k0, k1,
+                                                 sh, a0, n_act, wscr, ct);
                 __syncthreads();
             }
         }
@@ -419,8 +446,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
 static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
 size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res) {
-    size_t off[6];
-    return batch_lds_bytes(dim, ncomp, N, ncells, kBatchBlock / 64, res, off);
+    return batch_layout(dim, ncomp, N, ncells, kBatchBlock / 64, res).total;
 }
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream) {
@@ -456,6 +482,14 @@ hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const 
     k_scatter<<<blocks_for(N, 256), 256, 0, stream>>>(ws.cell_of, ws.slot_of, ws.start,
                                                        ws.members, N);
     k_sort_cells<<<blocks_for(nc, 256), 256, 0, stream>>>(ws.start, ws.members, nc);
+    if (shifted) {
+        if (rh.dim == 3)
+            k_gather_xs<3><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock,
+                                                                   ws.members, ws.xs);
+        else
+            k_gather_xs<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock,
+                                                                   ws.members, ws.xs);
+    }
     return hipGetLastError();
 }
 
@@ -469,7 +503,7 @@ static void launch_passes_g(const Workspace& ws, const ReplicaHost& rh, int r, d
     for (int rnd = 0; rnd < rh.rounds; ++rnd)
         for (uint32_t colour = 0; colour < ncol; ++colour)
             k_update<KIND, PREC, G, NV><<<blocks_for(n_act, cells_per_block), 256, 0, stream>>>(
-                ws.sys, ws.species, r, pos, orient, ws.start, ws.members, colour,
+                ws.sys, ws.species, r, pos, orient, ws.start, ws.members, ws.xs, colour,
                 (uint32_t)rnd * ncol + colour, ws.clock, ws.stats);
 }
 
@@ -501,6 +535,8 @@ hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double
         launch_passes<kPolygon, 1>(ws, rh, r, pos, orient, stream);
     else if (rh.kind == kPolygon)
         launch_passes<kPolygon, 0>(ws, rh, r, pos, orient, stream);
+    else if (precision == 1)
+        launch_passes<kPolyhedron, 1>(ws, rh, r, pos, orient, stream);
     else
         launch_passes<kPolyhedron, 0>(ws, rh, r, pos, orient, stream);
     return hipGetLastError();
@@ -546,6 +582,8 @@ hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* p
         return g.nv == 5 ? launch_batch_res<kPolygon, 0, 5>(ws, g, pos, orient, n_sweeps, prepare, stream)
                          : launch_batch_res<kPolygon, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
     }
+    if (precision == 1)
+        return launch_batch_res<kPolyhedron, 1, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
     return launch_batch_res<kPolyhedron, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
 }
 

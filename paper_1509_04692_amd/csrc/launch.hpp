@@ -22,6 +22,7 @@ struct Workspace {
     uint32_t* cell_of;  // N
     uint32_t* slot_of;  // N
     uint32_t* members;  // N
+    float* xs;          // N cell-sorted binary32 coordinates (2 or 4 floats each)
     uint32_t* partial;  // scan tiles
     int32_t* batch_list;  // replica indices of the persistent path, grouped by kind
     Clock* clock;         // sweep counter and key read by the kernels

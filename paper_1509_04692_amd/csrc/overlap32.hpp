@@ -16,6 +16,8 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "mpr32.hpp"
+#include "overlap64.hpp"
 #include "types.hpp"
 
 namespace hpmc {
@@ -93,6 +95,20 @@ __device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd
         }
     }
     return unsure ? kUncertain : kOverlap;
+}
+
+// Mixed-precision polyhedron test: the binary64 set-up, the certified
+// binary32 walk, and the binary64 walk when the former is uncertain.
+// Returns the overlap bit | (binary64 used) << 1.
+__device__ __noinline__ int polyhedron_overlap_mixed(const SpeciesDev& P, const V3& r, const Quat& qa,
+                                                     const Quat& qb) {
+    const Minkowski64 mk = polyhedron_setup64(r, qa, qb);
+    if (P.mpr32_ok) {
+        const double t[3] = {mk.t.x, mk.t.y, mk.t.z};
+        const int d = polyhedron_overlap32(P, mk.M.m, t);
+        if (d != kMprUncertain) return d;
+    }
+    return 2 | (polyhedron_mpr64(P, mk) ? 1 : 0);
 }
 
 }  // namespace hpmc

@@ -91,18 +91,31 @@ __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx
 // ---------------------------------------------------------------------------
 struct V3 { double x, y, z; };
 
-__device__ __forceinline__ double dot(const V3& a, const V3& b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
-__device__ __forceinline__ V3 cross(const V3& a, const V3& b) {
+__host__ __device__ inline double dot(const V3& a, const V3& b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+__host__ __device__ inline V3 cross(const V3& a, const V3& b) {
     return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-__device__ __forceinline__ V3 sub(const V3& a, const V3& b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ V3 neg(const V3& a) { return V3{-a.x, -a.y, -a.z}; }
-__device__ __forceinline__ bool is_zero(const V3& a) { return a.x == 0.0 && a.y == 0.0 && a.z == 0.0; }
+__host__ __device__ inline V3 sub(const V3& a, const V3& b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__host__ __device__ inline V3 neg(const V3& a) { return V3{-a.x, -a.y, -a.z}; }
+__host__ __device__ inline bool is_zero(const V3& a) { return a.x == 0.0 && a.y == 0.0 && a.z == 0.0; }
 
 struct Minkowski64 {
     Mat3 M;  // B frame -> A frame
     V3 t;    // B's centre in A's frame
 };
+
+// Set-up shared by the binary64 and binary32 tests: M = R(conj(qa) qb),
+// t = R(qa)^T r.
+__host__ __device__ inline Minkowski64 polyhedron_setup64(const V3& r, const Quat& qa, const Quat& qb) {
+    Minkowski64 mk;
+    const Quat qac{qa.w, -qa.x, -qa.y, -qa.z};
+    mk.M = rotation_matrix(qmul(qac, qb));
+    const Mat3 ma = rotation_matrix(qa);
+    mk.t = V3{(ma.m[0][0] * r.x + ma.m[1][0] * r.y) + ma.m[2][0] * r.z,
+              (ma.m[0][1] * r.x + ma.m[1][1] * r.y) + ma.m[2][1] * r.z,
+              (ma.m[0][2] * r.x + ma.m[1][2] * r.y) + ma.m[2][2] * r.z};
+    return mk;
+}
 
 __device__ __forceinline__ V3 support64(const SpeciesDev& P, const Minkowski64& mk, const V3& n) {
     const int nv = P.nv;
@@ -129,16 +142,7 @@ __device__ __forceinline__ V3 support64(const SpeciesDev& P, const Minkowski64& 
 
 constexpr int kMprMaxIter = 1024;
 
-__device__ __noinline__ bool polyhedron_overlap64(const SpeciesDev& P, const V3& r, const Quat& qa,
-                                                  const Quat& qb) {
-    Minkowski64 mk;
-    const Quat qac{qa.w, -qa.x, -qa.y, -qa.z};
-    mk.M = rotation_matrix(qmul(qac, qb));
-    const Mat3 ma = rotation_matrix(qa);
-    mk.t = V3{(ma.m[0][0] * r.x + ma.m[1][0] * r.y) + ma.m[2][0] * r.z,
-              (ma.m[0][1] * r.x + ma.m[1][1] * r.y) + ma.m[2][1] * r.z,
-              (ma.m[0][2] * r.x + ma.m[1][2] * r.y) + ma.m[2][2] * r.z};
-
+__device__ __forceinline__ bool polyhedron_mpr64(const SpeciesDev& P, const Minkowski64& mk) {
     const V3 v0 = mk.t;
     if (is_zero(v0)) return true;  // coincident centres
 
@@ -197,6 +201,11 @@ __device__ __noinline__ bool polyhedron_overlap64(const SpeciesDev& P, const V3&
                 v1 = v4;
         }
     }
+}
+
+__device__ __noinline__ bool polyhedron_overlap64(const SpeciesDev& P, const V3& r, const Quat& qa,
+                                                  const Quat& qb) {
+    return polyhedron_mpr64(P, polyhedron_setup64(r, qa, qb));
 }
 
 }  // namespace hpmc

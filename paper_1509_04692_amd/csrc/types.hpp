@@ -10,6 +10,9 @@ constexpr int kMaxPolyhedronVerts = 64;
 
 enum Kind : int32_t { kDisk = 0, kPolygon = 1, kPolyhedron = 2 };
 
+// Bytes per particle of the cell-sorted binary32 coordinate copy.
+constexpr int xs_bytes(int dim) { return dim == 3 ? 16 : 8; }
+
 // Counters kept per replica in the workspace (u64 each), same order as
 // hpmc_stats minus the host-side sweep count.
 enum Stat : int { kAttempted = 0, kAttemptedRot, kCellReject, kOverlapReject, kAccept,
@@ -26,12 +29,14 @@ struct alignas(16) SpeciesDev {
     double vx[kMaxPolyhedronVerts], vy[kMaxPolyhedronVerts], vz[kMaxPolyhedronVerts];
     double nx[kMaxPolyVerts], ny[kMaxPolyVerts];      // polygon outward edge normals
     double pmin[kMaxPolyVerts], pmax[kMaxPolyVerts];  // own projections onto them
-    // binary32 copies for the mixed-precision filter
-    float vx32[kMaxPolyVerts], vy32[kMaxPolyVerts];
+    // binary32 copies for the mixed-precision filters
+    float vx32[kMaxPolyhedronVerts], vy32[kMaxPolyhedronVerts], vz32[kMaxPolyhedronVerts];
     float nx32[kMaxPolyVerts], ny32[kMaxPolyVerts];
     float pmin32[kMaxPolyVerts], pmax32[kMaxPolyVerts];
     float sat_margin_scale;  // forward-error bound factor of the polygon filter
-    float pad1[3];
+    float R32;               // circumradius rounded up to binary32
+    float tol32;             // XenoCollide tolerance rounded up to binary32
+    int32_t mpr32_ok;        // binary32 XenoCollide allowed (R within its range)
 };
 
 // Sweep counter and Philox key, read by the kernels from device memory so that
@@ -47,6 +52,11 @@ struct alignas(16) SysDev {
     int32_t n, dim, N, rounds;
     int32_t ncells, species, replica, path;
     int64_t pos_off, orient_off;  // element offsets into the caller's arrays
+    // Threshold of the binary32 circumsphere pre-filter on the cell-sorted
+    // coordinate copy: every pair whose binary64 |r|^2 is below circ2 has a
+    // binary32 |r|^2 below scan_t2 (bound derived on the host).
+    float scan_t2;
+    uint32_t pad[3];
 };
 
 }  // namespace hpmc

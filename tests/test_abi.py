@@ -81,8 +81,9 @@ def test_workspace_size_grows_with_the_system(lib):
     rc2, b2 = ws_bytes(lib, [sp], [4194304], [2038.438])
     assert rc1 == rc2 == 0
     assert b2 > b1 > 0
-    # global cell list: >= 4 B x (cells + 1) + 12 B per particle
-    assert b2 >= 4 * (2038 * 2038 + 1) + 12 * 4194304
+    # global cell list: >= 4 B x (cells + 1) + 12 B per particle, and the
+    # cell-sorted binary32 coordinates 8 B per particle (2D)
+    assert b2 >= 4 * (2038 * 2038 + 1) + 20 * 4194304
 
 
 def test_box_too_small_and_invalid_shapes(lib):
@@ -97,6 +98,9 @@ def test_box_too_small_and_invalid_shapes(lib):
     assert ws_bytes(lib, [nine], [100], [20.0])[0] == -1  # more than 8 polygon vertices
     assert ws_bytes(lib, [disk], [0], [20.0])[0] == -1
     assert ws_bytes(lib, [disk], [10], [20.0], precision=5)[0] == -1
+    # queue entries carry 26-bit cell-list slots
+    assert ws_bytes(lib, [disk], [1 << 26], [10000.0])[0] == -7
+    assert ws_bytes(lib, [disk], [(1 << 26) - 1], [10000.0])[0] == 0
 
 
 def test_persistent_path_limits(lib):

@@ -89,16 +89,25 @@ def test_pentagons_dense_interlocked(precision):
     assert_parity(gpu, ref, sp)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("shape", ["cube", "trunc_oct"])
 @pytest.mark.parametrize("path", ["grid", "persistent"])
-def test_polyhedra(shape, path):
+def test_polyhedra(shape, path, precision):
     if shape == "cube":
         sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
     else:
         sp, N, L, pos, orient = inputs.workload_truncated_octahedra(343, 0.45)
-    system, gpu, ref = run_pair(sp, L, pos, orient, 10, seed=3, path=path)
+    system, gpu, ref = run_pair(sp, L, pos, orient, 10, seed=3, precision=precision, path=path)
     assert_parity(gpu, ref, sp)
     assert system.count_overlaps()[0] == 0
+    st = system.stats()[0]
+    if precision == "mixed":
+        # the certified binary32 walk decides most pairs
+        frac = st["pair_fp64"] / max(1, st["pair_tests"])
+        print(f"binary64 re-walk fraction {frac:.4f}", flush=True)
+        assert frac < 0.5
+    else:
+        assert st["pair_fp64"] == st["pair_tests"]
 
 
 def test_batched_heterogeneous_replicas():
@@ -246,5 +255,8 @@ def test_full_size_cubes_and_truncated_octahedra():
     """N=32768 cubes (2 rounds per sweep) and truncated octahedra at phi=0.45."""
     for sp, N, L, pos, orient in (inputs.workload_cubes(32768, 0.45),
                                   inputs.workload_truncated_octahedra(32768, 0.45)):
-        system, gpu, ref = run_pair(sp, L, pos, orient, 2, seed=1, path="grid")
-        assert_parity(gpu, ref, sp)
+        for precision in ("fp64", "mixed"):
+            system, gpu, ref = run_pair(sp, L, pos, orient, 2, seed=1, precision=precision,
+                                        path="grid")
+            assert_parity(gpu, ref, sp)
+            del system
