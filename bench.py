@@ -65,6 +65,10 @@ def workload(name):
         sp, N, L, pos, ori = inputs.workload_pentagons(4096, 0.60)
         return {"desc": "regular pentagons N=4096 R=0.5 phi=0.60 d=0.1 a=0.2 p_rot=0.5",
                 "items": [(sp, N, L, pos, ori)], "replicas": 512}
+    if name == "pentagons676":
+        sp, N, L, pos, ori = inputs.workload_pentagons(4096, 0.676)
+        return {"desc": "regular pentagons N=4096 R=0.5 phi=0.676 d=0.1 a=0.2 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 512}
     if name == "disks":
         sp, N, L, pos, ori = inputs.workload_disks_256()
         return {"desc": "hard disks N=256 sigma=1 phi=0.50 d=0.1",
@@ -195,10 +199,11 @@ def _device_info():
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=256, help="timed sweeps (multiple of 64: whole launches)")
-    ap.add_argument("--warmup", type=int, default=64, help="untimed sweeps first")
+    ap.add_argument("--steps", type=int, default=1024, help="timed sweeps (multiple of 64: whole launches)")
+    ap.add_argument("--warmup", type=int, default=128, help="untimed sweeps first")
     ap.add_argument("--workload", default="pentagons",
-                    choices=["pentagons", "disks", "cubes", "trunc_oct", "large", "screening"])
+                    choices=["pentagons", "pentagons676", "disks", "cubes", "trunc_oct", "large",
+                             "screening"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")

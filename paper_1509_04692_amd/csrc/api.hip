@@ -12,6 +12,7 @@
 
 #include "launch.hpp"
 #include "mpr32.hpp"
+#include "overlap32.hpp"
 #include "types.hpp"
 
 using namespace hpmc;
@@ -91,36 +92,7 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
             if (r > rmax) rmax = r;
         }
         P.R = std::nextafter(rmax, INFINITY);  // every vertex inside the circumsphere
-        if (s.shape == HPMC_POLYGON) {
-            double nmax = 0.0;
-            for (int k = 0; k < P.nv; ++k) {
-                const int k1 = (k + 1) % P.nv, k2 = (k + 2) % P.nv;
-                const double ex = P.vx[k1] - P.vx[k], ey = P.vy[k1] - P.vy[k];
-                const double fx = P.vx[k2] - P.vx[k1], fy = P.vy[k2] - P.vy[k1];
-                if (!(ex * fy - ey * fx > 0.0)) return HPMC_ERR_INVALID_ARG;  // CCW, strictly convex
-                P.nx[k] = ey;
-                P.ny[k] = -ex;
-                nmax = std::fmax(nmax, std::sqrt(ey * ey + ex * ex));
-            }
-            for (int k = 0; k < P.nv; ++k) {
-                double lo = 0.0, hi = 0.0;
-                for (int j = 0; j < P.nv; ++j) {
-                    const double p = P.nx[k] * P.vx[j] + P.ny[k] * P.vy[j];
-                    if (j == 0 || p < lo) lo = p;
-                    if (j == 0 || p > hi) hi = p;
-                }
-                P.pmin[k] = lo;
-                P.pmax[k] = hi;
-                P.vx32[k] = (float)P.vx[k];
-                P.vy32[k] = (float)P.vy[k];
-                P.nx32[k] = (float)P.nx[k];
-                P.ny32[k] = (float)P.ny[k];
-                P.pmin32[k] = (float)lo;
-                P.pmax32[k] = (float)hi;
-            }
-            // certification margin of the binary32 filter (see overlap32.hpp)
-            P.sat_margin_scale = (float)(256.0 * 0x1p-24 * nmax * P.R);
-        }
+        if (s.shape == HPMC_POLYGON && !fill_polygon_tables(P)) return HPMC_ERR_INVALID_ARG;
     } else {
         return HPMC_ERR_INVALID_ARG;
     }

@@ -25,7 +25,7 @@ namespace hpmc {
 enum : int { kNoOverlap = 0, kOverlap = 1, kUncertain = 2 };
 
 template <int NV>
-__device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd,
+__host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd,
                                                  double cAd, double sAd, double cBd, double sBd) {
     // NV > 0: vertex count known at compile time; NV == 0: P.nv at run time
     constexpr int MV = NV > 0 ? NV : kMaxPolyVerts;
@@ -95,6 +95,40 @@ __device__ __forceinline__ int polygon_overlap32(const SpeciesDev& P, double rxd
         }
     }
     return unsure ? kUncertain : kOverlap;
+}
+
+// Host side: edge normals, own projections and binary32 copies of a polygon
+// type (vertices and R already set).  False unless the vertices are
+// counter-clockwise and strictly convex.
+inline bool fill_polygon_tables(SpeciesDev& P) {
+    double nmax = 0.0;
+    for (int k = 0; k < P.nv; ++k) {
+        const int k1 = (k + 1) % P.nv, k2 = (k + 2) % P.nv;
+        const double ex = P.vx[k1] - P.vx[k], ey = P.vy[k1] - P.vy[k];
+        const double fx = P.vx[k2] - P.vx[k1], fy = P.vy[k2] - P.vy[k1];
+        if (!(ex * fy - ey * fx > 0.0)) return false;
+        P.nx[k] = ey;
+        P.ny[k] = -ex;
+        nmax = std::fmax(nmax, std::sqrt(ey * ey + ex * ex));
+    }
+    for (int k = 0; k < P.nv; ++k) {
+        double lo = 0.0, hi = 0.0;
+        for (int j = 0; j < P.nv; ++j) {
+            const double p = P.nx[k] * P.vx[j] + P.ny[k] * P.vy[j];
+            if (j == 0 || p < lo) lo = p;
+            if (j == 0 || p > hi) hi = p;
+        }
+        P.pmin[k] = lo;
+        P.pmax[k] = hi;
+        P.vx32[k] = (float)P.vx[k];
+        P.vy32[k] = (float)P.vy[k];
+        P.nx32[k] = (float)P.nx[k];
+        P.ny32[k] = (float)P.ny[k];
+        P.pmin32[k] = (float)lo;
+        P.pmax32[k] = (float)hi;
+    }
+    P.sat_margin_scale = (float)(256.0 * 0x1p-24 * nmax * P.R);
+    return true;
 }
 
 // Mixed-precision polyhedron test: the binary64 set-up, the certified

@@ -1,10 +1,12 @@
-// Host build of the library's certified binary32 XenoCollide (and of the
-// binary64 set-up it starts from), for CPU tests against the oracle.  Built
+// Host build of the library's certified binary32 overlap tests -- the polygon
+// separating-axis filter and the polyhedron XenoCollide walk (with the
+// binary64 set-up it starts from) -- for CPU tests against the oracle.  Built
 // with hipcc --offload-host-only; no GPU code runs.
 #include <cmath>
 #include <cstdint>
 
 #include "../paper_1509_04692_amd/csrc/mpr32.hpp"
+#include "../paper_1509_04692_amd/csrc/overlap32.hpp"
 #include "../paper_1509_04692_amd/csrc/overlap64.hpp"
 
 using namespace hpmc;
@@ -36,5 +38,31 @@ extern "C" int mpr32_pairs(const double* verts, int nv, int64_t n, const double*
         const double t[3] = {mk.t.x, mk.t.y, mk.t.z};
         out[i] = polyhedron_overlap32(P, mk.M.m, t);
     }
+    return 0;
+}
+
+// verts: nv x 2 (CCW); r: n x 2; za, zb: n x 2 (cos, sin).
+// out[i] = 0 no overlap, 1 overlap, 2 uncertain.  margin_scale multiplies
+// the certification margin (1 = the library's; tests shrink it to show that
+// the comparison notices).
+extern "C" int sat32_pairs(const double* verts, int nv, int64_t n, const double* r, const double* za,
+                           const double* zb, int32_t* out, double margin_scale) {
+    if (nv < 3 || nv > kMaxPolyVerts) return -1;
+    static SpeciesDev P;
+    P = SpeciesDev{};
+    P.nv = nv;
+    double rmax = 0.0;
+    for (int k = 0; k < nv; ++k) {
+        P.vx[k] = verts[2 * k];
+        P.vy[k] = verts[2 * k + 1];
+        const double rr = std::sqrt(P.vx[k] * P.vx[k] + P.vy[k] * P.vy[k]);
+        rmax = rr > rmax ? rr : rmax;
+    }
+    P.R = std::nextafter(rmax, INFINITY);
+    if (!fill_polygon_tables(P)) return -2;
+    P.sat_margin_scale = (float)(P.sat_margin_scale * margin_scale);
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = polygon_overlap32<0>(P, r[2 * i], r[2 * i + 1], za[2 * i], za[2 * i + 1], zb[2 * i],
+                                      zb[2 * i + 1]);
     return 0;
 }

@@ -1,11 +1,13 @@
-"""The library's certified binary32 XenoCollide (mixed precision, polyhedra),
-built for the host: every decision it certifies must equal the oracle's
-binary64 decision, and it must certify most pairs.
+"""The library's certified binary32 overlap tests (mixed precision), built
+for the host: the separating-axis filter for polygons and the XenoCollide
+walk for polyhedra.  Every decision they certify must equal the oracle's
+binary64 decision, and they must certify most pairs.
 
 Pairs: random orientations, centre offsets inside the circumsphere distance,
 half of them within 1e-10 .. 1e-2 (relative) of contact, found by bisection
-on the oracle along the offset direction.  Shapes: the cube, the truncated
-octahedron, and a random 40-vertex convex polyhedron.
+on the oracle along the offset direction.  Shapes: pentagon, triangle and a
+random 8-gon; cube, truncated octahedron and a random 40-vertex convex
+polyhedron.
 """
 import ctypes
 import os
@@ -26,11 +28,13 @@ def _build(tmp_path_factory, defines=()):
         pytest.skip("hipcc not available")
     so = tmp_path_factory.mktemp("mpr32") / "libmpr32_host.so"
     subprocess.run([hipcc, "-x", "hip", "--offload-host-only", "-O2", "-ffp-contract=off", "-fPIC",
-                    "-shared", *defines, os.path.join(HERE, "mpr32_host.hip"), "-o", str(so)],
+                    "-shared", *defines, os.path.join(HERE, "certified32_host.hip"), "-o", str(so)],
                    check=True, capture_output=True)
     lib = ctypes.CDLL(str(so))
     P = ctypes.POINTER(ctypes.c_double)
     lib.mpr32_pairs.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int32)]
+    lib.sat32_pairs.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.c_double]
     return lib
 
 
@@ -39,14 +43,14 @@ def mpr32(tmp_path_factory):
     return _build(tmp_path_factory)
 
 
-def run32(lib, verts, r, qa, qb):
+def run32(lib, verts, r, qa, qb, fn="mpr32_pairs", *extra):
     verts = np.ascontiguousarray(verts, dtype=np.float64)
     r, qa, qb = (np.ascontiguousarray(x, dtype=np.float64) for x in (r, qa, qb))
     out = np.zeros(len(r), dtype=np.int32)
     P = ctypes.POINTER(ctypes.c_double)
-    rc = lib.mpr32_pairs(verts.ctypes.data_as(P), len(verts), len(r), r.ctypes.data_as(P),
+    rc = getattr(lib, fn)(verts.ctypes.data_as(P), len(verts), len(r), r.ctypes.data_as(P),
                          qa.ctypes.data_as(P), qb.ctypes.data_as(P),
-                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), *extra)
     assert rc == 0
     return out
 
@@ -59,13 +63,15 @@ def random_polyhedron(rng, n):
 
 def pairs(rng, sp, n):
     lib = oracle.load()
+    dim = sp["dim"]
+    nq = 2 if dim == 2 else 4
     R = np.sqrt((np.asarray(sp["verts"]) ** 2).sum(axis=1)).max()
     r, qa, qb = [], [], []
     for k in range(n):
-        a, b = rng.normal(size=4), rng.normal(size=4)
+        a, b = rng.normal(size=nq), rng.normal(size=nq)
         a /= np.linalg.norm(a)
         b /= np.linalg.norm(b)
-        d = rng.normal(size=3)
+        d = rng.normal(size=dim)
         d /= np.linalg.norm(d)
         if k % 2:
             s = rng.uniform(0.0, 2.0 * R)
@@ -82,6 +88,48 @@ def pairs(rng, sp, n):
         qa.append(a)
         qb.append(b)
     return np.array(r), np.array(qa), np.array(qb)
+
+
+def random_polygon(rng, n):
+    ang = np.sort(rng.uniform(0.0, 2.0 * np.pi, size=n))
+    rad = rng.uniform(0.7, 1.0, size=n)
+    v = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+    from scipy.spatial import ConvexHull
+    return v[ConvexHull(v).vertices]  # counter-clockwise, strictly convex
+
+
+POLYGONS = {
+    "pentagon": inputs.pentagon_species(),
+    "triangle": dict(inputs.pentagon_species(), verts=inputs.regular_polygon_vertices(3, 0.5)),
+    "random8": dict(inputs.pentagon_species(), verts=random_polygon(np.random.default_rng(5), 8)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(POLYGONS))
+def test_certified_binary32_polygon_filter_equals_the_oracle(mpr32, name):
+    sp = POLYGONS[name]
+    r, za, zb = pairs(np.random.default_rng(13), sp, 6000)
+    got = run32(mpr32, sp["verts"], r, za, zb, "sat32_pairs", 1.0)
+    lib = oracle.load()
+    ref = np.array([oracle.pair_overlaps(sp, r[i], za[i], zb[i], lib=lib) for i in range(len(r))])
+    sure = got != 2
+    assert (got[sure] == ref[sure]).all(), np.flatnonzero(sure & (got != ref))[:10]
+    far = np.arange(len(r)) % 2 == 1
+    assert sure[far].mean() > 0.999, sure[far].mean()
+    assert sure.mean() > 0.6, sure.mean()
+    assert ref.mean() > 0.2 and ref.mean() < 0.8
+
+
+def test_a_zero_polygon_margin_is_caught(mpr32):
+    """Sensitivity: with no certification margin the binary32 filter decides
+    pairs it cannot resolve, and some differ from the oracle's."""
+    sp = POLYGONS["pentagon"]
+    r, za, zb = pairs(np.random.default_rng(13), sp, 6000)
+    got = run32(mpr32, sp["verts"], r, za, zb, "sat32_pairs", 0.0)
+    lib = oracle.load()
+    ref = np.array([oracle.pair_overlaps(sp, r[i], za[i], zb[i], lib=lib) for i in range(len(r))])
+    sure = got != 2
+    assert (got[sure] != ref[sure]).sum() > 10
 
 
 SHAPES = {
