@@ -147,6 +147,14 @@ __host__ __device__ inline Mat3 rotation_matrix(const Quat& q) {
 // ---------------------------------------------------------------------------
 // Wave64 helpers.
 // ---------------------------------------------------------------------------
+// Mask of the lanes where p holds (an SGPR pair, no VALU work).
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of set bits of m below this lane (v_mbcnt_lo / v_mbcnt_hi).
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);

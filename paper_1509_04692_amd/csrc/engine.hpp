@@ -112,6 +112,12 @@ struct XsView {
         else
             reinterpret_cast<float4*>(p)[s] = make_float4((float)y[0], (float)y[1], (float)y[2], 0.0f);
     }
+    __device__ __forceinline__ void store(uint32_t s, const float (&v)[3]) const {
+        if constexpr (D == 2)
+            reinterpret_cast<float2*>(p)[s] = make_float2(v[0], v[1]);
+        else
+            reinterpret_cast<float4*>(p)[s] = make_float4(v[0], v[1], v[2], 0.0f);
+    }
 };
 
 template <int KIND>
@@ -310,7 +316,9 @@ __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, cons
     wave_sync();
 }
 
-template <int KIND, int PREC, int G, int NV, class POS, class CELLS>
+// PARK: the sorted copy is in LDS and the moving particle's slot is parked
+// at infinity during its own scan (else the scan tests the slot).
+template <int KIND, int PREC, int G, int NV, bool PARK, class POS, class CELLS>
 __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                           double* __restrict__ ori, const CELLS& cl,
                                           const XsView<Traits<KIND>::dim>& xs, uint32_t colour,
@@ -377,10 +385,18 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     }
     ct.attempted_rot += (sub == 0 && a < n_act && c_rot) ? 1u : 0u;
     ct.cell_reject += (sub == 0 && a < n_act && c_moved && !live) ? 1u : 0u;
+    // the moving particle's own slot is parked at infinity for the scan (no
+    // candidate is closer), so the loop needs no self test
+    float own[3] = {0.0f, 0.0f, 0.0f};
+    if (PARK && sub == 0 && live) {
+        xs.load(pi, own);
+        const float far[3] = {INFINITY, INFINITY, INFINITY};
+        xs.store(pi, far);
+    }
     if (lane < 64 / G) ws.flag[lane] = 0u;
     if constexpr (G > 1) {
         live = __shfl((int)live, leader, 64) != 0;
-        pi = (uint32_t)__shfl((int)pi, leader, 64);
+        if constexpr (!PARK) pi = (uint32_t)__shfl((int)pi, leader, 64);
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             cc[ax] = __shfl(cc[ax], leader, 64);
@@ -405,35 +421,34 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         const int ri = sub + kr * G;
         uint32_t p = 0, e = 0;
         float ref[3] = {0.0f, 0.0f, 0.0f};
-        if (live && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
+        if (live && !flagged && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
         for (;;) {
-            const bool work = p < e && !flagged;
-            if (__ballot(work) == 0ull) break;
-            bool hit = false;
-            const uint32_t slot = p;
-            if (work) {
-                float v[3];
-                xs.load(slot, v);
-                const float rx = v[0] - ref[0], ry = v[1] - ref[1];
-                float r2 = fmaf(ry, ry, rx * rx);
-                if constexpr (D == 3) {
-                    const float rz = v[2] - ref[2];
-                    r2 = fmaf(rz, rz, r2);
-                }
-                hit = r2 < t2 && slot != pi;
-                ++p;
+            // each predicate is a single compare so that its ballot is the
+            // compare's lane mask: a flagged lane has e = p, an idle lane's
+            // distance is infinite
+            const bool work = p < e;
+            if (wave_ballot(work) == 0ull) break;
+            const uint32_t slot = work ? p : 0u;  // idle lanes read slot 0 (always valid)
+            float v[3];
+            xs.load(slot, v);
+            const float rx = v[0] - ref[0], ry = v[1] - ref[1];
+            float r2 = fmaf(ry, ry, rx * rx);
+            if constexpr (D == 3) {
+                const float rz = v[2] - ref[2];
+                r2 = fmaf(rz, rz, r2);
             }
-            const uint64_t hm = __ballot(hit);
-            if (hit) {
-                const uint32_t below = (uint32_t)__popcll(hm & ((1ull << lane) - 1ull));
-                ws.q[queued + below] = ((uint32_t)leader << 26) | slot;
-            }
-            queued += (uint32_t)__popcll(hm);
+            r2 = (work && (PARK || slot != pi)) ? r2 : INFINITY;
+            const bool hit = r2 < t2;
+            p += work ? 1u : 0u;
+            const uint64_t hm = wave_ballot(hit);
+            if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | slot;
+            queued += (uint32_t)__builtin_popcountll(hm);
             if (queued >= 64u) {
                 drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
                 queued -= 64u;
                 const uint32_t moved = (uint32_t)lane < queued ? ws.q[64 + lane] : 0u;
                 flagged = ws.flag[grp] != 0u;
+                e = flagged ? p : e;
                 wave_sync();
                 if ((uint32_t)lane < queued) ws.q[lane] = moved;
                 wave_sync();
@@ -447,10 +462,16 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     ct.overlap_reject += (sub == 0 && rejected) ? 1u : 0u;
     ct.accept += (sub == 0 && live && !rejected) ? 1u : 0u;
     if (sub == 0 && live) {
-        if (!rejected) {
+        if (!rejected && c_moved)
+            xs.store(pi, yn);
+        else if (PARK)
+            xs.store(pi, own);
+        // only what the move changed
+        if (!rejected && c_moved) {
 #pragma unroll
             for (int ax = 0; ax < D; ++ax) pos.set(ax, i, xn[ax]);
-            if (c_moved) xs.store(pi, yn);
+        }
+        if (!rejected && c_rot) {
             if constexpr (KIND == kPolygon) {
                 ori[i] = qn[0];
                 ori[N + i] = qn[1];

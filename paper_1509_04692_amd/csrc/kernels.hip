@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
         grid_shift(S, t, k0, k1, 1, sh);
         const PosView pos{pos_base + S.pos_off, S.N};
         const GlobalCells cl{start, members};
-        pass_tile<KIND, PREC, G, NV>(S, P, pos, ori_base + S.orient_off, cl, XsView<D>{xs}, colour,
+        pass_tile<KIND, PREC, G, NV, false>(S, P, pos, ori_base + S.orient_off, cl, XsView<D>{xs}, colour,
                                      select, t, k0, k1, sh, a0, n_act,
                                      WaveScratch{qbuf[wave], fbuf[wave]}, ct);
     }
@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
                 for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64)
-                    pass_tile<KIND, PREC, 1, NV>(S, P, pos, ori, cl, xs, colour, select, t, k0, k1,
+                    pass_tile<KIND, PREC, 1, NV, true>(S, P, pos, ori, cl, xs, colour, select, t, k0, k1,
                                                  sh, a0, n_act, wscr, ct);
                 __syncthreads();
             }
