@@ -44,11 +44,14 @@ constexpr uint64_t kSweepLimit = 1ull << 32;
 constexpr size_t kAlign = 256;
 // LDS per work-group available to the persistent path (gfx950: 160 KiB;
 // the device attribute is queried at init).
+// LDS per work-group of the current device; gfx950's 160 KiB when no device
+// can be queried (workspace sizing on a host without a GPU).
 size_t device_lds_limit() {
+    constexpr size_t kGfx950Lds = 160 * 1024;
     int dev = 0, v = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    if (hipGetDevice(&dev) != hipSuccess) return kGfx950Lds;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-        return 64 * 1024;
+        return kGfx950Lds;
     return (size_t)v;
 }
 constexpr uint32_t kPersistentChunk = HPMC_PERSISTENT_SWEEPS_PER_LAUNCH;

@@ -273,10 +273,15 @@ __device__ __forceinline__ void neighbour_range(const CELLS& cl, const int (&cc)
 // group (cell) of the tile.
 struct WaveScratch {
     uint32_t* q;     // 128 entries: owner lane << 26 | neighbour slot
+    uint32_t* q2;    // 128 entries: polygon pairs left after their first half of axes
     uint32_t* flag;  // 64 entries
 };
 constexpr int kQueueWords = 128;
 constexpr int kFlagWords = 64;
+constexpr int kWaveScratchWords = 2 * kQueueWords + kFlagWords;
+__device__ __forceinline__ WaveScratch wave_scratch(uint32_t* base) {
+    return WaveScratch{base, base + kQueueWords, base + 2 * kQueueWords};
+}
 constexpr uint32_t kTagMask = (1u << 26) - 1u;
 
 // ---------------------------------------------------------------------------
@@ -313,6 +318,95 @@ __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, cons
             if (full_test<KIND, PREC, NV>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
         }
     }
+    wave_sync();
+}
+
+// Binary64 polygons drain in two stages so that a drain's lanes run similar
+// work (the binary32 filter's halves are too cheap to pay for the second
+// queue, so the mixed path keeps one stage):
+// stage 1 runs the binary64 circumsphere test and the first half of the
+// separating axes (A's normals); pairs that half cannot separate go to a
+// second queue, whose drain runs the other half (B's normals).  The result
+// is the OR over both halves, as in the one-stage test.  Stage 1 returns the
+// new length of the second queue.  All lanes must call.
+template <int PREC, int G, int NV, class POS, class CELLS>
+__device__ __forceinline__ uint32_t drain_polygon1(const SysDev& S, const SpeciesDev& P, const POS& pos,
+                                                   const double* __restrict__ ori, const CELLS& cl,
+                                                   const double (&xn)[3], const double (&qn)[4],
+                                                   uint32_t n, WaveScratch ws, uint32_t queued2,
+                                                   Counters& ct) {
+    const uint32_t lane = __lane_id();
+    wave_sync();
+    const uint32_t e = lane < n ? ws.q[lane] : 0u;
+    const int owner = lane < n ? (int)(e >> 26) : (int)lane;
+    const double tx = __shfl(xn[0], owner, 64), ty = __shfl(xn[1], owner, 64);
+    const double tc = __shfl(qn[0], owner, 64), ts = __shfl(qn[1], owner, 64);
+    bool push = false;
+    if (lane < n && ws.flag[owner / G] == 0u) {
+        const uint32_t k = cl.member(e & kTagMask);
+        const double rx = min_image(pos.get(0, k) - tx, S.L, S.inv_L);
+        const double ry = min_image(pos.get(1, k) - ty, S.L, S.inv_L);
+        if (rx * rx + ry * ry < P.circ2) {
+            ct.pair_tests++;
+            const double kc = ori[k], ks = ori[S.N + k];
+            if constexpr (PREC == 1) {
+                const int h = polygon_half32<NV, 0>(P, rx, ry, tc, ts, kc, ks);
+                if (h == kHalfUnsure) {
+                    ct.pair_fp64++;
+                    if (polygon_overlap64<NV>(P, rx, ry, tc, ts, kc, ks)) ws.flag[owner / G] = 1u;
+                }
+                push = h == kHalfOverlaps;
+            } else {
+                ct.pair_fp64++;
+                push = !polygon_half_separated64<NV, 0>(P, rx, ry, tc, ts, kc, ks);
+            }
+        }
+    }
+    const uint64_t pm = wave_ballot(push);
+    if (push) ws.q2[queued2 + lanes_below(pm)] = e;
+    wave_sync();
+    return queued2 + (uint32_t)__builtin_popcountll(pm);
+}
+
+template <int PREC, int G, int NV, class POS, class CELLS>
+__device__ __forceinline__ void drain_polygon2(const SysDev& S, const SpeciesDev& P, const POS& pos,
+                                               const double* __restrict__ ori, const CELLS& cl,
+                                               const double (&xn)[3], const double (&qn)[4], uint32_t n,
+                                               WaveScratch ws, Counters& ct) {
+    const uint32_t lane = __lane_id();
+    wave_sync();
+    const uint32_t e = lane < n ? ws.q2[lane] : 0u;
+    const int owner = lane < n ? (int)(e >> 26) : (int)lane;
+    const double tx = __shfl(xn[0], owner, 64), ty = __shfl(xn[1], owner, 64);
+    const double tc = __shfl(qn[0], owner, 64), ts = __shfl(qn[1], owner, 64);
+    if (lane < n && ws.flag[owner / G] == 0u) {
+        const uint32_t k = cl.member(e & kTagMask);
+        const double rx = min_image(pos.get(0, k) - tx, S.L, S.inv_L);
+        const double ry = min_image(pos.get(1, k) - ty, S.L, S.inv_L);
+        const double kc = ori[k], ks = ori[S.N + k];
+        bool overlap;
+        if constexpr (PREC == 1) {
+            const int h = polygon_half32<NV, 1>(P, rx, ry, tc, ts, kc, ks);
+            if (h == kHalfUnsure) {
+                ct.pair_fp64++;
+                overlap = polygon_overlap64<NV>(P, rx, ry, tc, ts, kc, ks);
+            } else {
+                overlap = h == kHalfOverlaps;
+            }
+        } else {
+            overlap = !polygon_half_separated64<NV, 1>(P, rx, ry, tc, ts, kc, ks);
+        }
+        if (overlap) ws.flag[owner / G] = 1u;
+    }
+    wave_sync();
+}
+
+// Keep queue entries [from, from + count) as entries [0, count).
+__device__ __forceinline__ void compact_queue(uint32_t* q, uint32_t from, uint32_t count) {
+    const uint32_t lane = __lane_id();
+    const uint32_t v = lane < count ? q[from + lane] : 0u;
+    wave_sync();
+    if (lane < count) q[lane] = v;
     wave_sync();
 }
 
@@ -417,6 +511,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     const float t2 = S.scan_t2;
     bool flagged = false;  // this lane's cell already has an overlap (register copy)
     uint32_t queued = 0;   // wave-uniform
+    uint32_t queued2 = 0;  // wave-uniform, polygons only
     for (int kr = 0; kr < NK; ++kr) {
         const int ri = sub + kr * G;
         uint32_t p = 0, e = 0;
@@ -444,18 +539,36 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
             if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | slot;
             queued += (uint32_t)__builtin_popcountll(hm);
             if (queued >= 64u) {
-                drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+                if constexpr (KIND == kPolygon && PREC == 0) {
+                    queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, queued2, ct);
+                } else {
+                    drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+                }
                 queued -= 64u;
-                const uint32_t moved = (uint32_t)lane < queued ? ws.q[64 + lane] : 0u;
+                compact_queue(ws.q, 64u, queued);
+                if constexpr (KIND == kPolygon && PREC == 0) {
+                    if (queued2 >= 64u) {
+                        drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+                        queued2 -= 64u;
+                        compact_queue(ws.q2, 64u, queued2);
+                    }
+                }
                 flagged = ws.flag[grp] != 0u;
                 e = flagged ? p : e;
-                wave_sync();
-                if ((uint32_t)lane < queued) ws.q[lane] = moved;
-                wave_sync();
             }
         }
     }
-    if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, ct);
+    if constexpr (KIND == kPolygon && PREC == 0) {
+        if (queued) queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, queued2, ct);
+        while (queued2) {
+            const uint32_t m = queued2 < 64u ? queued2 : 64u;
+            drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, m, ws, ct);
+            queued2 -= m;
+            if (queued2) compact_queue(ws.q2, 64u, queued2);
+        }
+    } else {
+        if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, ct);
+    }
 
     // ---- 4. write back (counters updated arithmetically, not per branch)
     const bool rejected = live && ws.flag[grp] != 0u;

@@ -214,8 +214,7 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                                 const Clock* __restrict__ clock,
                                                 unsigned long long* __restrict__ stats) {
     constexpr int D = Traits<KIND>::dim;
-    __shared__ uint32_t qbuf[4][kQueueWords];
-    __shared__ uint32_t fbuf[4][kFlagWords];
+    __shared__ uint32_t scratch_words[4][kWaveScratchWords];
     const SysDev S = sys[r];
     const SpeciesDev& P = spc[S.species];
     Counters ct = {};
@@ -232,7 +231,7 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
         const GlobalCells cl{start, members};
         pass_tile<KIND, PREC, G, NV, false>(S, P, pos, ori_base + S.orient_off, cl, XsView<D>{xs}, colour,
                                      select, t, k0, k1, sh, a0, n_act,
-                                     WaveScratch{qbuf[wave], fbuf[wave]}, ct);
+                                     wave_scratch(scratch_words[wave]), ct);
     }
     flush(ct, stats + (size_t)r * kNumStats);
 }
@@ -320,9 +319,9 @@ __host__ __device__ inline BatchLayout batch_layout(int dim, int ncomp, int N, i
     b.ends = o;
     o += align16((size_t)ncells * 2);
     b.uni = o;
-    const size_t uni_words = (size_t)ncells > (size_t)nwaves * (kQueueWords + kFlagWords)
+    const size_t uni_words = (size_t)ncells > (size_t)nwaves * kWaveScratchWords
                                  ? (size_t)ncells
-                                 : (size_t)nwaves * (kQueueWords + kFlagWords);
+                                 : (size_t)nwaves * kWaveScratchWords;
     o += align16(uni_words * 4);
     b.scan = o;
     o += 16 * 4;
@@ -370,8 +369,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
     const int chunk = (nc + B - 1) / B;
-    const WaveScratch wscr{uni + wave * (kQueueWords + kFlagWords),
-                           uni + wave * (kQueueWords + kFlagWords) + kQueueWords};
+    const WaveScratch wscr = wave_scratch(uni + wave * kWaveScratchWords);
     for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
         const uint32_t t = t0 + sw;
         double sh[3];

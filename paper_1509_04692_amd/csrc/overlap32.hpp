@@ -24,9 +24,15 @@ namespace hpmc {
 
 enum : int { kNoOverlap = 0, kOverlap = 1, kUncertain = 2 };
 
-template <int NV>
-__host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd,
-                                                 double cAd, double sAd, double cBd, double sBd) {
+// One half of the axes (HALF 0: A's normals, B's vertices in A's frame;
+// HALF 1: B's normals, A's vertices in B's frame): kHalfSeparated when one
+// axis certainly separates, kHalfOverlaps when every axis certainly does
+// not, kHalfUnsure otherwise.
+enum : int { kHalfSeparated = 0, kHalfOverlaps = 1, kHalfUnsure = 2 };
+
+template <int NV, int HALF>
+__host__ __device__ inline int polygon_half32(const SpeciesDev& P, double rxd, double ryd, double cAd,
+                                              double sAd, double cBd, double sBd) {
     // NV > 0: vertex count known at compile time; NV == 0: P.nv at run time
     constexpr int MV = NV > 0 ? NV : kMaxPolyVerts;
     const int nv = NV > 0 ? NV : P.nv;
@@ -43,8 +49,15 @@ __host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd
 #pragma unroll
     for (int j = 0; j < MV; ++j) {
         if (j < nv) {
-            px[j] = fmaf(zc, P.vx32[j], fmaf(-zs, P.vy32[j], tx));
-            py[j] = fmaf(zs, P.vx32[j], fmaf(zc, P.vy32[j], ty));
+            if constexpr (HALF == 0) {
+                px[j] = fmaf(zc, P.vx32[j], fmaf(-zs, P.vy32[j], tx));
+                py[j] = fmaf(zs, P.vx32[j], fmaf(zc, P.vy32[j], ty));
+            } else {
+                const float ux = P.vx32[j] - tx;
+                const float uy = P.vy32[j] - ty;
+                px[j] = fmaf(zc, ux, zs * uy);
+                py[j] = fmaf(zc, uy, -(zs * ux));
+            }
         }
     }
 #pragma unroll
@@ -61,40 +74,22 @@ __host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd
                     hi = fmaxf(hi, p);
                 }
             }
-            const float amax = P.pmax32[k], amin = P.pmin32[k];
-            if (lo >= amax + M || hi <= amin - M) return kNoOverlap;
-            unsure |= !(lo < amax - M && hi > amin + M);
+            const float smax = P.pmax32[k], smin = P.pmin32[k];
+            if (lo >= smax + M || hi <= smin - M) return kHalfSeparated;
+            unsure |= !(lo < smax - M && hi > smin + M);
         }
     }
-#pragma unroll
-    for (int j = 0; j < MV; ++j) {
-        if (j < nv) {
-            const float ux = P.vx32[j] - tx;
-            const float uy = P.vy32[j] - ty;
-            px[j] = fmaf(zc, ux, zs * uy);
-            py[j] = fmaf(zc, uy, -(zs * ux));
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < MV; ++k) {
-        if (k < nv) {
-            const float nx = P.nx32[k], ny = P.ny32[k];
-            float lo = fmaf(nx, px[0], ny * py[0]);
-            float hi = lo;
-#pragma unroll
-            for (int j = 1; j < MV; ++j) {
-                if (j < nv) {
-                    const float p = fmaf(nx, px[j], ny * py[j]);
-                    lo = fminf(lo, p);
-                    hi = fmaxf(hi, p);
-                }
-            }
-            const float bmax = P.pmax32[k], bmin = P.pmin32[k];
-            if (hi <= bmin - M || lo >= bmax + M) return kNoOverlap;
-            unsure |= !(hi > bmin + M && lo < bmax - M);
-        }
-    }
-    return unsure ? kUncertain : kOverlap;
+    return unsure ? kHalfUnsure : kHalfOverlaps;
+}
+
+template <int NV>
+__host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd, double cAd,
+                                                 double sAd, double cBd, double sBd) {
+    const int a = polygon_half32<NV, 0>(P, rxd, ryd, cAd, sAd, cBd, sBd);
+    if (a == kHalfSeparated) return kNoOverlap;
+    const int b = polygon_half32<NV, 1>(P, rxd, ryd, cAd, sAd, cBd, sBd);
+    if (b == kHalfSeparated) return kNoOverlap;
+    return (a == kHalfUnsure || b == kHalfUnsure) ? kUncertain : kOverlap;
 }
 
 // Host side: edge normals, own projections and binary32 copies of a polygon

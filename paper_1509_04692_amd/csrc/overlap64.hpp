@@ -16,9 +16,12 @@ namespace hpmc {
 // their own normals are per-shape constants.  An axis separates when the
 // projection intervals are disjoint or touch.
 // ---------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx, double ry,
-                                                  double cA, double sA, double cB, double sB) {
+// One half of the axes: HALF 0 = A's normals with B's vertices mapped into
+// A's frame, HALF 1 = B's normals with A's vertices mapped into B's frame.
+// True when one of them separates.
+template <int NV, int HALF>
+__device__ __forceinline__ bool polygon_half_separated64(const SpeciesDev& P, double rx, double ry,
+                                                         double cA, double sA, double cB, double sB) {
     // NV > 0: vertex count known at compile time; NV == 0: P.nv at run time
     constexpr int MV = NV > 0 ? NV : kMaxPolyVerts;
     const int nv = NV > 0 ? NV : P.nv;
@@ -31,8 +34,15 @@ __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx
 #pragma unroll
     for (int j = 0; j < MV; ++j) {
         if (j < nv) {
-            px[j] = (zc * P.vx[j] - zs * P.vy[j]) + tx;
-            py[j] = (zs * P.vx[j] + zc * P.vy[j]) + ty;
+            if constexpr (HALF == 0) {
+                px[j] = (zc * P.vx[j] - zs * P.vy[j]) + tx;
+                py[j] = (zs * P.vx[j] + zc * P.vy[j]) + ty;
+            } else {
+                const double ux = P.vx[j] - tx;
+                const double uy = P.vy[j] - ty;
+                px[j] = zc * ux + zs * uy;
+                py[j] = zc * uy - zs * ux;
+            }
         }
     }
 #pragma unroll
@@ -49,36 +59,21 @@ __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx
                     hi = fmax(hi, p);
                 }
             }
-            if (P.pmax[k] <= lo || hi <= P.pmin[k]) return false;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < MV; ++j) {
-        if (j < nv) {
-            const double ux = P.vx[j] - tx;
-            const double uy = P.vy[j] - ty;
-            px[j] = zc * ux + zs * uy;
-            py[j] = zc * uy - zs * ux;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < MV; ++k) {
-        if (k < nv) {
-            const double nx = P.nx[k], ny = P.ny[k];
-            double lo = nx * px[0] + ny * py[0];
-            double hi = lo;
-#pragma unroll
-            for (int j = 1; j < MV; ++j) {
-                if (j < nv) {
-                    const double p = nx * px[j] + ny * py[j];
-                    lo = fmin(lo, p);
-                    hi = fmax(hi, p);
-                }
+            if constexpr (HALF == 0) {
+                if (P.pmax[k] <= lo || hi <= P.pmin[k]) return true;
+            } else {
+                if (hi <= P.pmin[k] || P.pmax[k] <= lo) return true;
             }
-            if (hi <= P.pmin[k] || P.pmax[k] <= lo) return false;
         }
     }
-    return true;
+    return false;
+}
+
+template <int NV>
+__device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx, double ry,
+                                                  double cA, double sA, double cB, double sB) {
+    return !polygon_half_separated64<NV, 0>(P, rx, ry, cA, sA, cB, sB) &&
+           !polygon_half_separated64<NV, 1>(P, rx, ry, cA, sA, cB, sB);
 }
 
 // ---------------------------------------------------------------------------
