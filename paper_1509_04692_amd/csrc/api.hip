@@ -276,7 +276,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     };
     lay.species = take(sizeof(SpeciesDev) * R);
     lay.sys = take(sizeof(SysDev) * R);
-    lay.stats = take(sizeof(unsigned long long) * kNumStats * R);
+    lay.stats = take(sizeof(unsigned long long) * kStatsPerReplica * R);
     lay.overlap = take(sizeof(unsigned long long) * R);
     lay.count = take(4 * (size_t)nc_max);
     lay.start = take(4 * ((size_t)nc_max + 1));
@@ -291,7 +291,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.ori_total = (size_t)ori_off;
     lay.backup_pos = take(8 * (size_t)pos_off);
     lay.backup_ori = take(8 * (size_t)(ori_off > 0 ? ori_off : 1));
-    lay.backup_stats = take(sizeof(unsigned long long) * kNumStats * R);
+    lay.backup_stats = take(sizeof(unsigned long long) * kStatsPerReplica * R);
     lay.total = off;
     return HPMC_OK;
 }
@@ -466,7 +466,8 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
         rc = check_hip(st, hipMemcpyAsync(st->ws.batch_list, list.data(), sizeof(int32_t) * list.size(),
                                           hipMemcpyHostToDevice, st->stream));
     if (!rc)
-        rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kNumStats * st->n_replicas, st->stream));
+        rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kStatsPerReplica * st->n_replicas,
+                                    st->stream));
     if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
     for (const BatchGroup& g : st->groups)
         if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0,
@@ -520,13 +521,16 @@ int hpmc_count_overlaps(hpmc_state* st, uint64_t* out_per_replica) {
 
 int hpmc_get_stats(hpmc_state* st, hpmc_stats* out) {
     if (st == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
-    std::vector<unsigned long long> raw((size_t)kNumStats * st->n_replicas);
+    std::vector<unsigned long long> raw((size_t)kStatsPerReplica * st->n_replicas);
     int rc = check_hip(st, hipMemcpyAsync(raw.data(), st->ws.stats, raw.size() * sizeof(raw[0]),
                                           hipMemcpyDeviceToHost, st->stream));
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
     if (rc) return rc;
     for (int r = 0; r < st->n_replicas; ++r) {
-        const unsigned long long* v = raw.data() + (size_t)r * kNumStats;
+        unsigned long long v[kNumStats] = {};
+        for (int s = 0; s < kStatStripes; ++s)
+            for (int k = 0; k < kNumStats; ++k)
+                v[k] += raw[((size_t)r * kStatStripes + s) * kStatStride + k];
         out[r].attempted = v[kAttempted];
         out[r].attempted_rot = v[kAttemptedRot];
         out[r].cell_reject = v[kCellReject];
@@ -542,7 +546,8 @@ int hpmc_get_stats(hpmc_state* st, hpmc_stats* out) {
 int hpmc_reset_stats(hpmc_state* st) {
     if (st == nullptr) return HPMC_ERR_INVALID_ARG;
     st->sweeps_done = 0;
-    return check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kNumStats * st->n_replicas, st->stream));
+    return check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kStatsPerReplica * st->n_replicas,
+                                  st->stream));
 }
 
 int hpmc_sync_to_canonical(hpmc_state* st) {
@@ -586,7 +591,7 @@ int hpmc_uses_graph(hpmc_state* st) { return (st && st->graph) ? 1 : 0; }
 
 int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
     if (st == nullptr || trial_sweeps == 0) return HPMC_ERR_INVALID_ARG;
-    const size_t nstat = (size_t)kNumStats * st->n_replicas;
+    const size_t nstat = (size_t)kStatsPerReplica * st->n_replicas;
     // snapshot the caller's state
     int rc = check_hip(st, hipMemcpyAsync(st->ws.backup_pos, st->pos, 8 * st->pos_total,
                                           hipMemcpyDeviceToDevice, st->stream));

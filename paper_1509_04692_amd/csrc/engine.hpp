@@ -43,6 +43,11 @@ __device__ __forceinline__ void flush_one(uint32_t v, unsigned long long* p) {
     if (__lane_id() == 0 && s != 0) atomicAdd(p, (unsigned long long)s);
 }
 
+// The stripe of replica r's counters that this work-group adds into.
+__device__ __forceinline__ unsigned long long* stat_stripe(unsigned long long* stats, int r) {
+    return stats + ((size_t)r * kStatStripes + blockIdx.x % kStatStripes) * kStatStride;
+}
+
 // One 64-bit atomic per wave and counter.  Every lane of the wave must call.
 __device__ __forceinline__ void flush(const Counters& c, unsigned long long* stats) {
     flush_one(c.attempted, stats + kAttempted);
@@ -52,6 +57,29 @@ __device__ __forceinline__ void flush(const Counters& c, unsigned long long* sta
     flush_one(c.accept, stats + kAccept);
     flush_one(c.pair_tests, stats + kPairTests);
     flush_one(c.pair_fp64, stats + kPairFp64);
+}
+
+// One 64-bit atomic per work-group and counter: the waves' sums meet in LDS
+// (lds: at least 4 x kNumStats words, free to overwrite).  Every thread of
+// the work-group must call (contains barriers); at most 16 waves.
+__device__ __forceinline__ void flush_block(const Counters& c, uint32_t* lds, unsigned long long* stats) {
+    const uint32_t v[kNumStats] = {c.attempted, c.attempted_rot, c.cell_reject, c.overlap_reject,
+                                   c.accept, c.pair_tests, c.pair_fp64};
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    uint32_t s[kNumStats];
+#pragma unroll
+    for (int k = 0; k < kNumStats; ++k) s[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (__lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < kNumStats; ++k) lds[wave * kNumStats + k] = s[k];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kNumStats) {
+        unsigned long long t = 0;
+        for (int w = 0; w < nwaves; ++w) t += lds[w * kNumStats + threadIdx.x];
+        if (t) atomicAdd(stats + threadIdx.x, t);
+    }
 }
 
 __device__ __forceinline__ void wave_sync() {

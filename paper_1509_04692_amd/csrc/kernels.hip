@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                      select, t, k0, k1, sh, a0, n_act,
                                      wave_scratch(scratch_words[wave]), ct);
     }
-    flush(ct, stats + (size_t)r * kNumStats);
+    flush_block(ct, &scratch_words[0][0], stat_stripe(stats, r));
 }
 
 template <int KIND>
@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     if constexpr (RES >= 2) {
         for (int k = tid; k < NC * N; k += B) gori[k] = ori[k];
     }
-    flush(ct, stats + (size_t)r * kNumStats);
+    flush(ct, stat_stripe(stats, r));
 }
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,7 @@ constexpr int kBatchBlock = 1024;  // lanes per persistent work-group (16 waves)
 struct Workspace {
     SpeciesDev* species;              // one per replica
     SysDev* sys;                      // one per replica
-    unsigned long long* stats;        // n_replicas x kNumStats
+    unsigned long long* stats;        // n_replicas x kStatStripes x kStatStride
     unsigned long long* overlap_out;  // n_replicas
     // global-memory cell list, sized for the largest grid-path replica
     uint32_t* count;    // ncells

@@ -18,6 +18,14 @@ constexpr int xs_bytes(int dim) { return dim == 3 ? 16 : 8; }
 enum Stat : int { kAttempted = 0, kAttemptedRot, kCellReject, kOverlapReject, kAccept,
                   kPairTests, kPairFp64, kNumStats };
 
+// The counters of a replica are kept in kStatStripes copies, one 64-byte line
+// each; a work-group adds into stripe blockIdx % kStatStripes, so that
+// thousands of work-groups of one pass do not serialise on one line.  Readers
+// sum the stripes.
+constexpr int kStatStripes = 64;
+constexpr int kStatStride = 8;  // u64 per stripe (kNumStats used)
+constexpr int kStatsPerReplica = kStatStripes * kStatStride;
+
 // One particle type, built on the host at init.  Vertex coordinates are
 // stored per axis so that a uniform loop over vertices reads scalars.
 struct alignas(16) SpeciesDev {
