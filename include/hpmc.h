@@ -146,6 +146,19 @@ int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
  * (persistent). */
 int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
 
+/* Histogram of pair separations of one replica, the sampling behind the
+ * pressure check of Sec. 4 (the contact value of g(r) for disks, Table 1):
+ * out[b] = number of unordered pairs i < k with
+ * edges2[b] <= r^2 < edges2[b + 1], r the minimum-image centre separation in
+ * binary64 (x^2 + y^2 (+ z^2), the circumsphere test's expression).
+ * edges2: host, n_bins + 1 strictly increasing squared distances, edges2[0]
+ * >= 0, 1 <= n_bins <= 64, edges2[n_bins] below (2 w)^2 with w the cell
+ * width (below w^2 when the grid has fewer than 5 cells per side), else
+ * HPMC_ERR_UNSUPPORTED.  out: host, n_bins counts.  Reads the caller's
+ * position array; synchronising. */
+int hpmc_pair_histogram(hpmc_state *st, int32_t replica, const double *edges2, int32_t n_bins,
+                        uint64_t *out);
+
 /* Unordered overlapping pairs per replica under the exact FP64 predicate
  * (circumsphere test and full test, the paper's system-level check, Sec. 4).
  * out_per_replica: host, n_replicas entries.  Synchronising. */

@@ -23,6 +23,7 @@ from .oracle import (  # noqa: F401
     index,
     load_counting,
     overlap_full,
+    pair_histogram,
     pair_overlaps,
     philox4x32_10,
     reset_events,

@@ -892,6 +892,35 @@ int or_sweep(const or_species *sp, int32_t N, double L, double *pos, double *ori
     return OR_OK;
 }
 
+int or_pair_histogram(int32_t dim, int32_t N, double L, const double *pos,
+                      const double *edges2, int32_t n_bins, int64_t *out)
+{
+    if ((dim != 2 && dim != 3) || N < 0 || !(L > 0.0) || n_bins < 1 || !edges2 || !out)
+        return OR_ERR_INVALID_ARG;
+    for (int b = 0; b < n_bins; ++b)
+        if (!(edges2[b] < edges2[b + 1]))
+            return OR_ERR_INVALID_ARG;
+    grid_t g;
+    memset(&g, 0, sizeof(g));
+    g.L = L;
+    g.inv_L = 1.0 / L;
+    for (int b = 0; b < n_bins; ++b)
+        out[b] = 0;
+    for (int i = 0; i < N; ++i)
+        for (int k = i + 1; k < N; ++k) {
+            double r[3] = { 0.0, 0.0, 0.0 };
+            for (int a = 0; a < dim; ++a)
+                r[a] = min_image(&g, pos[a * N + k] - pos[a * N + i]);
+            double r2 = r[0] * r[0] + r[1] * r[1];
+            if (dim == 3)
+                r2 = r2 + r[2] * r[2];
+            for (int b = 0; b < n_bins; ++b)
+                if (edges2[b] <= r2 && r2 < edges2[b + 1])
+                    ++out[b];
+        }
+    return OR_OK;
+}
+
 int64_t or_count_overlaps(const or_species *sp, int32_t N, double L, const double *pos,
                           const double *orient)
 {

@@ -80,6 +80,14 @@ int or_pair_overlaps(const or_species *sp, const double *r, const double *qa,
 int64_t or_count_overlaps(const or_species *sp, int32_t N, double L,
                           const double *pos, const double *orient);
 
+/* Histogram of pair separations, the sampling behind the pressure check of
+ * Sec. 4 (contact value of g(r)): out[b] = number of unordered pairs i < k
+ * with edges2[b] <= r^2 < edges2[b+1], r the minimum-image separation of
+ * particle k from particle i, r^2 = (x^2 + y^2) (+ z^2).  edges2: n_bins + 1
+ * ascending squared distances.  Every pair is visited (no cell list). */
+int or_pair_histogram(int32_t dim, int32_t N, double L, const double *pos,
+                      const double *edges2, int32_t n_bins, int64_t *out);
+
 /* n_sweeps checkerboard sweeps of one system, sweep counter t0, t0+1, ...
  * Updates pos / orient in place and ADDS to stats[OR_NSTATS]. */
 int or_sweep(const or_species *sp, int32_t N, double L, double *pos,

@@ -77,6 +77,9 @@ def _declare(lib):
     lib.or_overlap_full.restype = ctypes.c_int
     lib.or_pair_overlaps.argtypes = [sp, _P_D, _P_D, _P_D]
     lib.or_pair_overlaps.restype = ctypes.c_int
+    lib.or_pair_histogram.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P_D, _P_D,
+                                      ctypes.c_int32, _P_I64]
+    lib.or_pair_histogram.restype = ctypes.c_int
     lib.or_count_overlaps.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D]
     lib.or_count_overlaps.restype = ctypes.c_int64
     lib.or_sweep.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D,
@@ -237,6 +240,18 @@ def count_overlaps(sp, L, pos, orient=None, lib=None):
     N, pos, orient = _state(sp, pos, orient)
     return int(_check((lib or load()).or_count_overlaps(ctypes.byref(s), N, float(L), _dptr(pos),
                                                         _dptr(orient)), "count_overlaps"))
+
+
+def pair_histogram(L, pos, edges2, lib=None):
+    """Counts of unordered pairs with edges2[b] <= r^2 < edges2[b+1] (minimum
+    image); pos is (dim, N) float64."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    edges2 = np.ascontiguousarray(edges2, dtype=np.float64)
+    out = np.zeros(len(edges2) - 1, dtype=np.int64)
+    _check((lib or load()).or_pair_histogram(pos.shape[0], pos.shape[1], float(L), _dptr(pos),
+                                             _dptr(edges2), len(out),
+                                             out.ctypes.data_as(_P_I64)), "pair_histogram")
+    return out
 
 
 def sweep(sp, L, pos, orient, seed, n_sweeps, t0=0, replica=0, lib=None):

@@ -173,7 +173,8 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
 }
 
 struct Layout {
-    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, xs, partial, list,
+    size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, xs, hist_edges,
+        hist_out, partial, list,
         clock, backup_pos, backup_ori, backup_stats, total;
     size_t pos_total, ori_total;
 };
@@ -284,6 +285,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.slot_of = take(4 * (size_t)n_max);
     lay.members = take(4 * (size_t)n_max);
     lay.xs = take((size_t)xs_max);
+    lay.hist_edges = take(sizeof(double) * (kMaxHistBins + 1));
+    lay.hist_out = take(sizeof(unsigned long long) * kMaxHistBins);
     lay.partial = take(4 * (size_t)ntiles);
     lay.list = take(4 * (size_t)R);
     lay.clock = take(sizeof(Clock));
@@ -446,6 +449,8 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->ws.slot_of = (uint32_t*)(base + lay.slot_of);
     st->ws.members = (uint32_t*)(base + lay.members);
     st->ws.xs = (float*)(base + lay.xs);
+    st->ws.hist_edges = (double*)(base + lay.hist_edges);
+    st->ws.hist_out = (unsigned long long*)(base + lay.hist_out);
     st->ws.partial = (uint32_t*)(base + lay.partial);
     st->ws.batch_list = (int32_t*)(base + lay.list);
     st->ws.clock = (Clock*)(base + lay.clock);
@@ -517,6 +522,36 @@ int hpmc_sweep(hpmc_state* st, uint64_t n_sweeps, uint64_t seed) {
 int hpmc_count_overlaps(hpmc_state* st, uint64_t* out_per_replica) {
     if (st == nullptr || out_per_replica == nullptr) return HPMC_ERR_INVALID_ARG;
     return count_all(st, out_per_replica);
+}
+
+int hpmc_pair_histogram(hpmc_state* st, int32_t replica, const double* edges2, int32_t n_bins,
+                        uint64_t* out) {
+    if (st == nullptr || edges2 == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
+    if (replica < 0 || replica >= st->n_replicas || n_bins < 1 || n_bins > kMaxHistBins)
+        return HPMC_ERR_INVALID_ARG;
+    if (!(edges2[0] >= 0.0)) return HPMC_ERR_INVALID_ARG;
+    for (int b = 0; b < n_bins; ++b)
+        if (!(edges2[b] < edges2[b + 1]) || !std::isfinite(edges2[b + 1])) return HPMC_ERR_INVALID_ARG;
+    // pairs closer than reach cell widths lie within `reach` cells of each other
+    const ReplicaHost& rh = st->rep[replica];
+    const double w = st->sys[replica].w;
+    const double guard = 1.0 - 0x1p-30;
+    int reach = 0;
+    if (edges2[n_bins] <= w * w * guard)
+        reach = 1;
+    else if (edges2[n_bins] <= 4.0 * w * w * guard && rh.n >= 5)
+        reach = 2;
+    else
+        return HPMC_ERR_UNSUPPORTED;
+    int rc = check_hip(st, hipMemcpyAsync(st->ws.hist_edges, edges2, sizeof(double) * (n_bins + 1),
+                                          hipMemcpyHostToDevice, st->stream));
+    if (!rc) rc = check_hip(st, build_cells(st->ws, rh, replica, st->pos, 0, st->stream));
+    if (!rc) rc = check_hip(st, pair_histogram(st->ws, rh, replica, st->pos, n_bins, reach, st->stream));
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(out, st->ws.hist_out, sizeof(uint64_t) * n_bins,
+                                          hipMemcpyDeviceToHost, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    return rc;
 }
 
 int hpmc_get_stats(hpmc_state* st, hpmc_stats* out) {

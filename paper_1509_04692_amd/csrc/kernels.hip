@@ -288,6 +288,60 @@ __global__ void __launch_bounds__(256) k_count(const SysDev* __restrict__ sys,
     if (__lane_id() == 0 && s) atomicAdd(out + r, (unsigned long long)s);
 }
 
+// Histogram of pair separations (pairs i < k with edges2[b] <= r^2 <
+// edges2[b + 1]) over the unshifted cell list; cells within `reach` of the
+// particle's cell are searched (edges2[n_bins] < (reach * w)^2 keeps the
+// search complete).  One LDS histogram per work-group, one atomic per bin.
+template <int D>
+__global__ void __launch_bounds__(256) k_pair_hist(const SysDev* __restrict__ sys, int r,
+                                                   const double* __restrict__ pos_base,
+                                                   const uint32_t* __restrict__ start,
+                                                   const uint32_t* __restrict__ members,
+                                                   const uint32_t* __restrict__ cell_of,
+                                                   const double* __restrict__ edges2, int n_bins,
+                                                   int reach, unsigned long long* __restrict__ out) {
+    __shared__ uint32_t hist[kMaxHistBins];
+    const SysDev S = sys[r];
+    const double* pos = pos_base + S.pos_off;
+    const int N = S.N, n = S.n;
+    for (int b = threadIdx.x; b < n_bins; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        const uint32_t c = cell_of[i];
+        const int cc[3] = {(int)(c % (uint32_t)n), (int)((c / (uint32_t)n) % (uint32_t)n),
+                           (int)(c / ((uint32_t)n * (uint32_t)n))};
+        double xi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < D; ++a) xi[a] = pos[a * N + i];
+        const double lo = edges2[0], hi = edges2[n_bins];
+        const int zlo = D == 3 ? -reach : 0, zhi = D == 3 ? reach : 0;
+        for (int oz = zlo; oz <= zhi; ++oz)
+            for (int oy = -reach; oy <= reach; ++oy)
+                for (int ox = -reach; ox <= reach; ++ox) {
+                    const int x = (cc[0] + ox + n) % n, y = (cc[1] + oy + n) % n,
+                              z = D == 3 ? (cc[2] + oz + n) % n : 0;
+                    const uint32_t cn = (uint32_t)(x + n * (y + n * z));
+                    for (uint32_t p = start[cn]; p < start[cn + 1]; ++p) {
+                        const uint32_t k = members[p];
+                        if (k <= (uint32_t)i) continue;
+                        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int a = 0; a < D; ++a) rr[a] = min_image(pos[a * N + k] - xi[a], S.L, S.inv_L);
+                        double r2 = rr[0] * rr[0] + rr[1] * rr[1];
+                        if constexpr (D == 3) r2 = r2 + rr[2] * rr[2];
+                        if (!(lo <= r2 && r2 < hi)) continue;
+                        int b = 0;
+                        while (b + 1 < n_bins && edges2[b + 1] <= r2) ++b;
+                        atomicAdd(hist + b, 1u);
+                    }
+                }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+        if (hist[b]) atomicAdd(out + b, (unsigned long long)hist[b]);
+}
+
 // ---------------------------------------------------------------------------
 // Persistent path: one work-group owns one replica and runs whole sweeps.
 // LDS (dynamic), in this order: positions D*N f64 (residency >= 1),
@@ -583,6 +637,22 @@ hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* p
     if (precision == 1)
         return launch_batch_res<kPolyhedron, 1, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
     return launch_batch_res<kPolyhedron, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+}
+
+hipError_t pair_histogram(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                          int n_bins, int reach, hipStream_t stream) {
+    const int N = rh.N;
+    hipError_t e = fill_u64(ws.hist_out, 0ull, (size_t)n_bins, stream);
+    if (e != hipSuccess) return e;
+    if (rh.dim == 3)
+        k_pair_hist<3><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.start, ws.members,
+                                                               ws.cell_of, ws.hist_edges, n_bins,
+                                                               reach, ws.hist_out);
+    else
+        k_pair_hist<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.start, ws.members,
+                                                               ws.cell_of, ws.hist_edges, n_bins,
+                                                               reach, ws.hist_out);
+    return hipGetLastError();
 }
 
 hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,

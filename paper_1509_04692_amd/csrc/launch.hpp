@@ -23,6 +23,8 @@ struct Workspace {
     uint32_t* slot_of;  // N
     uint32_t* members;  // N
     float* xs;          // N cell-sorted binary32 coordinates (2 or 4 floats each)
+    double* hist_edges;             // kMaxHistBins + 1 squared bin edges
+    unsigned long long* hist_out;   // kMaxHistBins pair counts
     uint32_t* partial;  // scan tiles
     int32_t* batch_list;  // replica indices of the persistent path, grouped by kind
     Clock* clock;         // sweep counter and key read by the kernels
@@ -77,6 +79,9 @@ hipError_t count_pairs(const Workspace& ws, const ReplicaHost& rh, int r, const 
 
 // Invalid particles of replica r (coordinate outside [0, L), non-finite
 // orientation) added to ws.overlap_out[r].
+// Pair-separation histogram of replica r (edges already in ws.hist_edges).
+hipError_t pair_histogram(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                          int n_bins, int reach, hipStream_t stream);
 hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
                           const double* orient, hipStream_t stream);
 

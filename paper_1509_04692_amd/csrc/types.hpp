@@ -7,6 +7,7 @@ namespace hpmc {
 
 constexpr int kMaxPolyVerts = 8;     // polygons: 3..8 vertices
 constexpr int kMaxPolyhedronVerts = 64;
+constexpr int kMaxHistBins = 64;     // pair-separation histogram
 
 enum Kind : int32_t { kDisk = 0, kPolygon = 1, kPolyhedron = 2 };
 

@@ -148,6 +148,16 @@ class System:
         self._check(self._lib.hpmc_count_overlaps(self._handle, out), "hpmc_count_overlaps")
         return np.array(out[:], dtype=np.uint64)
 
+    def pair_histogram(self, edges2, r=0):
+        """Counts of unordered pairs of replica r with edges2[b] <= |r|^2 <
+        edges2[b+1] (minimum image); edges2 ascending squared distances."""
+        e = np.ascontiguousarray(np.asarray(edges2, dtype=np.float64))
+        out = (ctypes.c_uint64 * (len(e) - 1))()
+        self._check(self._lib.hpmc_pair_histogram(self._handle, int(r),
+                                                  e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                  len(e) - 1, out), "hpmc_pair_histogram")
+        return np.array(out[:], dtype=np.uint64)
+
     def stats(self):
         out = (_lib.Stats * self.n_replicas)()
         self._check(self._lib.hpmc_get_stats(self._handle, out), "hpmc_get_stats")

@@ -209,6 +209,38 @@ def test_count_overlaps_matches_oracle_on_overlapping_states(kind):
     assert int(system.count_overlaps()[0]) == want
 
 
+@pytest.mark.parametrize("kind", ["disk", "pentagon", "cube"])
+def test_pair_histogram_matches_oracle(kind):
+    """Pair-separation counts (the pressure sampling of Sec. 4) on random
+    positions written to the device, bins reaching one and two cell widths;
+    the second replica of a two-replica state checks the replica offsets."""
+    import torch
+    from paper_1509_04692_amd import _lib
+    rng = np.random.Generator(np.random.PCG64(43))
+    if kind == "disk":
+        sp, N, L, pos, orient = inputs.workload_disks_256()
+    elif kind == "pentagon":
+        sp, N, L, pos, orient = inputs.workload_pentagons(1000, 0.6)
+    else:
+        sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
+    announce(f"pair histogram {kind}")
+    system = _system([sp, sp], [N, N], [L, L], [pos, pos], [orient, orient], path="grid")
+    n = system.replica_info(1)["n"]
+    w = L / n
+    rnd = np.ascontiguousarray(rng.uniform(0, L, size=pos.shape))
+    dim = pos.shape[0]
+    system.pos[dim * N:].copy_(torch.from_numpy(rnd.ravel()))
+    for top in (0.999 * w, 1.99 * w):
+        edges2 = np.linspace(0.2 * w, top, 17) ** 2
+        got = system.pair_histogram(edges2, r=1)
+        want = oracle.pair_histogram(L, rnd, edges2)
+        assert list(got) == [int(x) for x in want], top
+        assert want.sum() > 0
+    with pytest.raises(_lib.HpmcError) as err:
+        system.pair_histogram(np.array([0.0, (2.01 * w) ** 2]), r=1)
+    assert err.value.code == -7
+
+
 def test_initial_overlap_and_box_errors():
     from paper_1509_04692_amd._lib import HpmcError
     sp, N, L, pos, orient = inputs.workload_disks_256()
