@@ -229,12 +229,25 @@ __device__ __forceinline__ uint32_t particle_cell(const SysDev& S, const POS& po
     return cell_of_grid<D>(S, y);
 }
 
+// floor(a / m) for 0 <= a < 2^30 through a binary64 reciprocal (within one
+// of the quotient, then corrected): cheaper than an integer division.
+__device__ __forceinline__ int div_floor(int a, int m, double inv_m) {
+    int q = (int)((double)a * inv_m);
+    q -= q * m > a ? 1 : 0;
+    q += (q + 1) * m <= a ? 1 : 0;
+    return q;
+}
+
+// Cell of active index a in colour `colour`: the active cells of a colour
+// are every other cell along each axis, offset by the colour's bits.
 __device__ __forceinline__ void active_cell(const SysDev& S, int D, uint32_t colour, int a,
-                                            int (&cc)[3], uint32_t& c) {
+                                            double inv_half, int (&cc)[3], uint32_t& c) {
     const int half = S.n / 2;
-    cc[0] = 2 * (a % half) + (int)(colour & 1u);
-    cc[1] = 2 * ((a / half) % half) + (int)((colour >> 1) & 1u);
-    cc[2] = D == 3 ? 2 * (a / (half * half)) + (int)((colour >> 2) & 1u) : 0;
+    const int q1 = div_floor(a, half, inv_half);
+    const int q2 = D == 3 ? div_floor(q1, half, inv_half) : 0;
+    cc[0] = 2 * (a - q1 * half) + (int)(colour & 1u);
+    cc[1] = 2 * (q1 - q2 * half) + (int)((colour >> 1) & 1u);
+    cc[2] = D == 3 ? 2 * q2 + (int)((colour >> 2) & 1u) : 0;
     c = (uint32_t)(cc[0] + S.n * (cc[1] + S.n * cc[2]));
 }
 
@@ -462,7 +475,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     double qn[4] = {1.0, 0.0, 0.0, 0.0};
     bool c_rot = false, c_moved = false;  // rotation attempted / translation attempted
     if (sub == 0 && a < n_act) {
-        active_cell(S, D, colour, a, cc, c);
+        active_cell(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
         const uint32_t beg = cl.begin(c), fin = cl.end(c);
         if (beg != fin) {
             ct.attempted++;

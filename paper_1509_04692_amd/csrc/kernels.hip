@@ -428,11 +428,30 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         const uint32_t t = t0 + sw;
         double sh[3];
         grid_shift(S, t, k0, k1, 1, sh);
-        // counting sort of the shifted grid (ascending tags within a cell)
+        // counting sort of the shifted grid (ascending tags within a cell); the
+        // first kOwn particles of each thread keep their cell and binary32
+        // shifted-frame coordinates in registers between the passes
+        constexpr int kOwn = 4;
+        uint32_t own_cell[kOwn];
+        float own_y[kOwn][3];
         uint32_t* count = uni;
         for (int c = tid; c < nc; c += B) count[c] = 0u;
         __syncthreads();
-        for (int i = tid; i < N; i += B) atomicAdd(count + particle_cell<D>(S, pos, (uint32_t)i, sh), 1u);
+#pragma unroll
+        for (int j = 0; j < kOwn; ++j) {
+            const int i = tid + j * B;
+            own_cell[j] = 0u;
+            own_y[j][0] = own_y[j][1] = own_y[j][2] = 0.0f;
+            if (i < N) {
+                double y[3];
+                particle_grid<D>(S, pos, (uint32_t)i, sh, y);
+                own_cell[j] = cell_of_grid<D>(S, y);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) own_y[j][a] = (float)y[a];
+                atomicAdd(count + own_cell[j], 1u);
+            }
+        }
+        for (int i = tid + kOwn * B; i < N; i += B) atomicAdd(count + particle_cell<D>(S, pos, (uint32_t)i, sh), 1u);
         __syncthreads();
         {
             const int c0 = tid * chunk, c1 = min(nc, c0 + chunk);
@@ -447,27 +466,43 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             }
         }
         __syncthreads();
-        for (int i = tid; i < N; i += B)
-            mem[atomicAdd(count + particle_cell<D>(S, pos, (uint32_t)i, sh), 1u)] = (uint16_t)i;
+        // scatter the tags and their binary32 coordinates
+#pragma unroll
+        for (int j = 0; j < kOwn; ++j) {
+            const int i = tid + j * B;
+            if (i < N) {
+                const uint32_t slot = atomicAdd(count + own_cell[j], 1u);
+                mem[slot] = (uint16_t)i;
+                xs.store(slot, own_y[j]);
+            }
+        }
+        for (int i = tid + kOwn * B; i < N; i += B) {
+            double y[3];
+            particle_grid<D>(S, pos, (uint32_t)i, sh, y);
+            const uint32_t slot = atomicAdd(count + cell_of_grid<D>(S, y), 1u);
+            mem[slot] = (uint16_t)i;
+            xs.store(slot, y);
+        }
         __syncthreads();
+        // ascending tags within each cell; the coordinates move with their tags
         for (int c = tid; c < nc; c += B) {
             const uint32_t b = c ? count[c - 1] : 0u, e = count[c];
             ends[c] = (uint16_t)e;
             for (uint32_t p = b + 1; p < e; ++p) {
                 const uint16_t v = mem[p];
+                float vy[3];
+                xs.load(p, vy);
                 uint32_t q = p;
                 while (q > b && mem[q - 1] > v) {
                     mem[q] = mem[q - 1];
+                    float m[3];
+                    xs.load(q - 1, m);
+                    xs.store(q, m);
                     --q;
                 }
                 mem[q] = v;
+                xs.store(q, vy);
             }
-        }
-        __syncthreads();
-        for (int p = tid; p < N; p += B) {
-            double y[3];
-            particle_grid<D>(S, pos, mem[p], sh, y);
-            xs.store((uint32_t)p, y);
         }
         __syncthreads();
         const LdsCells cl{ends, mem};
