@@ -174,7 +174,7 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
 
 struct Layout {
     size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, xs, hist_edges,
-        hist_out, partial, list,
+        hist_out, partial, list, ident,
         clock, backup_pos, backup_ori, backup_stats, total;
     size_t pos_total, ori_total;
 };
@@ -201,7 +201,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     sys.assign(R, SysDev{});
     spc.assign(R, SpeciesDev{});
     int64_t pos_off = 0, ori_off = 0;
-    int64_t nc_max = 1, n_max = 1, xs_max = 16;
+    int64_t cell_total = 0, slot_total = 0, part_total = 0;
     bool fits_lds = true;
     for (int r = 0; r < R; ++r) {
         int rc = build_species(a->species[r], spc[r]);
@@ -217,9 +217,13 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         const int ncomp = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
         pos_off += (int64_t)sys[r].dim * sys[r].N;
         ori_off += (int64_t)ncomp * sys[r].N;
-        nc_max = std::max<int64_t>(nc_max, sys[r].ncells);
-        n_max = std::max<int64_t>(n_max, sys[r].N);
-        xs_max = std::max<int64_t>(xs_max, (int64_t)sys[r].N * xs_bytes(sys[r].dim));
+        // this replica's slice of the global cell lists
+        sys[r].cell_off = cell_total;
+        sys[r].slot_off = slot_total;
+        sys[r].part_off = part_total;
+        cell_total += (int64_t)sys[r].ncells + 1;
+        slot_total += sys[r].N;
+        part_total += ((int64_t)sys[r].ncells + kScanTile - 1) / kScanTile;
         const int ncomp_r = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
         const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, sys[r].ncells, sys[r].N, 0);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
@@ -267,8 +271,33 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
             if (g.nv < 0) g.nv = 0;
             groups.push_back(g);
         }
+    } else {
+        // grid path: one launch per step for all replicas of a kind
+        for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
+            BatchGroup g{kind, (int32_t)list.size(), 0, 0, -1, 0, {0, 0, 0}, 0, 1, 0, 0, 0, 0};
+            int64_t n_act_total = 0;
+            for (int r = 0; r < R; ++r) {
+                if (spc[r].kind != kind) continue;
+                list.push_back(r);
+                g.count++;
+                g.nv = (g.nv == -1 || g.nv == spc[r].nv) ? spc[r].nv : 0;
+                g.dim = sys[r].dim;
+                const int half = sys[r].n / 2;
+                const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
+                g.rounds_max = std::max<int32_t>(g.rounds_max, sys[r].rounds);
+                g.n_max = std::max<int64_t>(g.n_max, sys[r].N);
+                g.nc_max = std::max<int64_t>(g.nc_max, sys[r].ncells);
+                g.n_act_max = std::max<int64_t>(g.n_act_max, n_act);
+                n_act_total += n_act;
+            }
+            if (g.count == 0) continue;
+            if (g.nv < 0) g.nv = 0;
+            g.lanes = choose_lanes_per_cell(n_act_total);
+            for (int r : list)
+                if (spc[r].kind == kind) rep[r].lanes_per_cell = g.lanes;
+            groups.push_back(g);
+        }
     }
-    const int64_t ntiles = (nc_max + kScanTile - 1) / kScanTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -279,16 +308,17 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.sys = take(sizeof(SysDev) * R);
     lay.stats = take(sizeof(unsigned long long) * kStatsPerReplica * R);
     lay.overlap = take(sizeof(unsigned long long) * R);
-    lay.count = take(4 * (size_t)nc_max);
-    lay.start = take(4 * ((size_t)nc_max + 1));
-    lay.cell_of = take(4 * (size_t)n_max);
-    lay.slot_of = take(4 * (size_t)n_max);
-    lay.members = take(4 * (size_t)n_max);
-    lay.xs = take((size_t)xs_max);
+    lay.count = take(4 * (size_t)cell_total);
+    lay.start = take(4 * (size_t)cell_total);
+    lay.cell_of = take(4 * (size_t)slot_total);
+    lay.slot_of = take(4 * (size_t)slot_total);
+    lay.members = take(4 * (size_t)slot_total);
+    lay.xs = take(sizeof(float) * kXsStride * (size_t)slot_total);
     lay.hist_edges = take(sizeof(double) * (kMaxHistBins + 1));
     lay.hist_out = take(sizeof(unsigned long long) * kMaxHistBins);
-    lay.partial = take(4 * (size_t)ntiles);
+    lay.partial = take(4 * (size_t)(part_total > 0 ? part_total : 1));
     lay.list = take(4 * (size_t)R);
+    lay.ident = take(4 * (size_t)R);
     lay.clock = take(sizeof(Clock));
     lay.pos_total = (size_t)pos_off;
     lay.ori_total = (size_t)ori_off;
@@ -303,7 +333,7 @@ int count_all(hpmc_state* st, uint64_t* out) {
     int rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
     if (rc) return rc;
     for (int r = 0; r < st->n_replicas; ++r) {
-        rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, 0, st->stream));
+        rc = check_hip(st, build_cells_one(st->ws, st->rep[r], r, st->pos, 0, st->stream));
         if (rc) return rc;
         rc = check_hip(st, count_pairs(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
         if (rc) return rc;
@@ -326,9 +356,11 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
         }
         return check_hip(st, advance_clock(st->ws, chunk, s));
     }
-    for (int r = 0; r < st->n_replicas && !rc; ++r) {
-        rc = check_hip(st, build_cells(st->ws, st->rep[r], r, st->pos, 1, s));
-        if (!rc) rc = check_hip(st, grid_passes(st->ws, st->rep[r], r, st->pos, st->orient, st->precision, s));
+    for (const BatchGroup& g : st->groups) {
+        if (rc) break;
+        rc = check_hip(st, build_cells(st->ws, st->ws.batch_list + g.first, g.count, g.dim, g.n_max,
+                                       g.nc_max, st->pos, 1, s));
+        if (!rc) rc = check_hip(st, grid_passes(st->ws, g, st->pos, st->orient, st->precision, s));
     }
     if (!rc) rc = check_hip(st, advance_clock(st->ws, 1, s));
     return rc;
@@ -453,6 +485,7 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->ws.hist_out = (unsigned long long*)(base + lay.hist_out);
     st->ws.partial = (uint32_t*)(base + lay.partial);
     st->ws.batch_list = (int32_t*)(base + lay.list);
+    st->ws.ident = (int32_t*)(base + lay.ident);
     st->ws.clock = (Clock*)(base + lay.clock);
     st->ws.backup_pos = (double*)(base + lay.backup_pos);
     st->ws.backup_ori = (double*)(base + lay.backup_ori);
@@ -470,13 +503,19 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     if (!rc && !list.empty())
         rc = check_hip(st, hipMemcpyAsync(st->ws.batch_list, list.data(), sizeof(int32_t) * list.size(),
                                           hipMemcpyHostToDevice, st->stream));
+    std::vector<int32_t> ident(st->n_replicas);
+    for (int r = 0; r < st->n_replicas; ++r) ident[r] = r;
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(st->ws.ident, ident.data(), sizeof(int32_t) * ident.size(),
+                                          hipMemcpyHostToDevice, st->stream));
     if (!rc)
         rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kStatsPerReplica * st->n_replicas,
                                     st->stream));
     if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
-    for (const BatchGroup& g : st->groups)
-        if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0,
-                                                      true, st->stream));
+    if (st->path == HPMC_PATH_PERSISTENT)
+        for (const BatchGroup& g : st->groups)
+            if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0,
+                                                          true, st->stream));
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
     if (!rc) {  // positions in [0, L) and finite orientations, before any cell lookup
         std::vector<uint64_t> bad(st->n_replicas, 0);
@@ -545,7 +584,7 @@ int hpmc_pair_histogram(hpmc_state* st, int32_t replica, const double* edges2, i
         return HPMC_ERR_UNSUPPORTED;
     int rc = check_hip(st, hipMemcpyAsync(st->ws.hist_edges, edges2, sizeof(double) * (n_bins + 1),
                                           hipMemcpyHostToDevice, st->stream));
-    if (!rc) rc = check_hip(st, build_cells(st->ws, rh, replica, st->pos, 0, st->stream));
+    if (!rc) rc = check_hip(st, build_cells_one(st->ws, rh, replica, st->pos, 0, st->stream));
     if (!rc) rc = check_hip(st, pair_histogram(st->ws, rh, replica, st->pos, n_bins, reach, st->stream));
     if (!rc)
         rc = check_hip(st, hipMemcpyAsync(out, st->ws.hist_out, sizeof(uint64_t) * n_bins,
@@ -657,6 +696,7 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
             }
         } else {
             for (ReplicaHost& rh : st->rep) rh.lanes_per_cell = c;
+            for (BatchGroup& g : st->groups) g.lanes = c;
         }
         capture_graph(st);
     };

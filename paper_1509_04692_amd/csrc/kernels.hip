@@ -49,11 +49,6 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // ---------------------------------------------------------------------------
 // Grid path: global cell list.
 // ---------------------------------------------------------------------------
-__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 __global__ void k_fill_u64(unsigned long long* __restrict__ p, unsigned long long v, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -67,22 +62,35 @@ __global__ void k_advance_clock(Clock* __restrict__ clock, uint32_t n) {
     if (threadIdx.x == 0) clock->t += n;
 }
 
+// Global cell lists of the grid path.  Every kernel below serves the
+// replicas list[0 .. gridDim.y): blockIdx.y picks the replica, whose slice
+// of the arrays starts at the offsets in its SysDev; blocks beyond the
+// replica's size return at once (whole blocks, before any barrier).
+__global__ void __launch_bounds__(256) k_zero_counts(const SysDev* __restrict__ sys,
+                                                     const int32_t* __restrict__ list,
+                                                     uint32_t* __restrict__ count) {
+    const SysDev S = sys[list[blockIdx.y]];
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < S.ncells) count[S.cell_off + c] = 0u;
+}
+
 template <int D>
-__global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys, int r,
+__global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys,
+                                                const int32_t* __restrict__ list,
                                                 const double* __restrict__ pos_base,
                                                 const Clock* __restrict__ clock, int shifted,
                                                 uint32_t* __restrict__ count,
                                                 uint32_t* __restrict__ cell_of,
                                                 uint32_t* __restrict__ slot_of) {
-    const SysDev S = sys[r];
+    const SysDev S = sys[list[blockIdx.y]];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N) return;
     const Clock ck = *clock;
     double sh[3];
     grid_shift(S, ck.t, ck.k0, ck.k1, shifted, sh);
     const uint32_t c = particle_cell<D>(S, PosView{const_cast<double*>(pos_base) + S.pos_off, S.N}, (uint32_t)i, sh);
-    cell_of[i] = c;
-    slot_of[i] = atomicAdd(count + c, 1u);
+    cell_of[S.slot_off + i] = c;
+    slot_of[S.slot_off + i] = atomicAdd(count + S.cell_off + c, 1u);
 }
 
 // Counts particles of replica r with a coordinate outside [0, L) or a
@@ -109,112 +117,142 @@ __global__ void __launch_bounds__(256) k_validate(const SysDev* __restrict__ sys
 }
 
 // Tile sums of the cell histogram (kScanTile cells per 256-lane work-group).
-__global__ void __launch_bounds__(256) k_scan_tiles(const uint32_t* __restrict__ count, int nc,
+__global__ void __launch_bounds__(256) k_scan_tiles(const SysDev* __restrict__ sys,
+                                                    const int32_t* __restrict__ list,
+                                                    const uint32_t* __restrict__ count,
                                                     uint32_t* __restrict__ partial) {
     __shared__ uint32_t sm[16];
+    const SysDev S = sys[list[blockIdx.y]];
+    const int nc = S.ncells;
+    if ((int)blockIdx.x * kScanTile >= nc) return;
+    const uint32_t* cnt = count + S.cell_off;
     const int base = blockIdx.x * kScanTile + threadIdx.x * 8;
     uint32_t s = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += base + j < nc ? count[base + j] : 0u;
+    for (int j = 0; j < 8; ++j) s += base + j < nc ? cnt[base + j] : 0u;
     uint32_t total;
     block_exclusive_scan(s, sm, total);
-    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+    if (threadIdx.x == 0) partial[S.part_off + blockIdx.x] = total;
 }
 
-// Exclusive scan of the tile sums in place (one work-group).
-__global__ void __launch_bounds__(256) k_scan_partials(uint32_t* __restrict__ partial, int ntiles) {
+// Exclusive scan of a replica's tile sums in place (one work-group each).
+__global__ void __launch_bounds__(256) k_scan_partials(const SysDev* __restrict__ sys,
+                                                       const int32_t* __restrict__ list,
+                                                       uint32_t* __restrict__ partial) {
     __shared__ uint32_t sm[16];
+    const SysDev S = sys[list[blockIdx.y]];
+    const int ntiles = (S.ncells + kScanTile - 1) / kScanTile;
+    uint32_t* part = partial + S.part_off;
     uint32_t carry = 0;
     for (int base = 0; base < ntiles; base += blockDim.x) {
         const int j = base + threadIdx.x;
-        const uint32_t v = j < ntiles ? partial[j] : 0u;
+        const uint32_t v = j < ntiles ? part[j] : 0u;
         uint32_t total;
         const uint32_t ex = block_exclusive_scan(v, sm, total);
-        if (j < ntiles) partial[j] = carry + ex;
+        if (j < ntiles) part[j] = carry + ex;
         carry += total;
         __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ count, int nc,
+__global__ void __launch_bounds__(256) k_scan_apply(const SysDev* __restrict__ sys,
+                                                    const int32_t* __restrict__ list,
+                                                    const uint32_t* __restrict__ count,
                                                     const uint32_t* __restrict__ partial,
-                                                    uint32_t* __restrict__ start, uint32_t N) {
+                                                    uint32_t* __restrict__ start) {
     __shared__ uint32_t sm[16];
+    const SysDev S = sys[list[blockIdx.y]];
+    const int nc = S.ncells;
+    if ((int)blockIdx.x * kScanTile >= nc) return;
+    const uint32_t* cnt = count + S.cell_off;
+    uint32_t* st = start + S.cell_off;
     const int base = blockIdx.x * kScanTile + threadIdx.x * 8;
     uint32_t v[8], s = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        v[j] = base + j < nc ? count[base + j] : 0u;
+        v[j] = base + j < nc ? cnt[base + j] : 0u;
         s += v[j];
     }
     uint32_t total;
-    uint32_t run = block_exclusive_scan(s, sm, total) + partial[blockIdx.x];
+    uint32_t run = block_exclusive_scan(s, sm, total) + partial[S.part_off + blockIdx.x];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        if (base + j < nc) start[base + j] = run;
+        if (base + j < nc) st[base + j] = run;
         run += v[j];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) start[nc] = N;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[nc] = (uint32_t)S.N;
 }
 
-__global__ void __launch_bounds__(256) k_scatter(const uint32_t* __restrict__ cell_of,
+__global__ void __launch_bounds__(256) k_scatter(const SysDev* __restrict__ sys,
+                                                 const int32_t* __restrict__ list,
+                                                 const uint32_t* __restrict__ cell_of,
                                                  const uint32_t* __restrict__ slot_of,
                                                  const uint32_t* __restrict__ start,
-                                                 uint32_t* __restrict__ members, int N) {
+                                                 uint32_t* __restrict__ members) {
+    const SysDev S = sys[list[blockIdx.y]];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) members[start[cell_of[i]] + slot_of[i]] = (uint32_t)i;
+    if (i < S.N)
+        members[S.slot_off + start[S.cell_off + cell_of[S.slot_off + i]] + slot_of[S.slot_off + i]] =
+            (uint32_t)i;
 }
 
 // Occupants of each cell in ascending tag order (atomics scatter them in
 // arbitrary order; cells hold a handful, so insertion sort).
-__global__ void __launch_bounds__(256) k_sort_cells(const uint32_t* __restrict__ start,
-                                                    uint32_t* __restrict__ members, int nc) {
+__global__ void __launch_bounds__(256) k_sort_cells(const SysDev* __restrict__ sys,
+                                                    const int32_t* __restrict__ list,
+                                                    const uint32_t* __restrict__ start,
+                                                    uint32_t* __restrict__ members) {
+    const SysDev S = sys[list[blockIdx.y]];
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    const uint32_t b = start[c], e = start[c + 1];
+    if (c >= S.ncells) return;
+    uint32_t* mem = members + S.slot_off;
+    const uint32_t b = start[S.cell_off + c], e = start[S.cell_off + c + 1];
     for (uint32_t p = b + 1; p < e; ++p) {
-        const uint32_t v = members[p];
+        const uint32_t v = mem[p];
         uint32_t q = p;
-        while (q > b && members[q - 1] > v) {
-            members[q] = members[q - 1];
+        while (q > b && mem[q - 1] > v) {
+            mem[q] = mem[q - 1];
             --q;
         }
-        members[q] = v;
+        mem[q] = v;
     }
 }
 
 // Cell-sorted binary32 copy of the shifted-frame coordinates (slot order).
 template <int D>
-__global__ void __launch_bounds__(256) k_gather_xs(const SysDev* __restrict__ sys, int r,
+__global__ void __launch_bounds__(256) k_gather_xs(const SysDev* __restrict__ sys,
+                                                   const int32_t* __restrict__ list,
                                                    const double* __restrict__ pos_base,
                                                    const Clock* __restrict__ clock,
                                                    const uint32_t* __restrict__ members,
                                                    float* __restrict__ xs) {
-    const SysDev S = sys[r];
+    const SysDev S = sys[list[blockIdx.y]];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= S.N) return;
     const Clock ck = *clock;
     double sh[3], y[3];
     grid_shift(S, ck.t, ck.k0, ck.k1, 1, sh);
-    particle_grid<D>(S, PosView{const_cast<double*>(pos_base) + S.pos_off, S.N}, members[p], sh, y);
-    XsView<D>{xs}.store((uint32_t)p, y);
+    particle_grid<D>(S, PosView{const_cast<double*>(pos_base) + S.pos_off, S.N}, members[S.slot_off + p],
+                     sh, y);
+    XsView<D>{xs + kXsStride * S.slot_off}.store((uint32_t)p, y);
 }
 
 // One colour pass of the grid path: one wave per tile of 64/G active cells,
 // four waves per work-group.
 template <int KIND, int PREC, int G, int NV>
 __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
-                                                const SpeciesDev* __restrict__ spc, int r,
+                                                const SpeciesDev* __restrict__ spc,
+                                                const int32_t* __restrict__ list,
                                                 double* __restrict__ pos_base,
                                                 double* __restrict__ ori_base,
                                                 const uint32_t* __restrict__ start,
                                                 const uint32_t* __restrict__ members,
-                                                float* __restrict__ xs,
-                                                uint32_t colour, uint32_t select,
-                                                const Clock* __restrict__ clock,
+                                                float* __restrict__ xs, int rnd,
+                                                uint32_t colour, const Clock* __restrict__ clock,
                                                 unsigned long long* __restrict__ stats) {
     constexpr int D = Traits<KIND>::dim;
     __shared__ uint32_t scratch_words[4][kWaveScratchWords];
+    const int r = list[blockIdx.y];
     const SysDev S = sys[r];
     const SpeciesDev& P = spc[S.species];
     Counters ct = {};
@@ -222,16 +260,18 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
     const int n_act = D == 3 ? half * half * half : half * half;
     const int wave = threadIdx.x >> 6;
     const int a0 = (blockIdx.x * 4 + wave) * (64 / G);
-    if (a0 < n_act) {
+    if (rnd < S.rounds && a0 < n_act) {  // replicas with fewer rounds sit this one out
         const Clock ck = *clock;
         const uint32_t t = ck.t, k0 = ck.k0, k1 = ck.k1;
         double sh[3];
         grid_shift(S, t, k0, k1, 1, sh);
         const PosView pos{pos_base + S.pos_off, S.N};
-        const GlobalCells cl{start, members};
-        pass_tile<KIND, PREC, G, NV, false>(S, P, pos, ori_base + S.orient_off, cl, XsView<D>{xs}, colour,
-                                     select, t, k0, k1, sh, a0, n_act,
-                                     wave_scratch(scratch_words[wave]), ct);
+        const GlobalCells cl{start + S.cell_off, members + S.slot_off};
+        const uint32_t select = (uint32_t)rnd * (1u << D) + colour;
+        pass_tile<KIND, PREC, G, NV, false>(S, P, pos, ori_base + S.orient_off, cl,
+                                            XsView<D>{xs + kXsStride * S.slot_off}, colour, select,
+                                            t, k0, k1, sh, a0, n_act,
+                                            wave_scratch(scratch_words[wave]), ct);
     }
     flush_block(ct, &scratch_words[0][0], stat_stripe(stats, r));
 }
@@ -250,6 +290,9 @@ __global__ void __launch_bounds__(256) k_count(const SysDev* __restrict__ sys,
     const SpeciesDev& P = spc[S.species];
     const double* pos = pos_base + S.pos_off;
     const double* ori = ori_base + S.orient_off;
+    start += S.cell_off;
+    members += S.slot_off;
+    cell_of += S.slot_off;
     const int N = S.N, n = S.n;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t found = 0;
@@ -303,6 +346,9 @@ __global__ void __launch_bounds__(256) k_pair_hist(const SysDev* __restrict__ sy
     __shared__ uint32_t hist[kMaxHistBins];
     const SysDev S = sys[r];
     const double* pos = pos_base + S.pos_off;
+    start += S.cell_off;
+    members += S.slot_off;
+    cell_of += S.slot_off;
     const int N = S.N, n = S.n;
     for (int b = threadIdx.x; b < n_bins; b += blockDim.x) hist[b] = 0u;
     __syncthreads();
@@ -552,80 +598,84 @@ hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
-                       int shifted, hipStream_t stream) {
-    const int nc = rh.ncells, N = rh.N;
-    const int ntiles = blocks_for(nc, kScanTile);
-    k_fill_u32<<<blocks_for(nc, 256), 256, 0, stream>>>(ws.count, 0u, nc);
-    if (rh.dim == 3)
-        k_assign<3><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock, shifted,
-                                                             ws.count, ws.cell_of, ws.slot_of);
+hipError_t build_cells(const Workspace& ws, const int32_t* list, int count, int dim, int64_t n_max,
+                       int64_t nc_max, const double* pos, int shifted, hipStream_t stream) {
+    const dim3 by_cell(blocks_for(nc_max, 256), count), by_particle(blocks_for(n_max, 256), count);
+    const dim3 by_tile(blocks_for(nc_max, kScanTile), count), one(1, count);
+    k_zero_counts<<<by_cell, 256, 0, stream>>>(ws.sys, list, ws.count);
+    if (dim == 3)
+        k_assign<3><<<by_particle, 256, 0, stream>>>(ws.sys, list, pos, ws.clock, shifted, ws.count,
+                                                     ws.cell_of, ws.slot_of);
     else
-        k_assign<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock, shifted,
-                                                             ws.count, ws.cell_of, ws.slot_of);
-    k_scan_tiles<<<ntiles, 256, 0, stream>>>(ws.count, nc, ws.partial);
-    k_scan_partials<<<1, 256, 0, stream>>>(ws.partial, ntiles);
-    k_scan_apply<<<ntiles, 256, 0, stream>>>(ws.count, nc, ws.partial, ws.start, (uint32_t)N);
-    k_scatter<<<blocks_for(N, 256), 256, 0, stream>>>(ws.cell_of, ws.slot_of, ws.start,
-                                                       ws.members, N);
-    k_sort_cells<<<blocks_for(nc, 256), 256, 0, stream>>>(ws.start, ws.members, nc);
+        k_assign<2><<<by_particle, 256, 0, stream>>>(ws.sys, list, pos, ws.clock, shifted, ws.count,
+                                                     ws.cell_of, ws.slot_of);
+    k_scan_tiles<<<by_tile, 256, 0, stream>>>(ws.sys, list, ws.count, ws.partial);
+    k_scan_partials<<<one, 256, 0, stream>>>(ws.sys, list, ws.partial);
+    k_scan_apply<<<by_tile, 256, 0, stream>>>(ws.sys, list, ws.count, ws.partial, ws.start);
+    k_scatter<<<by_particle, 256, 0, stream>>>(ws.sys, list, ws.cell_of, ws.slot_of, ws.start,
+                                               ws.members);
+    k_sort_cells<<<by_cell, 256, 0, stream>>>(ws.sys, list, ws.start, ws.members);
     if (shifted) {
-        if (rh.dim == 3)
-            k_gather_xs<3><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock,
-                                                                   ws.members, ws.xs);
+        if (dim == 3)
+            k_gather_xs<3><<<by_particle, 256, 0, stream>>>(ws.sys, list, pos, ws.clock, ws.members,
+                                                            ws.xs);
         else
-            k_gather_xs<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.clock,
-                                                                   ws.members, ws.xs);
+            k_gather_xs<2><<<by_particle, 256, 0, stream>>>(ws.sys, list, pos, ws.clock, ws.members,
+                                                            ws.xs);
     }
     return hipGetLastError();
 }
 
+hipError_t build_cells_one(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                           int shifted, hipStream_t stream) {
+    return build_cells(ws, ws.ident + r, 1, rh.dim, rh.N, rh.ncells, pos, shifted, stream);
+}
+
 template <int KIND, int PREC, int G, int NV>
-static void launch_passes_g(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                            double* orient, hipStream_t stream) {
-    const int half = rh.n / 2;
-    const long n_act = rh.dim == 3 ? (long)half * half * half : (long)half * half;
+static void launch_passes_g(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
+                            hipStream_t stream) {
     const int cells_per_block = 4 * (64 / G);
-    const uint32_t ncol = 1u << rh.dim;
-    for (int rnd = 0; rnd < rh.rounds; ++rnd)
+    const uint32_t ncol = 1u << g.dim;
+    const dim3 grid(blocks_for(g.n_act_max, cells_per_block), g.count);
+    for (int rnd = 0; rnd < g.rounds_max; ++rnd)
         for (uint32_t colour = 0; colour < ncol; ++colour)
-            k_update<KIND, PREC, G, NV><<<blocks_for(n_act, cells_per_block), 256, 0, stream>>>(
-                ws.sys, ws.species, r, pos, orient, ws.start, ws.members, ws.xs, colour,
-                (uint32_t)rnd * ncol + colour, ws.clock, ws.stats);
+            k_update<KIND, PREC, G, NV><<<grid, 256, 0, stream>>>(
+                ws.sys, ws.species, ws.batch_list + g.first, pos, orient, ws.start, ws.members, ws.xs,
+                rnd, colour, ws.clock, ws.stats);
 }
 
 template <int KIND, int PREC, int NV>
-static void launch_passes_nv(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                             double* orient, hipStream_t stream) {
-    switch (rh.lanes_per_cell) {
-        case 8: launch_passes_g<KIND, PREC, 8, NV>(ws, rh, r, pos, orient, stream); break;
-        case 4: launch_passes_g<KIND, PREC, 4, NV>(ws, rh, r, pos, orient, stream); break;
-        case 2: launch_passes_g<KIND, PREC, 2, NV>(ws, rh, r, pos, orient, stream); break;
-        default: launch_passes_g<KIND, PREC, 1, NV>(ws, rh, r, pos, orient, stream); break;
+static void launch_passes_nv(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
+                             hipStream_t stream) {
+    switch (g.lanes) {
+        case 8: launch_passes_g<KIND, PREC, 8, NV>(ws, g, pos, orient, stream); break;
+        case 4: launch_passes_g<KIND, PREC, 4, NV>(ws, g, pos, orient, stream); break;
+        case 2: launch_passes_g<KIND, PREC, 2, NV>(ws, g, pos, orient, stream); break;
+        default: launch_passes_g<KIND, PREC, 1, NV>(ws, g, pos, orient, stream); break;
     }
 }
 
 template <int KIND, int PREC>
-static void launch_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                          double* orient, hipStream_t stream) {
-    if (KIND == kPolygon && rh.nv == 5)
-        launch_passes_nv<KIND, PREC, 5>(ws, rh, r, pos, orient, stream);
+static void launch_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
+                          hipStream_t stream) {
+    if (KIND == kPolygon && g.nv == 5)
+        launch_passes_nv<KIND, PREC, 5>(ws, g, pos, orient, stream);
     else
-        launch_passes_nv<KIND, PREC, 0>(ws, rh, r, pos, orient, stream);
+        launch_passes_nv<KIND, PREC, 0>(ws, g, pos, orient, stream);
 }
 
-hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                       double* orient, int precision, hipStream_t stream) {
-    if (rh.kind == kDisk)
-        launch_passes<kDisk, 0>(ws, rh, r, pos, orient, stream);
-    else if (rh.kind == kPolygon && precision == 1)
-        launch_passes<kPolygon, 1>(ws, rh, r, pos, orient, stream);
-    else if (rh.kind == kPolygon)
-        launch_passes<kPolygon, 0>(ws, rh, r, pos, orient, stream);
+hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
+                       int precision, hipStream_t stream) {
+    if (g.kind == kDisk)
+        launch_passes<kDisk, 0>(ws, g, pos, orient, stream);
+    else if (g.kind == kPolygon && precision == 1)
+        launch_passes<kPolygon, 1>(ws, g, pos, orient, stream);
+    else if (g.kind == kPolygon)
+        launch_passes<kPolygon, 0>(ws, g, pos, orient, stream);
     else if (precision == 1)
-        launch_passes<kPolyhedron, 1>(ws, rh, r, pos, orient, stream);
+        launch_passes<kPolyhedron, 1>(ws, g, pos, orient, stream);
     else
-        launch_passes<kPolyhedron, 0>(ws, rh, r, pos, orient, stream);
+        launch_passes<kPolyhedron, 0>(ws, g, pos, orient, stream);
     return hipGetLastError();
 }
 

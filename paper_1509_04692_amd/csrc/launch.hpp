@@ -16,17 +16,18 @@ struct Workspace {
     SysDev* sys;                      // one per replica
     unsigned long long* stats;        // n_replicas x kStatStripes x kStatStride
     unsigned long long* overlap_out;  // n_replicas
-    // global-memory cell list, sized for the largest grid-path replica
-    uint32_t* count;    // ncells
-    uint32_t* start;    // ncells + 1
-    uint32_t* cell_of;  // N
-    uint32_t* slot_of;  // N
-    uint32_t* members;  // N
-    float* xs;          // N cell-sorted binary32 coordinates (2 or 4 floats each)
+    // global-memory cell lists, one slice per replica (offsets in SysDev)
+    uint32_t* count;    // ncells + 1 per replica
+    uint32_t* start;    // ncells + 1 per replica
+    uint32_t* cell_of;  // N per replica
+    uint32_t* slot_of;  // N per replica
+    uint32_t* members;  // N per replica
+    float* xs;          // kXsStride floats per particle: cell-sorted binary32 coordinates
     double* hist_edges;             // kMaxHistBins + 1 squared bin edges
     unsigned long long* hist_out;   // kMaxHistBins pair counts
-    uint32_t* partial;  // scan tiles
-    int32_t* batch_list;  // replica indices of the persistent path, grouped by kind
+    uint32_t* partial;  // scan tiles, per replica
+    int32_t* batch_list;  // replica indices of the launch groups, grouped by kind
+    int32_t* ident;       // 0 .. n_replicas - 1 (single-replica launches)
     Clock* clock;         // sweep counter and key read by the kernels
     double* backup_pos;   // autotuning snapshot of the caller's arrays
     double* backup_ori;
@@ -40,29 +41,39 @@ struct ReplicaHost {
     int64_t pos_off, orient_off;
 };
 
-// Replicas of one shape kind launched together on the persistent path.
+// Replicas of one shape kind launched together: the persistent path (one
+// work-group per replica) and the grid path (blockIdx.y selects the replica).
 struct BatchGroup {
     int32_t kind, first, count;
-    int32_t resident;  // 0 none, 1 positions, 2 positions + orientations in LDS
+    int32_t resident;  // persistent: 0 none, 1 positions, 2 positions + orientations in LDS
     int32_t nv;        // common polygon vertex count, 0 when mixed or not a polygon
     size_t lds_bytes;
     size_t need[3];    // dynamic LDS per residency level
+    // grid path: largest replica of the group and the lanes per active cell
+    int32_t dim, lanes, rounds_max;
+    int64_t n_max, nc_max, n_act_max;
 };
 
 constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
 
-// Cell list of replica r in global memory: shifted grid of sweep t when
-// shifted != 0, the unshifted grid otherwise.
-hipError_t build_cells(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
-                       int shifted, hipStream_t stream);
+// Cell lists of the replicas list[0 .. count) in global memory (one launch
+// per step, blockIdx.y picks the replica; all of dimension dim, at most
+// n_max particles and nc_max cells): shifted grid of sweep t when shifted !=
+// 0, the unshifted grid otherwise.
+hipError_t build_cells(const Workspace& ws, const int32_t* list, int count, int dim, int64_t n_max,
+                       int64_t nc_max, const double* pos, int shifted, hipStream_t stream);
+// The same for replica r alone.
+hipError_t build_cells_one(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                           int shifted, hipStream_t stream);
 
 // Device clock: set {t, key}; advance t by n.
 hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, hipStream_t stream);
 hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream);
 
-// All colour passes of sweep t for replica r on the global cell list.
-hipError_t grid_passes(const Workspace& ws, const ReplicaHost& rh, int r, double* pos,
-                       double* orient, int precision, hipStream_t stream);
+// All colour passes of sweep t for the replicas of a grid-path group on
+// their global cell lists.
+hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
+                       int precision, hipStream_t stream);
 
 // n_sweeps whole sweeps of the replicas of one batch group, one work-group
 // each.

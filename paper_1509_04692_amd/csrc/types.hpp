@@ -61,11 +61,19 @@ struct alignas(16) SysDev {
     int32_t n, dim, N, rounds;
     int32_t ncells, species, replica, path;
     int64_t pos_off, orient_off;  // element offsets into the caller's arrays
+    // this replica's slice of the global cell list: count/start entries from
+    // cell_off (ncells + 1 of them), per-particle entries (cell_of, slot_of,
+    // members, sorted coordinates) from slot_off, scan partials from part_off
+    int64_t cell_off, slot_off, part_off;
     // Threshold of the binary32 circumsphere pre-filter on the cell-sorted
     // coordinate copy: every pair whose binary64 |r|^2 is below circ2 has a
     // binary32 |r|^2 below scan_t2 (bound derived on the host).
     float scan_t2;
-    uint32_t pad[3];
+    uint32_t pad;
 };
+
+// Floats per particle reserved for the cell-sorted coordinates of any
+// replica in the global cell list (float2 in 2D, float4 in 3D).
+constexpr int kXsStride = 4;
 
 }  // namespace hpmc

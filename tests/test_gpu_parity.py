@@ -110,16 +110,19 @@ def test_polyhedra(shape, path, precision):
         assert st["pair_fp64"] == st["pair_tests"]
 
 
-def test_batched_heterogeneous_replicas():
-    """Disk and pentagon replicas of different N and phi in one persistent launch;
-    each must equal the oracle run with its own replica word."""
+@pytest.mark.parametrize("path", ["persistent", "grid"])
+def test_batched_heterogeneous_replicas(path):
+    """Disk and pentagon replicas of different N and phi in one launch per
+    kind (persistent: a work-group per replica; grid: blockIdx.y per
+    replica, uneven cell counts and rounds); each must equal the oracle run
+    with its own replica word."""
     batch = inputs.screening_batch(n_replicas=6, seed=2026, n_lo=64, n_hi=700)
     species = [b[0] for b in batch]
     Ns = [b[1] for b in batch]
     Ls = [b[2] for b in batch]
     announce(f"batch N={Ns}")
     system = _system(species, Ns, Ls, [b[3] for b in batch], [b[4] for b in batch],
-                     precision="mixed", path="persistent")
+                     precision="mixed", path=path)
     system.sweep(25, seed=11)
     stats = system.stats()
     for r, (sp, N, L, pos, orient) in enumerate(batch):
