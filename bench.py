@@ -154,11 +154,43 @@ def cpu_baseline(wl, warmup, steps, budget_s=12.0):
         cpu = next((l.split(":", 1)[1].strip() for l in out.splitlines() if "Model name" in l), cpu)
     except OSError:
         pass
+    # all host cores: one oracle process per core, each on its own replica
+    # word, started as fresh interpreters (no GPU state is inherited)
+    n_proc = max(1, min(16, os.cpu_count() or 1))
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                               wl["name"], str(r), str(budget_s * 0.75)],
+                              stdout=subprocess.PIPE, text=True) for r in range(n_proc)]
+    all_moves, all_dt = 0, 0.0
+    for pr in procs:
+        out, _ = pr.communicate()
+        res = json.loads(out.strip().splitlines()[-1])
+        all_moves += res["moves"]
+        all_dt = max(all_dt, res["seconds"])
     return {
         "value": moves / dt, "unit": "trial moves/s", "cores": 1, "kind": "oracle",
         "sample": f"replica 0 ({N} particles), sweeps 0..{t_sweep} from the initial state, "
                   f"{dt:.1f} s on one core of {cpu} (nproc {os.cpu_count()})",
+        "all_cores": {"value": all_moves / all_dt, "cores": n_proc,
+                      "sample": f"{n_proc} oracle processes, one replica word each, "
+                                f"{all_dt:.1f} s"},
     }, opm, {k: v / max(int(st[0]), 1) for k, v in ev.items()}, n_count
+
+
+def oracle_worker(name, replica, budget_s):
+    """One oracle process of the all-cores leg: sweeps of the workload's first
+    system with its own replica word for about budget_s seconds."""
+    import oracle
+    wl = workload(name)
+    sp, N, L, pos, ori = wl["items"][0]
+    p, o = pos.copy(), ori.copy()
+    moves, t_sweep = 0, 0
+    chunk = max(1, int(2e5 // N))
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        st = oracle.sweep(sp, L, p, o, seed=1, n_sweeps=chunk, t0=t_sweep, replica=replica)
+        moves += int(st[0])
+        t_sweep += chunk
+    print(json.dumps({"moves": moves, "seconds": time.perf_counter() - t0}))
 
 
 def _csrc_hash():
@@ -197,6 +229,9 @@ def _device_info():
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
+        oracle_worker(sys.argv[2], int(sys.argv[3]), float(sys.argv[4]))
+        return 0
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1024, help="timed sweeps (multiple of 64: whole launches)")
@@ -233,6 +268,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 8, "ok": bool(b[-1].item() == n - 1)}))
         return 0
     wl = workload(args.workload)
+    wl["name"] = args.workload
     batched_ok = wl["replicas"] is None or wl["replicas"] > 1
     runs = ["mixed_batched", "fp64_single", "fp64_batched", "mixed_single"]
     if not batched_ok:

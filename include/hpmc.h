@@ -49,7 +49,7 @@ extern "C" {
 #define HPMC_ERR_WORKSPACE_TOO_SMALL (-4) /* workspace_bytes below requirement */
 #define HPMC_ERR_HIP (-5)                 /* a HIP runtime call failed */
 #define HPMC_ERR_SWEEP_OVERFLOW (-6)      /* sweep counter would reach 2^32 */
-#define HPMC_ERR_UNSUPPORTED (-7)         /* valid request this build cannot run */
+#define HPMC_ERR_UNSUPPORTED (-7)         /* valid request the library does not support */
 
 /* The persistent path launches one kernel per this many sweeps. */
 #define HPMC_PERSISTENT_SWEEPS_PER_LAUNCH 64

@@ -1,8 +1,8 @@
 """ctypes binding of libhpmc.so (argument marshalling only).
 
-The library is built in-tree by ``paper_1509_04692_amd.build`` (or
-``__graft_entry__.build()``).  Loading fails loudly when it is missing: there
-is no fallback implementation.
+The library is built in-tree by ``python -m paper_1509_04692_amd.build``.
+Loading fails loudly when it is missing: there is no fallback
+implementation.
 """
 import ctypes
 import os

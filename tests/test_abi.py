@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB_PATH):
-        pytest.fail("libhpmc.so is not built (run __graft_entry__.build())")
+        pytest.fail("libhpmc.so is not built (run python -m paper_1509_04692_amd.build)")
     return _lib.load()
 
 
