@@ -174,7 +174,8 @@ __device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)
     } else if constexpr (KIND == kPolygon) {
         ct.pair_tests++;
         if constexpr (PREC == 1) {
-            const int d = polygon_overlap32<NV>(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
+            const int d = P.regular ? polygon_overlap32_regular<NV>(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1])
+                                    : polygon_overlap32<NV>(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
             if (d != kUncertain) return d == kOverlap;
         }
         ct.pair_fp64++;

@@ -82,6 +82,78 @@ __host__ __device__ inline int polygon_half32(const SpeciesDev& P, double rxd, d
     return unsure ? kHalfUnsure : kHalfOverlaps;
 }
 
+// The same decision for a polygon with the rotational symmetry of its own
+// vertex count (P.regular): the projections of one shape onto the other's
+// normals then differ between normals only by the offset of the centres, so
+// the extent is computed once per half (normal 0) and every normal adds its
+// offset n_k . t.  Exact symmetry makes this equal to the per-normal
+// extents; the tables' measured symmetry defect widens the margin
+// (P.sat_margin_regular).  Certification as in polygon_half32.
+template <int NV>
+__host__ __device__ inline int polygon_overlap32_regular(const SpeciesDev& P, double rxd, double ryd,
+                                                         double cAd, double sAd, double cBd, double sBd) {
+    constexpr int MV = NV > 0 ? NV : kMaxPolyVerts;
+    const int nv = NV > 0 ? NV : P.nv;
+    const float M = P.sat_margin_regular;
+    const float rx = (float)rxd, ry = (float)ryd;
+    const float cA = (float)cAd, sA = (float)sAd, cB = (float)cBd, sB = (float)sBd;
+    const float zc = fmaf(cA, cB, sA * sB);
+    const float zs = fmaf(cA, sB, -(sA * cB));
+    const float tx = fmaf(cA, rx, sA * ry);
+    const float ty = fmaf(cA, ry, -(sA * rx));
+    const float n0x = P.nx32[0], n0y = P.ny32[0];
+    bool unsure = false;
+    // A's normals: B's vertices (Z b_j + t) projected; Z^T n_0 . b_j
+    {
+        const float mx = fmaf(zc, n0x, zs * n0y), my = fmaf(zc, n0y, -(zs * n0x));
+        float lo = fmaf(mx, P.vx32[0], my * P.vy32[0]), hi = lo;
+#pragma unroll
+        for (int j = 1; j < MV; ++j) {
+            if (j < nv) {
+                const float p = fmaf(mx, P.vx32[j], my * P.vy32[j]);
+                lo = fminf(lo, p);
+                hi = fmaxf(hi, p);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MV; ++k) {
+            if (k < nv) {
+                const float c = fmaf(P.nx32[k], tx, P.ny32[k] * ty);
+                const float l = lo + c, h = hi + c;
+                const float smax = P.pmax32[k], smin = P.pmin32[k];
+                if (l >= smax + M || h <= smin - M) return kNoOverlap;
+                unsure |= !(l < smax - M && h > smin + M);
+            }
+        }
+    }
+    // B's normals: A's vertices in B's frame, Z^T (a_j - t); (Z n_0) . a_j and
+    // the offset -n_k . (Z^T t)
+    {
+        const float mx = fmaf(zc, n0x, -(zs * n0y)), my = fmaf(zs, n0x, zc * n0y);
+        const float ux = fmaf(zc, tx, zs * ty), uy = fmaf(zc, ty, -(zs * tx));
+        float lo = fmaf(mx, P.vx32[0], my * P.vy32[0]), hi = lo;
+#pragma unroll
+        for (int j = 1; j < MV; ++j) {
+            if (j < nv) {
+                const float p = fmaf(mx, P.vx32[j], my * P.vy32[j]);
+                lo = fminf(lo, p);
+                hi = fmaxf(hi, p);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < MV; ++k) {
+            if (k < nv) {
+                const float c = -fmaf(P.nx32[k], ux, P.ny32[k] * uy);
+                const float l = lo + c, h = hi + c;
+                const float smax = P.pmax32[k], smin = P.pmin32[k];
+                if (h <= smin - M || l >= smax + M) return kNoOverlap;
+                unsure |= !(h > smin + M && l < smax - M);
+            }
+        }
+    }
+    return unsure ? kUncertain : kOverlap;
+}
+
 template <int NV>
 __host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd, double ryd, double cAd,
                                                  double sAd, double cBd, double sBd) {
@@ -123,6 +195,20 @@ inline bool fill_polygon_tables(SpeciesDev& P) {
         P.pmax32[k] = (float)hi;
     }
     P.sat_margin_scale = (float)(256.0 * 0x1p-24 * nmax * P.R);
+    // rotational symmetry of the tables: vertex j and normal k against vertex
+    // 0 and normal 0 turned by 2 pi j / nv and 2 pi k / nv; the defect enters
+    // every projection of the symmetric filter as an absolute error
+    double defect_v = 0.0, defect_n = 0.0;
+    for (int k = 0; k < P.nv; ++k) {
+        const double ang = 6.283185307179586 * k / P.nv, c = std::cos(ang), s = std::sin(ang);
+        defect_v = std::fmax(defect_v, std::hypot(P.vx[k] - (c * P.vx[0] - s * P.vy[0]),
+                                                  P.vy[k] - (s * P.vx[0] + c * P.vy[0])));
+        defect_n = std::fmax(defect_n, std::hypot(P.nx[k] - (c * P.nx[0] - s * P.ny[0]),
+                                                  P.ny[k] - (s * P.nx[0] + c * P.ny[0])));
+    }
+    const double asym = defect_v * nmax + defect_n * P.R;
+    P.regular = asym <= 1e-12 * nmax * P.R ? 1 : 0;
+    P.sat_margin_regular = (float)((256.0 * 0x1p-24 * nmax * P.R + 4.0 * asym) * (1.0 + 0x1p-20));
     return true;
 }
 

@@ -46,6 +46,9 @@ struct alignas(16) SpeciesDev {
     float R32;               // circumradius rounded up to binary32
     float tol32;             // XenoCollide tolerance rounded up to binary32
     int32_t mpr32_ok;        // binary32 XenoCollide allowed (R within its range)
+    int32_t regular;         // polygon symmetric under rotation by 2 pi / nv (to the margin)
+    float sat_margin_regular;  // margin of the symmetric-polygon filter
+    float pad2[2];
 };
 
 // Sweep counter and Philox key, read by the kernels from device memory so that

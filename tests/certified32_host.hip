@@ -44,9 +44,10 @@ extern "C" int mpr32_pairs(const double* verts, int nv, int64_t n, const double*
 // verts: nv x 2 (CCW); r: n x 2; za, zb: n x 2 (cos, sin).
 // out[i] = 0 no overlap, 1 overlap, 2 uncertain.  margin_scale multiplies
 // the certification margin (1 = the library's; tests shrink it to show that
-// the comparison notices).
+// the comparison notices); symmetric selects the filter for polygons with
+// the rotational symmetry of their vertex count (-3 if the shape lacks it).
 extern "C" int sat32_pairs(const double* verts, int nv, int64_t n, const double* r, const double* za,
-                           const double* zb, int32_t* out, double margin_scale) {
+                           const double* zb, int32_t* out, double margin_scale, int symmetric) {
     if (nv < 3 || nv > kMaxPolyVerts) return -1;
     static SpeciesDev P;
     P = SpeciesDev{};
@@ -61,8 +62,12 @@ extern "C" int sat32_pairs(const double* verts, int nv, int64_t n, const double*
     P.R = std::nextafter(rmax, INFINITY);
     if (!fill_polygon_tables(P)) return -2;
     P.sat_margin_scale = (float)(P.sat_margin_scale * margin_scale);
+    P.sat_margin_regular = (float)(P.sat_margin_regular * margin_scale);
+    if (symmetric && !P.regular) return -3;
     for (int64_t i = 0; i < n; ++i)
-        out[i] = polygon_overlap32<0>(P, r[2 * i], r[2 * i + 1], za[2 * i], za[2 * i + 1], zb[2 * i],
-                                      zb[2 * i + 1]);
+        out[i] = symmetric ? polygon_overlap32_regular<0>(P, r[2 * i], r[2 * i + 1], za[2 * i],
+                                                          za[2 * i + 1], zb[2 * i], zb[2 * i + 1])
+                           : polygon_overlap32<0>(P, r[2 * i], r[2 * i + 1], za[2 * i], za[2 * i + 1],
+                                                  zb[2 * i], zb[2 * i + 1]);
     return 0;
 }

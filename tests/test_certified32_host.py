@@ -34,7 +34,7 @@ def _build(tmp_path_factory, defines=()):
     P = ctypes.POINTER(ctypes.c_double)
     lib.mpr32_pairs.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int32)]
     lib.sat32_pairs.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.POINTER(ctypes.c_int32),
-                                ctypes.c_double]
+                                ctypes.c_double, ctypes.c_int]
     return lib
 
 
@@ -51,7 +51,7 @@ def run32(lib, verts, r, qa, qb, fn="mpr32_pairs", *extra):
     rc = getattr(lib, fn)(verts.ctypes.data_as(P), len(verts), len(r), r.ctypes.data_as(P),
                          qa.ctypes.data_as(P), qb.ctypes.data_as(P),
                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), *extra)
-    assert rc == 0
+    assert rc == 0, rc
     return out
 
 
@@ -105,11 +105,12 @@ POLYGONS = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(POLYGONS))
-def test_certified_binary32_polygon_filter_equals_the_oracle(mpr32, name):
+@pytest.mark.parametrize("name,symmetric", [("pentagon", 0), ("pentagon", 1), ("triangle", 0),
+                                            ("triangle", 1), ("random8", 0)])
+def test_certified_binary32_polygon_filter_equals_the_oracle(mpr32, name, symmetric):
     sp = POLYGONS[name]
     r, za, zb = pairs(np.random.default_rng(13), sp, 6000)
-    got = run32(mpr32, sp["verts"], r, za, zb, "sat32_pairs", 1.0)
+    got = run32(mpr32, sp["verts"], r, za, zb, "sat32_pairs", 1.0, symmetric)
     lib = oracle.load()
     ref = np.array([oracle.pair_overlaps(sp, r[i], za[i], zb[i], lib=lib) for i in range(len(r))])
     sure = got != 2
@@ -120,16 +121,24 @@ def test_certified_binary32_polygon_filter_equals_the_oracle(mpr32, name):
     assert ref.mean() > 0.2 and ref.mean() < 0.8
 
 
-def test_a_zero_polygon_margin_is_caught(mpr32):
+@pytest.mark.parametrize("symmetric", [0, 1])
+def test_a_zero_polygon_margin_is_caught(mpr32, symmetric):
     """Sensitivity: with no certification margin the binary32 filter decides
     pairs it cannot resolve, and some differ from the oracle's."""
     sp = POLYGONS["pentagon"]
     r, za, zb = pairs(np.random.default_rng(13), sp, 6000)
-    got = run32(mpr32, sp["verts"], r, za, zb, "sat32_pairs", 0.0)
+    got = run32(mpr32, sp["verts"], r, za, zb, "sat32_pairs", 0.0, symmetric)
     lib = oracle.load()
     ref = np.array([oracle.pair_overlaps(sp, r[i], za[i], zb[i], lib=lib) for i in range(len(r))])
     sure = got != 2
     assert (got[sure] != ref[sure]).sum() > 10
+
+
+def test_only_symmetric_polygons_take_the_symmetric_filter(mpr32):
+    one = (np.zeros((1, 2)), np.array([[1.0, 0.0]]), np.array([[1.0, 0.0]]))
+    run32(mpr32, POLYGONS["pentagon"]["verts"], *one, "sat32_pairs", 1.0, 1)
+    with pytest.raises(AssertionError, match="-3"):
+        run32(mpr32, POLYGONS["random8"]["verts"], *one, "sat32_pairs", 1.0, 1)
 
 
 SHAPES = {
