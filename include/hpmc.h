@@ -141,9 +141,11 @@ int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
  * active cell 1, 2, 4, 8; persistent path: which particle data stays in LDS)
  * over trial_sweeps sweeps each, keep the fastest, and restore positions,
  * orientations, counters and the sweep counter exactly.  The trajectory does
- * not depend on the configuration.  Synchronising.  *out_config (may be
- * NULL) receives the chosen lanes per cell (grid) or residency level
- * (persistent). */
+ * not depend on the configuration.  With HPMC_MIXED and polyhedra the
+ * binary64 XenoCollide walk is tried as well (its decisions equal the
+ * certified binary32 walk's).  Synchronising.  *out_config (may be NULL)
+ * receives the chosen lanes per cell (grid) or residency level (persistent)
+ * in its low byte, plus 0x100 when MIXED polyhedra walk in binary64. */
 int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
 
 /* Histogram of pair separations of one replica, the sampling behind the

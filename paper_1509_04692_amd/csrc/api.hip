@@ -20,6 +20,7 @@ using namespace hpmc;
 struct hpmc_state {
     int n_replicas = 0;
     int precision = HPMC_FP64;
+    int walk64 = 0;  // MIXED: polyhedra walk in binary64 (autotuned; same results)
     int path = HPMC_PATH_GRID;
     hipStream_t stream = nullptr;
     double* pos = nullptr;
@@ -344,13 +345,19 @@ int count_all(hpmc_state* st, uint64_t* out) {
     return check_hip(st, hipStreamSynchronize(st->stream));
 }
 
+// Precision of a group's kernels: MIXED polyhedra may take the binary64
+// walk when the autotuner found it faster (the decisions are the same).
+int group_precision(const hpmc_state* st, const BatchGroup& g) {
+    return (g.kind == kPolyhedron && st->walk64) ? HPMC_FP64 : st->precision;
+}
+
 // One sweep (grid path) or `chunk` sweeps (persistent path) of every replica
 // on stream s, ending with the device clock advanced accordingly.
 int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
     int rc = HPMC_OK;
     if (st->path == HPMC_PATH_PERSISTENT) {
         for (const BatchGroup& g : st->groups) {
-            rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, chunk,
+            rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), chunk,
                                                  false, s));
             if (rc) return rc;
         }
@@ -360,7 +367,7 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
         if (rc) break;
         rc = check_hip(st, build_cells(st->ws, st->ws.batch_list + g.first, g.count, g.dim, g.n_max,
                                        g.nc_max, st->pos, 1, s));
-        if (!rc) rc = check_hip(st, grid_passes(st->ws, g, st->pos, st->orient, st->precision, s));
+        if (!rc) rc = check_hip(st, grid_passes(st->ws, g, st->pos, st->orient, group_precision(st, g), s));
     }
     if (!rc) rc = check_hip(st, advance_clock(st->ws, 1, s));
     return rc;
@@ -514,7 +521,7 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
     if (st->path == HPMC_PATH_PERSISTENT)
         for (const BatchGroup& g : st->groups)
-            if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0,
+            if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), 0,
                                                           true, st->stream));
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
     if (!rc) {  // positions in [0, L) and finite orientations, before any cell lookup
@@ -676,6 +683,9 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
         rc = check_hip(st, hipMemcpyAsync(st->ws.backup_stats, st->ws.stats, 8 * nstat,
                                           hipMemcpyDeviceToDevice, st->stream));
     if (rc) return rc;
+    // configuration = lanes per cell (grid) or residency level (persistent),
+    // plus kWalk64 when MIXED polyhedra take the binary64 walk
+    constexpr int kWalk64 = 0x100;
     std::vector<int> cands;
     if (st->path == HPMC_PATH_PERSISTENT) {
         int top = 0;
@@ -684,14 +694,22 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
     } else {
         cands = {1, 2, 4, 8};
     }
+    bool poly_mixed = false;
+    for (const BatchGroup& g : st->groups) poly_mixed |= g.kind == kPolyhedron && st->precision == HPMC_MIXED;
+    if (poly_mixed) {
+        const size_t n0 = cands.size();
+        for (size_t i = 0; i < n0; ++i) cands.push_back(cands[i] | kWalk64);
+    }
     const std::vector<BatchGroup> groups0 = st->groups;
-    auto apply = [&](int c) {
+    auto apply = [&](int cfg) {
+        const int c = cfg & 0xff;
+        st->walk64 = (cfg & kWalk64) ? 1 : 0;
         if (st->path == HPMC_PATH_PERSISTENT) {
             for (size_t i = 0; i < st->groups.size(); ++i) {
                 BatchGroup& g = st->groups[i];
                 g.resident = std::min<int>(c, groups0[i].resident);
                 g.lds_bytes = g.need[g.resident];
-                (void)persistent_sweeps(st->ws, g, st->pos, st->orient, st->precision, 0, true,
+                (void)persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), 0, true,
                                         st->stream);
             }
         } else {

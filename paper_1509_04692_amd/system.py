@@ -133,7 +133,8 @@ class System:
     def autotune(self, trial_sweeps=8):
         """Time the launch configurations, keep the fastest; the state is
         restored exactly.  Returns the chosen lanes per cell (grid path) or
-        LDS residency level (persistent path)."""
+        LDS residency level (persistent path) in the low byte, plus 0x100
+        when mixed-precision polyhedra walk in binary64."""
         cfg = ctypes.c_int32()
         self._check(self._lib.hpmc_autotune(self._handle, int(trial_sweeps), ctypes.byref(cfg)),
                     "hpmc_autotune")

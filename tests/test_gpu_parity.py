@@ -110,6 +110,21 @@ def test_polyhedra(shape, path, precision):
         assert st["pair_fp64"] == st["pair_tests"]
 
 
+def test_autotuned_mixed_polyhedra_equal_the_oracle():
+    """The autotuner may move mixed-precision polyhedra to the binary64 walk;
+    either way the trajectory is the oracle's."""
+    sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
+    announce("autotune mixed cubes")
+    system = _system(sp, N, L, pos, orient, precision="mixed", path="grid")
+    cfg = system.autotune(trial_sweeps=2)
+    assert (cfg & 0xff) in (1, 2, 4, 8) and cfg & ~0x1ff == 0
+    system.sweep(8, seed=3)
+    ref_pos, ref_ori = pos.copy(), orient.copy()
+    ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=3, n_sweeps=8)
+    assert_parity((system.positions(), system.orientations(), system.stats()[0]),
+                  (ref_pos, ref_ori, ref_stats), sp)
+
+
 @pytest.mark.parametrize("path", ["persistent", "grid"])
 def test_batched_heterogeneous_replicas(path):
     """Disk and pentagon replicas of different N and phi in one launch per
