@@ -81,6 +81,10 @@ def workload(name):
         sp, N, L, pos, ori = inputs.workload_truncated_octahedra(32768, 0.45)
         return {"desc": "truncated octahedra N=32768 edge 1 phi=0.45 d=0.08 a=0.1 p_rot=0.5",
                 "items": [(sp, N, L, pos, ori)], "replicas": 1}
+    if name == "dodecahedra":
+        sp, N, L, pos, ori = inputs.workload_dodecahedra(4096, 0.50)
+        return {"desc": "regular dodecahedra N=4096 edge 1 phi=0.50 d=0.08 a=0.1 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 256}
     if name == "large":
         sp, N, L, pos, ori = inputs.workload_pentagons(4194304, 0.60)
         return {"desc": "regular pentagons N=4194304 R=0.5 phi=0.60 d=0.1 a=0.2 p_rot=0.5",
@@ -93,7 +97,7 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def make_system(wl, precision, path, batched):
+def make_system(wl, precision, path, batched, queue="wave"):
     from paper_1509_04692_amd.system import System
     items = wl["items"]
     if wl["replicas"] is None:  # heterogeneous batch
@@ -101,7 +105,8 @@ def make_system(wl, precision, path, batched):
     else:
         chosen = items * (wl["replicas"] if batched else 1)
     return System([c[0] for c in chosen], [c[1] for c in chosen], [c[2] for c in chosen],
-                  [c[3] for c in chosen], [c[4] for c in chosen], precision=precision, path=path)
+                  [c[3] for c in chosen], [c[4] for c in chosen], precision=precision, path=path,
+                  queue=queue)
 
 
 def timed_run(system, steps, warmup, seed):
@@ -237,9 +242,12 @@ def main():
     ap.add_argument("--steps", type=int, default=1024, help="timed sweeps (multiple of 64: whole launches)")
     ap.add_argument("--warmup", type=int, default=128, help="untimed sweeps first")
     ap.add_argument("--workload", default="pentagons",
-                    choices=["pentagons", "pentagons676", "disks", "cubes", "trunc_oct", "large",
-                             "screening"])
+                    choices=["pentagons", "pentagons676", "disks", "cubes", "trunc_oct", "dodecahedra",
+                             "large", "screening"])
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--queue", default="wave", choices=["wave", "register", "global"],
+                    help="schedule of the full overlap tests (register/global: grid path, "
+                         "single-system runs only; for comparison with the default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -273,6 +281,8 @@ def main():
     runs = ["mixed_batched", "fp64_single", "fp64_batched", "mixed_single"]
     if not batched_ok:
         runs = ["mixed_single", "fp64_single"]
+    if args.queue != "wave":
+        runs = ["mixed_single", "fp64_single"]
     if args.only:
         runs = [r for r in args.only.split(",") if r]
     results = {}
@@ -280,7 +290,7 @@ def main():
         precision, mode = name.split("_")
         batched = mode == "batched"
         path = "persistent" if batched else "grid"
-        system = make_system(wl, precision, path, batched)
+        system = make_system(wl, precision, path, batched, args.queue)
         tuned = system.autotune(trial_sweeps=8) if not args.no_autotune else None
         ms, diff = timed_run(system, args.steps, args.warmup, args.seed)
         n_launch = (math.ceil(args.steps / PERSISTENT_SWEEPS_PER_LAUNCH) if path == "persistent"
@@ -343,7 +353,8 @@ def main():
         "dtype": "f32+f64" if head.startswith("mixed") else "f64",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "run": head, "replicas": h["replicas"],
-                   "path": h["path"], "sweeps_per_step": 1, "seed": args.seed},
+                   "path": h["path"], "sweeps_per_step": 1, "seed": args.seed,
+                   "queue": args.queue},
         "speedup_vs_fp64_single": (h["value"] / results["fp64_single"]["value"]
                                    if "fp64_single" in results else None),
         "runs": results,

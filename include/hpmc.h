@@ -56,6 +56,19 @@ extern "C" {
 
 /* hpmc_init_args.flags */
 #define HPMC_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a hipGraph */
+/* How the full overlap tests of a colour pass are scheduled (Sec. 2.5.3).  The
+ * default is the block work queue, kept per wave64 in LDS.  The two flags
+ * below select the variants the paper measured it against; they exist for
+ * comparison, give the same trajectory (only pair_tests differ), run on the
+ * GRID path only (PERSISTENT with either flag: HPMC_ERR_UNSUPPORTED; AUTO
+ * then means GRID) and are mutually exclusive (HPMC_ERR_INVALID_ARG).
+ *   REGISTER_QUEUE: each lane pre-filters its candidates up to its first hit;
+ *     the wave then runs the full tests of all lanes holding one.
+ *   GLOBAL_QUEUE: three kernels per pass (propose and pre-filter into a queue
+ *     in the workspace, test every queued pair, apply); no early exit; the
+ *     workspace grows by about 64 bytes per particle and 60 per cell. */
+#define HPMC_FLAG_REGISTER_QUEUE 2
+#define HPMC_FLAG_GLOBAL_QUEUE 4
 
 /* Opaque host-side handle of one set of replicas. */
 typedef struct hpmc_state hpmc_state;

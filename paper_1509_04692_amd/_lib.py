@@ -31,6 +31,7 @@ EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune",
            "hpmc_sync_to_canonical", "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info",
            "hpmc_uses_graph", "hpmc_last_hip_error", "hpmc_destroy", "hpmc_strerror")
 FLAG_NO_GRAPH = 1
+QUEUE_FLAGS = {"wave": 0, "register": 2, "global": 4}  # HPMC_FLAG_*_QUEUE
 
 
 class HpmcError(RuntimeError):

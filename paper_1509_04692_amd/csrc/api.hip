@@ -22,6 +22,7 @@ struct hpmc_state {
     int precision = HPMC_FP64;
     int walk64 = 0;  // MIXED: polyhedra walk in binary64 (autotuned; same results)
     int path = HPMC_PATH_GRID;
+    int queue = kQueueWave;  // grid path: how full tests are scheduled
     hipStream_t stream = nullptr;
     double* pos = nullptr;
     double* orient = nullptr;
@@ -176,12 +177,21 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
 struct Layout {
     size_t species, sys, stats, overlap, count, start, cell_of, slot_of, members, xs, hist_edges,
         hist_out, partial, list, ident,
-        clock, backup_pos, backup_ori, backup_stats, total;
+        clock, backup_pos, backup_ori, backup_stats, gq_trial, gq_meta, gq_flag, gq_entries,
+        gq_count, total;
+    int64_t cell_total;
     size_t pos_total, ori_total;
 };
 
 // Lanes per active cell on the grid path: enough waves to cover the chip
 // (256 CUs x 8 waves) when a pass has few active cells.
+// Queue mode from hpmc_init_args.flags; -1 when both variants are asked for.
+int queue_mode(int32_t flags) {
+    const bool reg = (flags & HPMC_FLAG_REGISTER_QUEUE) != 0, glob = (flags & HPMC_FLAG_GLOBAL_QUEUE) != 0;
+    if (reg && glob) return -1;
+    return glob ? kQueueGlobal : (reg ? kQueueRegister : kQueueWave);
+}
+
 int choose_lanes_per_cell(int64_t n_act) {
     const int64_t target_waves = 256 * 8;
     int g = 1;
@@ -197,6 +207,9 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         return HPMC_ERR_INVALID_ARG;
     if (a->precision != HPMC_FP64 && a->precision != HPMC_MIXED) return HPMC_ERR_INVALID_ARG;
     if (a->path < HPMC_PATH_AUTO || a->path > HPMC_PATH_PERSISTENT) return HPMC_ERR_INVALID_ARG;
+    const int queue = queue_mode(a->flags);
+    if (queue < 0) return HPMC_ERR_INVALID_ARG;
+    if (queue != kQueueWave && a->path == HPMC_PATH_PERSISTENT) return HPMC_ERR_UNSUPPORTED;
     const int R = a->n_replicas;
     rep.assign(R, ReplicaHost{});
     sys.assign(R, SysDev{});
@@ -235,7 +248,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     }
     if (a->path == HPMC_PATH_PERSISTENT && !fits_lds) return HPMC_ERR_UNSUPPORTED;
     if (a->path == HPMC_PATH_AUTO)
-        path = (fits_lds && R > 1) ? HPMC_PATH_PERSISTENT : HPMC_PATH_GRID;
+        path = (fits_lds && R > 1 && queue == kQueueWave) ? HPMC_PATH_PERSISTENT : HPMC_PATH_GRID;
     else
         path = a->path;
     for (int r = 0; r < R; ++r) {
@@ -326,6 +339,13 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.backup_pos = take(8 * (size_t)pos_off);
     lay.backup_ori = take(8 * (size_t)(ori_off > 0 ? ori_off : 1));
     lay.backup_stats = take(sizeof(unsigned long long) * kStatsPerReplica * R);
+    const bool gq = queue == kQueueGlobal;
+    lay.cell_total = cell_total;
+    lay.gq_trial = take(gq ? 8 * 7 * (size_t)cell_total : 0);
+    lay.gq_meta = take(gq ? 4 * 3 * (size_t)cell_total : 0);
+    lay.gq_flag = take(gq ? 4 * (size_t)cell_total : 0);
+    lay.gq_entries = take(gq ? 8 * (size_t)kGqPerSlot * (size_t)slot_total : 0);
+    lay.gq_count = take(gq ? 8 * (size_t)R : 0);
     lay.total = off;
     return HPMC_OK;
 }
@@ -367,7 +387,9 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
         if (rc) break;
         rc = check_hip(st, build_cells(st->ws, st->ws.batch_list + g.first, g.count, g.dim, g.n_max,
                                        g.nc_max, st->pos, 1, s));
-        if (!rc) rc = check_hip(st, grid_passes(st->ws, g, st->pos, st->orient, group_precision(st, g), s));
+        if (!rc)
+            rc = check_hip(st, grid_passes(st->ws, g, st->pos, st->orient, group_precision(st, g),
+                                           st->queue, s));
     }
     if (!rc) rc = check_hip(st, advance_clock(st->ws, 1, s));
     return rc;
@@ -500,6 +522,16 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->pos_total = lay.pos_total;
     st->ori_total = lay.ori_total;
     st->flags = args->flags;
+    st->queue = queue_mode(args->flags);
+    if (st->queue == kQueueGlobal) {
+        GlobalQueue& q = st->ws.gq;
+        q.trial = (double*)(base + lay.gq_trial);
+        q.meta = (uint32_t*)(base + lay.gq_meta);
+        q.flag = (uint32_t*)(base + lay.gq_flag);
+        q.entries = (uint2*)(base + lay.gq_entries);
+        q.count = (uint32_t*)(base + lay.gq_count);
+        q.cell_total = lay.cell_total;
+    }
 
     rc = check_hip(st, hipMemcpyAsync(st->ws.species, st->spc.data(),
                                       sizeof(SpeciesDev) * st->n_replicas, hipMemcpyHostToDevice,
@@ -519,6 +551,9 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
         rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kStatsPerReplica * st->n_replicas,
                                     st->stream));
     if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
+    if (!rc && st->queue == kQueueGlobal)  // queue lengths start at zero; each pass leaves them so
+        rc = check_hip(st, fill_u64((unsigned long long*)st->ws.gq.count, 0ull, (size_t)st->n_replicas,
+                                    st->stream));
     if (st->path == HPMC_PATH_PERSISTENT)
         for (const BatchGroup& g : st->groups)
             if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), 0,
@@ -691,6 +726,8 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
         int top = 0;
         for (const BatchGroup& g : st->groups) top = std::max(top, (int)g.resident);
         for (int lv = top; lv >= 0; --lv) cands.push_back(lv);
+    } else if (st->queue == kQueueGlobal) {
+        cands = {1};  // one lane per cell or queued pair: nothing to choose but the walk
     } else {
         cands = {1, 2, 4, 8};
     }

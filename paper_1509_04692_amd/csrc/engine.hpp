@@ -326,6 +326,10 @@ __device__ __forceinline__ WaveScratch wave_scratch(uint32_t* base) {
 }
 constexpr uint32_t kTagMask = (1u << 26) - 1u;
 
+// How a pass hands the full overlap tests to lanes: the per-wave LDS queue
+// (the paper's block queue), or the register queue it improves on.
+enum QueueKind : int { kWaveQueue = 0, kRegisterQueue = 1 };
+
 // ---------------------------------------------------------------------------
 // Drain n (<= 64) queued pair tests: lane L takes entry L, fetches the owner
 // cell's trial state from the owner lane, runs the binary64 circumsphere test
@@ -452,9 +456,67 @@ __device__ __forceinline__ void compact_queue(uint32_t* q, uint32_t from, uint32
     wave_sync();
 }
 
+// Trial move of active cell a (index within its colour): uniform occupant
+// (Philox SELECT), translation or rotation (Philox MOVE keyed on the tag),
+// periodic wrap, and the rule that a translation must stay in the cell.
+// Sets live when the cell is non-empty and the trial stays in it.
+template <int KIND, class POS, class CELLS>
+__device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, const POS& pos,
+                                        const double* __restrict__ ori, const CELLS& cl,
+                                        uint32_t colour, uint32_t select, uint32_t t, uint32_t k0,
+                                        uint32_t k1, const double (&sh)[3], int a, int (&cc)[3],
+                                        uint32_t& c, uint32_t& i, uint32_t& pi, bool& live,
+                                        double (&xn)[3], double (&qn)[4], bool& c_rot,
+                                        bool& c_moved, Counters& ct) {
+    constexpr int D = Traits<KIND>::dim;
+    const int n = S.n;
+    active_cell(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
+    const uint32_t beg = cl.begin(c), fin = cl.end(c);
+    if (beg != fin) {
+        ct.attempted++;
+        const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
+        pi = beg + index_below(wsel.x, fin - beg);
+        i = cl.member(pi);
+        const uint4 m = draw(t, kMove, select, i, S.replica, k0, k1);
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) xn[ax] = pos.get(ax, i);
+        load_orient<KIND>(ori, S.N, i, qn);
+        const bool rotate = KIND != kDisk && P.p_rot > 0.0 && u01(m.x) < P.p_rot;
+        live = true;
+        c_rot = rotate;
+        c_moved = !rotate;
+        if (!rotate) {
+            const uint32_t mw[3] = {m.y, m.z, m.w};
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) {
+                xn[ax] = wrap_periodic(xn[ax] + P.d * (2.0 * u01(mw[ax]) - 1.0), S.L);
+                live &= cell_coord(xn[ax], sh[ax], S.L, S.inv_w, n) == cc[ax];
+            }
+        } else {
+            if constexpr (KIND == kPolygon) {
+                const double delta = P.a * (2.0 * u01(m.y) - 1.0);
+                double cd, sd;
+                small_angle_sincos(delta, cd, sd);
+                const double c0 = qn[0], s0 = qn[1];
+                qn[0] = c0 * cd - s0 * sd;
+                qn[1] = s0 * cd + c0 * sd;
+            } else if constexpr (KIND == kPolyhedron) {
+                const Quat dq{1.0, P.a * (2.0 * u01(m.y) - 1.0), P.a * (2.0 * u01(m.z) - 1.0),
+                              P.a * (2.0 * u01(m.w) - 1.0)};
+                const Quat p = qmul(Quat{qn[0], qn[1], qn[2], qn[3]}, dq);
+                const double nrm = sqrt(((p.w * p.w + p.x * p.x) + p.y * p.y) + p.z * p.z);
+                qn[0] = p.w / nrm;
+                qn[1] = p.x / nrm;
+                qn[2] = p.y / nrm;
+                qn[3] = p.z / nrm;
+            }
+        }
+    }
+}
+
 // PARK: the sorted copy is in LDS and the moving particle's slot is parked
 // at infinity during its own scan (else the scan tests the slot).
-template <int KIND, int PREC, int G, int NV, bool PARK, class POS, class CELLS>
+template <int KIND, int PREC, int G, int NV, bool PARK, int Q = kWaveQueue, class POS, class CELLS>
 __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                           double* __restrict__ ori, const CELLS& cl,
                                           const XsView<Traits<KIND>::dim>& xs, uint32_t colour,
@@ -468,7 +530,8 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     const int a = a0 + grp;
     const int n = S.n, N = S.N;
 
-    // ---- 1. propose (group leaders)
+    // ---- 1. propose (group leaders; the steps of propose() above, kept inline here
+    // because the call changes the register allocation of this hot kernel)
     int cc[3] = {0, 0, 0};
     uint32_t c = 0, i = 0, pi = 0;  // active cell, moving tag, its slot in the cell list
     bool live = false;
@@ -544,72 +607,129 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     for (int ax = 0; ax < D; ++ax) yn[ax] = grid_coord(xn[ax], sh[ax], S.L);
     wave_sync();
 
-    // ---- 2 + 3. binary32 circumsphere pre-filter over the neighbour ranges
-    // (lane `sub` of a group takes ranges sub, sub + G, ...), queued exact
-    // tests.  The outer loop over ranges is uniform; each inner loop runs to
-    // the longest range of the wave.
-    constexpr int NR = Neighbourhood<D>::ranges;
-    constexpr int NK = (NR + G - 1) / G;
-    const float t2 = S.scan_t2;
-    bool flagged = false;  // this lane's cell already has an overlap (register copy)
-    uint32_t queued = 0;   // wave-uniform
-    uint32_t queued2 = 0;  // wave-uniform, polygons only
-    for (int kr = 0; kr < NK; ++kr) {
-        const int ri = sub + kr * G;
-        uint32_t p = 0, e = 0;
-        float ref[3] = {0.0f, 0.0f, 0.0f};
-        if (live && !flagged && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
-        for (;;) {
-            // each predicate is a single compare so that its ballot is the
-            // compare's lane mask: a flagged lane has e = p, an idle lane's
-            // distance is infinite
-            const bool work = p < e;
-            if (wave_ballot(work) == 0ull) break;
-            const uint32_t slot = work ? p : 0u;  // idle lanes read slot 0 (always valid)
-            float v[3];
-            xs.load(slot, v);
-            const float rx = v[0] - ref[0], ry = v[1] - ref[1];
-            float r2 = fmaf(ry, ry, rx * rx);
-            if constexpr (D == 3) {
-                const float rz = v[2] - ref[2];
-                r2 = fmaf(rz, rz, r2);
-            }
-            r2 = (work && (PARK || slot != pi)) ? r2 : INFINITY;
-            const bool hit = r2 < t2;
-            p += work ? 1u : 0u;
-            const uint64_t hm = wave_ballot(hit);
-            if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | slot;
-            queued += (uint32_t)__builtin_popcountll(hm);
-            if (queued >= 64u) {
-                if constexpr (KIND == kPolygon && PREC == 0) {
-                    queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, queued2, ct);
-                } else {
-                    drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+    if constexpr (Q == kWaveQueue) {
+        // ---- 2 + 3. binary32 circumsphere pre-filter over the neighbour ranges
+        // (lane `sub` of a group takes ranges sub, sub + G, ...), queued exact
+        // tests.  The outer loop over ranges is uniform; each inner loop runs to
+        // the longest range of the wave.
+        constexpr int NR = Neighbourhood<D>::ranges;
+        constexpr int NK = (NR + G - 1) / G;
+        const float t2 = S.scan_t2;
+        bool flagged = false;  // this lane's cell already has an overlap (register copy)
+        uint32_t queued = 0;   // wave-uniform
+        uint32_t queued2 = 0;  // wave-uniform, polygons only
+        for (int kr = 0; kr < NK; ++kr) {
+            const int ri = sub + kr * G;
+            uint32_t p = 0, e = 0;
+            float ref[3] = {0.0f, 0.0f, 0.0f};
+            if (live && !flagged && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
+            for (;;) {
+                // each predicate is a single compare so that its ballot is the
+                // compare's lane mask: a flagged lane has e = p, an idle lane's
+                // distance is infinite
+                const bool work = p < e;
+                if (wave_ballot(work) == 0ull) break;
+                const uint32_t slot = work ? p : 0u;  // idle lanes read slot 0 (always valid)
+                float v[3];
+                xs.load(slot, v);
+                const float rx = v[0] - ref[0], ry = v[1] - ref[1];
+                float r2 = fmaf(ry, ry, rx * rx);
+                if constexpr (D == 3) {
+                    const float rz = v[2] - ref[2];
+                    r2 = fmaf(rz, rz, r2);
                 }
-                queued -= 64u;
-                compact_queue(ws.q, 64u, queued);
-                if constexpr (KIND == kPolygon && PREC == 0) {
-                    if (queued2 >= 64u) {
-                        drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
-                        queued2 -= 64u;
-                        compact_queue(ws.q2, 64u, queued2);
+                r2 = (work && (PARK || slot != pi)) ? r2 : INFINITY;
+                const bool hit = r2 < t2;
+                p += work ? 1u : 0u;
+                const uint64_t hm = wave_ballot(hit);
+                if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | slot;
+                queued += (uint32_t)__builtin_popcountll(hm);
+                if (queued >= 64u) {
+                    if constexpr (KIND == kPolygon && PREC == 0) {
+                        queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, queued2, ct);
+                    } else {
+                        drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+                    }
+                    queued -= 64u;
+                    compact_queue(ws.q, 64u, queued);
+                    if constexpr (KIND == kPolygon && PREC == 0) {
+                        if (queued2 >= 64u) {
+                            drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+                            queued2 -= 64u;
+                            compact_queue(ws.q2, 64u, queued2);
+                        }
+                    }
+                    flagged = ws.flag[grp] != 0u;
+                    e = flagged ? p : e;
+                }
+            }
+        }
+        if constexpr (KIND == kPolygon && PREC == 0) {
+            if (queued) queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, queued2, ct);
+            while (queued2) {
+                const uint32_t m = queued2 < 64u ? queued2 : 64u;
+                drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, m, ws, ct);
+                queued2 -= m;
+                if (queued2) compact_queue(ws.q2, 64u, queued2);
+            }
+        } else {
+            if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, ct);
+        }
+    } else {
+        // ---- 2 + 3, register queue (the paper's first variant): each lane
+        // runs the pre-filter over its ranges and stops at its first hit; the
+        // wave then runs the full tests of all lanes that hold a hit, on the
+        // lane's own trial state, and the scan resumes where it stopped.
+        if constexpr (G > 1) {
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) qn[c4] = __shfl(qn[c4], leader, 64);
+        }
+        constexpr int NR = Neighbourhood<D>::ranges;
+        constexpr int NK = (NR + G - 1) / G;
+        const float t2 = S.scan_t2;
+        bool flagged = false;
+        for (int kr = 0; kr < NK; ++kr) {
+            const int ri = sub + kr * G;
+            uint32_t p = 0, e = 0;
+            float ref[3] = {0.0f, 0.0f, 0.0f};
+            if (live && !flagged && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
+            for (;;) {
+                uint32_t hit = 0xffffffffu;
+                while (p < e) {
+                    const uint32_t slot = p++;
+                    float v[3];
+                    xs.load(slot, v);
+                    const float rx = v[0] - ref[0], ry = v[1] - ref[1];
+                    float r2 = fmaf(ry, ry, rx * rx);
+                    if constexpr (D == 3) {
+                        const float rz = v[2] - ref[2];
+                        r2 = fmaf(rz, rz, r2);
+                    }
+                    if (r2 < t2 && (PARK || slot != pi)) {
+                        hit = slot;
+                        break;
                     }
                 }
+                const bool has = hit != 0xffffffffu;
+                if (wave_ballot(has) == 0ull) break;
+                if (has) {
+                    const uint32_t k = cl.member(hit);
+                    double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) r[ax] = min_image(pos.get(ax, k) - xn[ax], S.L, S.inv_L);
+                    double r2 = r[0] * r[0] + r[1] * r[1];
+                    if constexpr (D == 3) r2 = r2 + r[2] * r[2];
+                    if (r2 < P.circ2) {
+                        double qk[4];
+                        load_orient<KIND>(ori, S.N, k, qk);
+                        if (full_test<KIND, PREC, NV>(P, r, qn, qk, ct)) ws.flag[grp] = 1u;
+                    }
+                }
+                wave_sync();
                 flagged = ws.flag[grp] != 0u;
                 e = flagged ? p : e;
             }
         }
-    }
-    if constexpr (KIND == kPolygon && PREC == 0) {
-        if (queued) queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, queued2, ct);
-        while (queued2) {
-            const uint32_t m = queued2 < 64u ? queued2 : 64u;
-            drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, m, ws, ct);
-            queued2 -= m;
-            if (queued2) compact_queue(ws.q2, 64u, queued2);
-        }
-    } else {
-        if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, ct);
     }
 
     // ---- 4. write back (counters updated arithmetically, not per branch)

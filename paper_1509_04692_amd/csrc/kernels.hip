@@ -9,6 +9,8 @@
 // replica and runs whole sweeps; its cell list lives in LDS and the colour
 // passes are separated by work-group barriers, so no grid-wide
 // synchronisation is needed.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "engine.hpp"
 #include "launch.hpp"
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(256) k_gather_xs(const SysDev* __restrict__ sy
 
 // One colour pass of the grid path: one wave per tile of 64/G active cells,
 // four waves per work-group.
-template <int KIND, int PREC, int G, int NV>
+template <int KIND, int PREC, int G, int NV, int Q>
 __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
                                                 const SpeciesDev* __restrict__ spc,
                                                 const int32_t* __restrict__ list,
@@ -268,12 +270,224 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
         const PosView pos{pos_base + S.pos_off, S.N};
         const GlobalCells cl{start + S.cell_off, members + S.slot_off};
         const uint32_t select = (uint32_t)rnd * (1u << D) + colour;
-        pass_tile<KIND, PREC, G, NV, false>(S, P, pos, ori_base + S.orient_off, cl,
+        pass_tile<KIND, PREC, G, NV, false, Q>(S, P, pos, ori_base + S.orient_off, cl,
                                             XsView<D>{xs + kXsStride * S.slot_off}, colour, select,
                                             t, k0, k1, sh, a0, n_act,
                                             wave_scratch(scratch_words[wave]), ct);
     }
     flush_block(ct, &scratch_words[0][0], stat_stripe(stats, r));
+}
+
+// ---------------------------------------------------------------------------
+// Global-queue variant of a colour pass (the paper's second variant), three
+// kernels: (1) one lane per active cell proposes its move, keeps the trial
+// state in global memory and appends every pre-filter hit to its replica's
+// queue; (2) one lane per queued pair runs the binary64 circumsphere test and
+// the full test and marks the owner cell on an overlap; (3) one lane per
+// active cell applies the moves of unmarked cells.  There is no early exit:
+// every queued pair is tested.
+//
+// Queue bound: active cells of one colour are two cells apart on every axis,
+// so a slot lies in the 3^dim neighbourhood of at most 2^dim of them, and a
+// replica queues at most 2^dim N pairs per pass.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(256) k_gq_scan(const SysDev* __restrict__ sys,
+                                                 const SpeciesDev* __restrict__ spc,
+                                                 const int32_t* __restrict__ list,
+                                                 const double* __restrict__ pos_base,
+                                                 const double* __restrict__ ori_base,
+                                                 const uint32_t* __restrict__ start,
+                                                 const uint32_t* __restrict__ members,
+                                                 const float* __restrict__ xs, int rnd,
+                                                 uint32_t colour, const Clock* __restrict__ clock,
+                                                 GlobalQueue gq, unsigned long long* __restrict__ stats) {
+    constexpr int D = Traits<KIND>::dim;
+    __shared__ uint32_t red[4 * kNumStats];
+    __shared__ uint2 stage[4][128];
+    const int r = list[blockIdx.y];
+    const SysDev S = sys[r];
+    const SpeciesDev& P = spc[S.species];
+    Counters ct = {};
+    const int half = S.n / 2;
+    const int n_act = D == 3 ? half * half * half : half * half;
+    const int a = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (rnd < S.rounds && (int)(blockIdx.x * 256) < n_act) {  // uniform over the work-group
+        const Clock ck = *clock;
+        double sh[3];
+        grid_shift(S, ck.t, ck.k0, ck.k1, 1, sh);
+        const PosView pos{const_cast<double*>(pos_base) + S.pos_off, S.N};
+        const double* ori = ori_base + S.orient_off;
+        const GlobalCells cl{start + S.cell_off, members + S.slot_off};
+        const XsView<D> xv{const_cast<float*>(xs) + kXsStride * S.slot_off};
+        const uint32_t select = (uint32_t)rnd * (1u << D) + colour;
+        int cc[3] = {0, 0, 0};
+        uint32_t c = 0, i = 0, pi = 0;
+        bool live = false, c_rot = false, c_moved = false;
+        double xn[3] = {0.0, 0.0, 0.0};
+        double qn[4] = {1.0, 0.0, 0.0, 0.0};
+        if (a < n_act) {
+            propose<KIND>(S, P, pos, ori, cl, colour, select, ck.t, ck.k0, ck.k1, sh, a, cc, c, i, pi,
+                          live, xn, qn, c_rot, c_moved, ct);
+            ct.attempted_rot += c_rot ? 1u : 0u;
+            ct.cell_reject += (c_moved && !live) ? 1u : 0u;
+            const size_t o = (size_t)S.cell_off + a, T = (size_t)gq.cell_total;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) gq.trial[ax * T + o] = xn[ax];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) gq.trial[(3 + q) * T + o] = qn[q];
+            gq.meta[o] = i;
+            gq.meta[T + o] = pi;
+            gq.meta[2 * T + o] = (live ? 1u : 0u) | (c_rot ? 2u : 0u) | (c_moved ? 4u : 0u);
+            gq.flag[o] = 0u;
+        }
+        double yn[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) yn[ax] = grid_coord(xn[ax], sh[ax], S.L);
+        uint2* ent = gq.entries + ((size_t)S.slot_off * kGqPerSlot);
+        const uint32_t cap = (uint32_t)S.N << D;
+        const float t2 = S.scan_t2;
+        // hits are staged per wave in LDS and appended 64 at a time, one
+        // atomic per 64 entries
+        uint2* st = stage[threadIdx.x >> 6];
+        const uint32_t lane = __lane_id();
+        uint32_t staged = 0;  // wave-uniform, < 64 between iterations
+        auto append = [&](uint32_t m) {
+            wave_sync();
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(gq.count + r, m);
+            base = (uint32_t)__shfl((int)base, 0, 64);
+            if (lane < m && base + lane < cap) ent[base + lane] = st[lane];
+            const uint32_t left = staged - m;
+            const uint2 v = lane < left ? st[m + lane] : make_uint2(0u, 0u);
+            wave_sync();
+            if (lane < left) st[lane] = v;
+            staged = left;
+            wave_sync();
+        };
+        for (int ri = 0; ri < Neighbourhood<D>::ranges; ++ri) {
+            uint32_t p = 0, e = 0;
+            float ref[3] = {0.0f, 0.0f, 0.0f};
+            if (live) neighbour_range<D>(cl, cc, S.n, ri, S.L, yn, p, e, ref);
+            for (;;) {
+                const bool work = p < e;
+                if (wave_ballot(work) == 0ull) break;
+                const uint32_t slot = work ? p : 0u;
+                float v[3];
+                xv.load(slot, v);
+                const float rx = v[0] - ref[0], ry = v[1] - ref[1];
+                float r2 = fmaf(ry, ry, rx * rx);
+                if constexpr (D == 3) {
+                    const float rz = v[2] - ref[2];
+                    r2 = fmaf(rz, rz, r2);
+                }
+                r2 = (work && slot != pi) ? r2 : INFINITY;
+                const bool hit = r2 < t2;
+                p += work ? 1u : 0u;
+                const uint64_t hm = wave_ballot(hit);
+                if (hit) st[staged + lanes_below(hm)] = make_uint2((uint32_t)a, slot);
+                staged += (uint32_t)__builtin_popcountll(hm);
+                if (staged >= 64u) append(64u);
+            }
+        }
+        if (staged) append(staged);
+    }
+    flush_block(ct, red, stat_stripe(stats, r));
+}
+
+template <int KIND, int PREC, int NV>
+__global__ void __launch_bounds__(256) k_gq_test(const SysDev* __restrict__ sys,
+                                                 const SpeciesDev* __restrict__ spc,
+                                                 const int32_t* __restrict__ list,
+                                                 const double* __restrict__ pos_base,
+                                                 const double* __restrict__ ori_base,
+                                                 const uint32_t* __restrict__ members, int rnd,
+                                                 GlobalQueue gq, unsigned long long* __restrict__ stats) {
+    constexpr int D = Traits<KIND>::dim;
+    __shared__ uint32_t red[4 * kNumStats];
+    const int r = list[blockIdx.y];
+    const SysDev S = sys[r];
+    const SpeciesDev& P = spc[S.species];
+    Counters ct = {};
+    if (rnd < S.rounds) {
+        const uint32_t cap = (uint32_t)S.N << D;
+        const uint32_t nq = min(gq.count[r], cap);
+        const uint2* ent = gq.entries + ((size_t)S.slot_off * kGqPerSlot);
+        const double* pos = pos_base + S.pos_off;
+        const double* ori = ori_base + S.orient_off;
+        const size_t T = (size_t)gq.cell_total;
+        for (uint32_t q = blockIdx.x * 256 + threadIdx.x; q < nq; q += gridDim.x * 256) {
+            const uint2 e = ent[q];
+            const size_t o = (size_t)S.cell_off + e.x;
+            const uint32_t k = members[S.slot_off + e.y];
+            double r3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax)
+                r3[ax] = min_image(pos[(size_t)ax * S.N + k] - gq.trial[ax * T + o], S.L, S.inv_L);
+            double r2 = r3[0] * r3[0] + r3[1] * r3[1];
+            if constexpr (D == 3) r2 = r2 + r3[2] * r3[2];
+            if (r2 < P.circ2) {
+                double qi[4], qk[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) qi[c] = gq.trial[(3 + c) * T + o];
+                load_orient<KIND>(ori, S.N, k, qk);
+                if (full_test<KIND, PREC, NV>(P, r3, qi, qk, ct)) gq.flag[o] = 1u;
+            }
+        }
+    }
+    flush_block(ct, red, stat_stripe(stats, r));
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_gq_apply(const SysDev* __restrict__ sys,
+                                                  const int32_t* __restrict__ list,
+                                                  double* __restrict__ pos_base,
+                                                  double* __restrict__ ori_base,
+                                                  float* __restrict__ xs, int rnd,
+                                                  const Clock* __restrict__ clock, GlobalQueue gq,
+                                                  unsigned long long* __restrict__ stats) {
+    constexpr int D = Traits<KIND>::dim;
+    __shared__ uint32_t red[4 * kNumStats];
+    const int r = list[blockIdx.y];
+    const SysDev S = sys[r];
+    Counters ct = {};
+    const int half = S.n / 2;
+    const int n_act = D == 3 ? half * half * half : half * half;
+    const int a = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (rnd < S.rounds && a < n_act) {
+        const size_t o = (size_t)S.cell_off + a, T = (size_t)gq.cell_total;
+        const uint32_t bits = gq.meta[2 * T + o];
+        if (bits & 1u) {
+            const bool rejected = gq.flag[o] != 0u;
+            ct.overlap_reject += rejected ? 1u : 0u;
+            ct.accept += rejected ? 0u : 1u;
+            if (!rejected) {
+                const uint32_t i = gq.meta[o], pi = gq.meta[T + o];
+                const int N = S.N;
+                if (bits & 4u) {
+                    const Clock ck = *clock;
+                    double sh[3], xn[3] = {0.0, 0.0, 0.0}, yn[3] = {0.0, 0.0, 0.0};
+                    grid_shift(S, ck.t, ck.k0, ck.k1, 1, sh);
+                    double* pos = pos_base + S.pos_off;
+#pragma unroll
+                    for (int ax = 0; ax < D; ++ax) {
+                        xn[ax] = gq.trial[ax * T + o];
+                        pos[(size_t)ax * N + i] = xn[ax];
+                        yn[ax] = grid_coord(xn[ax], sh[ax], S.L);
+                    }
+                    XsView<D>{xs + kXsStride * S.slot_off}.store(pi, yn);
+                }
+                if (bits & 2u) {
+                    double* ori = ori_base + S.orient_off;
+                    constexpr int NC = Traits<KIND>::ncomp;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) ori[(size_t)c * N + i] = gq.trial[(3 + c) * T + o];
+                }
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) gq.count[r] = 0u;  // the test kernel has read it
+    flush_block(ct, red, stat_stripe(stats, r));
 }
 
 template <int KIND>
@@ -631,7 +845,7 @@ hipError_t build_cells_one(const Workspace& ws, const ReplicaHost& rh, int r, co
     return build_cells(ws, ws.ident + r, 1, rh.dim, rh.N, rh.ncells, pos, shifted, stream);
 }
 
-template <int KIND, int PREC, int G, int NV>
+template <int KIND, int PREC, int G, int NV, int Q>
 static void launch_passes_g(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
                             hipStream_t stream) {
     const int cells_per_block = 4 * (64 / G);
@@ -639,43 +853,75 @@ static void launch_passes_g(const Workspace& ws, const BatchGroup& g, double* po
     const dim3 grid(blocks_for(g.n_act_max, cells_per_block), g.count);
     for (int rnd = 0; rnd < g.rounds_max; ++rnd)
         for (uint32_t colour = 0; colour < ncol; ++colour)
-            k_update<KIND, PREC, G, NV><<<grid, 256, 0, stream>>>(
+            k_update<KIND, PREC, G, NV, Q><<<grid, 256, 0, stream>>>(
                 ws.sys, ws.species, ws.batch_list + g.first, pos, orient, ws.start, ws.members, ws.xs,
                 rnd, colour, ws.clock, ws.stats);
 }
 
-template <int KIND, int PREC, int NV>
+template <int KIND, int PREC, int NV, int Q>
 static void launch_passes_nv(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
                              hipStream_t stream) {
     switch (g.lanes) {
-        case 8: launch_passes_g<KIND, PREC, 8, NV>(ws, g, pos, orient, stream); break;
-        case 4: launch_passes_g<KIND, PREC, 4, NV>(ws, g, pos, orient, stream); break;
-        case 2: launch_passes_g<KIND, PREC, 2, NV>(ws, g, pos, orient, stream); break;
-        default: launch_passes_g<KIND, PREC, 1, NV>(ws, g, pos, orient, stream); break;
+        case 8: launch_passes_g<KIND, PREC, 8, NV, Q>(ws, g, pos, orient, stream); break;
+        case 4: launch_passes_g<KIND, PREC, 4, NV, Q>(ws, g, pos, orient, stream); break;
+        case 2: launch_passes_g<KIND, PREC, 2, NV, Q>(ws, g, pos, orient, stream); break;
+        default: launch_passes_g<KIND, PREC, 1, NV, Q>(ws, g, pos, orient, stream); break;
     }
+}
+
+template <int KIND, int PREC, int NV>
+static void launch_global_queue(const Workspace& ws, const BatchGroup& g, double* pos,
+                                double* orient, hipStream_t stream) {
+    const uint32_t ncol = 1u << g.dim;
+    const dim3 by_cell(blocks_for(g.n_act_max, 256), g.count);
+    const int64_t cap = g.n_max << g.dim;
+    const dim3 by_entry((unsigned)std::min<int64_t>(blocks_for(cap, 256), 4096), g.count);
+    const int32_t* list = ws.batch_list + g.first;
+    for (int rnd = 0; rnd < g.rounds_max; ++rnd)
+        for (uint32_t colour = 0; colour < ncol; ++colour) {
+            k_gq_scan<KIND><<<by_cell, 256, 0, stream>>>(ws.sys, ws.species, list, pos, orient,
+                                                         ws.start, ws.members, ws.xs, rnd, colour,
+                                                         ws.clock, ws.gq, ws.stats);
+            k_gq_test<KIND, PREC, NV><<<by_entry, 256, 0, stream>>>(ws.sys, ws.species, list, pos,
+                                                                    orient, ws.members, rnd, ws.gq,
+                                                                    ws.stats);
+            k_gq_apply<KIND><<<by_cell, 256, 0, stream>>>(ws.sys, list, pos, orient, ws.xs, rnd,
+                                                          ws.clock, ws.gq, ws.stats);
+        }
+}
+
+template <int KIND, int PREC, int NV>
+static void launch_passes_q(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
+                            int queue, hipStream_t stream) {
+    if (queue == kQueueGlobal)
+        launch_global_queue<KIND, PREC, NV>(ws, g, pos, orient, stream);
+    else if (queue == kQueueRegister)
+        launch_passes_nv<KIND, PREC, NV, kRegisterQueue>(ws, g, pos, orient, stream);
+    else
+        launch_passes_nv<KIND, PREC, NV, kWaveQueue>(ws, g, pos, orient, stream);
 }
 
 template <int KIND, int PREC>
 static void launch_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
-                          hipStream_t stream) {
+                          int queue, hipStream_t stream) {
     if (KIND == kPolygon && g.nv == 5)
-        launch_passes_nv<KIND, PREC, 5>(ws, g, pos, orient, stream);
+        launch_passes_q<KIND, PREC, 5>(ws, g, pos, orient, queue, stream);
     else
-        launch_passes_nv<KIND, PREC, 0>(ws, g, pos, orient, stream);
+        launch_passes_q<KIND, PREC, 0>(ws, g, pos, orient, queue, stream);
 }
 
 hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
-                       int precision, hipStream_t stream) {
+                       int precision, int queue, hipStream_t stream) {
     if (g.kind == kDisk)
-        launch_passes<kDisk, 0>(ws, g, pos, orient, stream);
+        launch_passes<kDisk, 0>(ws, g, pos, orient, queue, stream);
     else if (g.kind == kPolygon && precision == 1)
-        launch_passes<kPolygon, 1>(ws, g, pos, orient, stream);
+        launch_passes<kPolygon, 1>(ws, g, pos, orient, queue, stream);
     else if (g.kind == kPolygon)
-        launch_passes<kPolygon, 0>(ws, g, pos, orient, stream);
+        launch_passes<kPolygon, 0>(ws, g, pos, orient, queue, stream);
     else if (precision == 1)
-        launch_passes<kPolyhedron, 1>(ws, g, pos, orient, stream);
+        launch_passes<kPolyhedron, 1>(ws, g, pos, orient, queue, stream);
     else
-        launch_passes<kPolyhedron, 0>(ws, g, pos, orient, stream);
+        launch_passes<kPolyhedron, 0>(ws, g, pos, orient, queue, stream);
     return hipGetLastError();
 }
 

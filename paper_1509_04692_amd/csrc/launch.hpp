@@ -11,6 +11,19 @@ namespace hpmc {
 
 constexpr int kBatchBlock = 1024;  // lanes per persistent work-group (16 waves)
 
+constexpr int64_t kGqPerSlot = 8;  // queue entries reserved per particle (2^dim, dim <= 3)
+
+// Global-queue variant of a colour pass: trial state of every active cell and
+// the queue of pair tests in global memory (allocated only when selected).
+struct GlobalQueue {
+    double* trial;      // 7 x cell_total: x, y, z, q0 .. q3 of each active cell
+    uint32_t* meta;     // 3 x cell_total: moving tag, its slot, bits (1 live, 2 rotated, 4 translated)
+    uint32_t* flag;     // cell_total: an overlap was found
+    uint2* entries;     // per replica 2^dim N entries from kGqPerSlot slot_off: (active index, slot)
+    uint32_t* count;    // queued entries per replica (zero between passes)
+    int64_t cell_total; // sum over replicas of ncells + 1
+};
+
 struct Workspace {
     SpeciesDev* species;              // one per replica
     SysDev* sys;                      // one per replica
@@ -32,7 +45,11 @@ struct Workspace {
     double* backup_pos;   // autotuning snapshot of the caller's arrays
     double* backup_ori;
     unsigned long long* backup_stats;
+    GlobalQueue gq;       // null pointers unless the global queue is selected
 };
+
+// How the full overlap tests of a pass are scheduled (grid path).
+enum QueueMode : int32_t { kQueueWave = 0, kQueueRegister = 1, kQueueGlobal = 2 };
 
 struct ReplicaHost {
     int32_t kind, dim, N, n, ncells, rounds, path;
@@ -73,7 +90,7 @@ hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream);
 // All colour passes of sweep t for the replicas of a grid-path group on
 // their global cell lists.
 hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
-                       int precision, hipStream_t stream);
+                       int precision, int queue, hipStream_t stream);
 
 // n_sweeps whole sweeps of the replicas of one batch group, one work-group
 // each.

@@ -50,8 +50,39 @@ def truncated_octahedron_vertices(edge=1.0):
     return v * (edge / math.sqrt(2.0))
 
 
+GOLDEN = (1.0 + math.sqrt(5.0)) / 2.0
+
+
+def dodecahedron_vertices(edge=1.0):
+    """Regular dodecahedron: the cube (+-1, +-1, +-1) and the cyclic
+    permutations of (0, +-1/g, +-g), g the golden ratio (edge 2/g), scaled to
+    `edge`."""
+    g = GOLDEN
+    pts = [(sx, sy, sz) for sx in (-1.0, 1.0) for sy in (-1.0, 1.0) for sz in (-1.0, 1.0)]
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            a, b = s1 / g, s2 * g
+            pts += [(0.0, a, b), (a, b, 0.0), (b, 0.0, a)]
+    return np.array(pts, dtype=np.float64) * (edge * g / 2.0)
+
+
+def dodecahedron_face_normals():
+    """Unit outward normals of the 12 pentagonal faces: the cyclic
+    permutations of (0, +-g, +-1), normalised (the dual icosahedron)."""
+    g = GOLDEN
+    out = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            base = np.array([0.0, s1 * g, s2 * 1.0])
+            out += [np.roll(base, k) for k in range(3)]
+    n = np.array(out)
+    return n / np.linalg.norm(n, axis=1, keepdims=True)
+
+
 CUBE_VOLUME_PER_EDGE3 = 1.0
 TRUNC_OCT_VOLUME_PER_EDGE3 = 8.0 * math.sqrt(2.0)
+DODECA_VOLUME_PER_EDGE3 = (15.0 + 7.0 * math.sqrt(5.0)) / 4.0
+DODECA_INRADIUS_PER_EDGE = GOLDEN ** 2 / (2.0 * math.sqrt(3.0 - GOLDEN))
 
 
 def disk_species(diameter=1.0, d=0.1):
@@ -75,6 +106,16 @@ def truncated_octahedron_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
     return {"dim": 3, "shape": "polyhedron", "verts": truncated_octahedron_vertices(edge),
             "d": float(d), "a": float(a), "p_rot": float(p_rot), "rounds": 0,
             "volume": TRUNC_OCT_VOLUME_PER_EDGE3 * edge ** 3}
+
+
+def dodecahedron_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
+    """Regular dodecahedra; the face normals and inradius are kept for the
+    lattice start only (the method itself takes just the vertices)."""
+    return {"dim": 3, "shape": "polyhedron", "verts": dodecahedron_vertices(edge),
+            "d": float(d), "a": float(a), "p_rot": float(p_rot), "rounds": 0,
+            "volume": DODECA_VOLUME_PER_EDGE3 * edge ** 3,
+            "face_normals": dodecahedron_face_normals(),
+            "inradius": DODECA_INRADIUS_PER_EDGE * edge}
 
 
 def box_length(N, particle_volume, phi, dim):
@@ -125,6 +166,44 @@ def simple_lattice(sp, N, L, seed=INIT_SEED):
         keep = np.sort(rng.choice(m ** dim, size=N, replace=False))
         sites = sites[:, keep]
     pos = np.ascontiguousarray((sites + 0.5) * spacing)
+    return pos, identity_orientations(sp, N)
+
+
+def fcc_lattice(sp, N, L, seed=INIT_SEED):
+    """Aligned polyhedra on a face-centred cubic lattice of 4 m^3 >= N sites
+    (a seeded random subset if larger).
+
+    Two aligned copies of a centrally symmetric convex body K = {x : n_f.x <= h}
+    are disjoint exactly when their displacement t has max_f n_f.t > 2 h, so
+    every lattice vector shorter than the circumsphere diameter is checked
+    against the face normals; raises if one fails.
+    """
+    if sp["dim"] != 3 or "face_normals" not in sp:
+        raise ValueError("fcc_lattice needs a 3D species with face normals")
+    m = 1
+    while 4 * m ** 3 < N:
+        m += 1
+    a = L / m
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    R = float(np.linalg.norm(sp["verts"], axis=1).max())
+    normals, h = sp["face_normals"], sp["inradius"]
+    rng3 = range(-2, 3)
+    for i, j, k in ((i, j, k) for i in rng3 for j in rng3 for k in rng3):
+        for b in basis:
+            t = (np.array([i, j, k], dtype=np.float64) + b) * a
+            dist = np.linalg.norm(t)
+            if dist == 0.0 or dist >= 2.0 * R:
+                continue
+            if (normals @ t).max() <= 2.0 * h * (1 + 1e-9):
+                raise ValueError(f"fcc spacing {a:.4f} too small for the shape")
+    cells = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"),
+                     axis=0).reshape(3, -1, order="F").T
+    sites = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3).T.astype(np.float64)
+    if sites.shape[1] > N:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        keep = np.sort(rng.choice(sites.shape[1], size=N, replace=False))
+        sites = sites[:, keep]
+    pos = np.ascontiguousarray((sites + 0.25) * a)
     return pos, identity_orientations(sp, N)
 
 
@@ -195,6 +274,8 @@ def initial_state(sp, N, phi, seed=INIT_SEED):
             pos, orient = disk_triangular_lattice(sp, N, L, seed)
         elif sp["shape"] == "polygon" and len(sp["verts"]) == 5:
             pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
+        elif "face_normals" in sp:
+            pos, orient = fcc_lattice(sp, N, L, seed)
         else:
             raise
     return L, pos, orient
@@ -224,6 +305,14 @@ def workload_cubes(N=32768, phi=0.45):
 
 def workload_truncated_octahedra(N=32768, phi=0.45):
     sp = truncated_octahedron_species(1.0, d=0.08, a=0.1, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_dodecahedra(N=4096, phi=0.50):
+    """Regular dodecahedra, edge 1, the paper's second benchmark state (fluid
+    at packing fraction 0.5, NVT); translation d=0.08, rotation a=0.1."""
+    sp = dodecahedron_species(1.0, d=0.08, a=0.1, p_rot=0.5)
     L, pos, orient = initial_state(sp, N, phi)
     return sp, N, L, pos, orient
 

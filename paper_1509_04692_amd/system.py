@@ -6,6 +6,10 @@ every step of the sweep runs in the library's HIP kernels.
     sys.count_overlaps()              # system-level overlap check (Sec. 4)
     sys.stats()
 
+``queue`` picks how a pass schedules its full overlap tests: "wave" (the
+block work queue, per wave64 in LDS; the default), or the paper's two
+comparison variants "register" and "global" (grid path only).
+
 ``species`` is a dict (or one per replica) with keys dim, shape ("disk",
 "polygon", "polyhedron"), verts (n x dim), diameter, d, a, p_rot and rounds,
 as produced by ``paper_1509_04692_amd.inputs``.
@@ -29,7 +33,7 @@ def _as_list(x, n):
 
 class System:
     def __init__(self, species, N, L, pos, orient=None, precision="fp64", path="auto",
-                 device="cuda", stream=None, graphs=True):
+                 device="cuda", stream=None, graphs=True, queue="wave"):
         import torch
 
         self._torch = torch
@@ -106,7 +110,9 @@ class System:
         args.pos = self.pos.data_ptr()
         args.orient = self.orient.data_ptr()
         args.stream = stream.cuda_stream
-        args.flags = 0 if graphs else _lib.FLAG_NO_GRAPH
+        if queue not in _lib.QUEUE_FLAGS:
+            raise ValueError(f"queue must be one of {sorted(_lib.QUEUE_FLAGS)}")
+        args.flags = (0 if graphs else _lib.FLAG_NO_GRAPH) | _lib.QUEUE_FLAGS[queue]
         nbytes = ctypes.c_size_t()
         self._check(self._lib.hpmc_workspace_bytes(ctypes.byref(args), ctypes.byref(nbytes)),
                     "hpmc_workspace_bytes")

@@ -44,7 +44,7 @@ def test_strerror(lib):
     assert lib.hpmc_strerror(-99) == b"unknown error"
 
 
-def _args(species_list, Ns, Ls, precision=0, path=0):
+def _args(species_list, Ns, Ls, precision=0, path=0, flags=0):
     n = len(species_list)
     keep = []
     sp_arr = (_lib.Species * n)()
@@ -64,7 +64,7 @@ def _args(species_list, Ns, Ls, precision=0, path=0):
     Narr = (ctypes.c_int32 * n)(*Ns)
     Larr = (ctypes.c_double * n)(*Ls)
     a.N, a.L = Narr, Larr
-    a.precision, a.path = precision, path
+    a.precision, a.path, a.flags = precision, path, flags
     return a, (keep, sp_arr, Narr, Larr)
 
 
@@ -108,3 +108,21 @@ def test_persistent_path_limits(lib):
     # N beyond the 16-bit LDS member index cannot use the persistent path
     assert ws_bytes(lib, [sp], [70000], [400.0], path=2)[0] == -7
     assert ws_bytes(lib, [sp, sp], [4096, 4096], [63.7, 63.7], path=2)[0] == 0
+
+
+def test_queue_variant_flags(lib):
+    sp = inputs.pentagon_species()
+    one = ([sp], [4096], [63.70118630129784])
+    rc0, b0 = ws_bytes(lib, *one)
+    rcr, br = ws_bytes(lib, *one, flags=_lib.QUEUE_FLAGS["register"])
+    rcg, bg = ws_bytes(lib, *one, flags=_lib.QUEUE_FLAGS["global"])
+    assert rc0 == rcr == rcg == 0
+    assert br == b0  # the register queue needs no memory
+    # global queue: 8 entries of 8 B per particle, 7 doubles + 4 words per cell
+    assert bg - b0 >= 64 * 4096 + 72 * (62 * 62 + 1)
+    both = _lib.QUEUE_FLAGS["register"] | _lib.QUEUE_FLAGS["global"]
+    assert ws_bytes(lib, *one, flags=both)[0] == -1
+    two = ([sp, sp], [4096, 4096], [63.7, 63.7])
+    for q in ("register", "global"):
+        assert ws_bytes(lib, *two, path=2, flags=_lib.QUEUE_FLAGS[q])[0] == -7  # grid path only
+        assert ws_bytes(lib, *two, path=0, flags=_lib.QUEUE_FLAGS[q])[0] == 0   # auto: grid

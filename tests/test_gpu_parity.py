@@ -31,10 +31,12 @@ def announce(msg):
     sys.stdout.flush()
 
 
-def run_pair(sp, L, pos, orient, n_sweeps, seed, precision="fp64", path="grid", t0=0):
+def run_pair(sp, L, pos, orient, n_sweeps, seed, precision="fp64", path="grid", t0=0,
+             queue="wave"):
     N = pos.shape[1]
-    announce(f"{sp['shape']} N={N} L={L:.4f} sweeps={n_sweeps} seed={seed} {precision} {path}")
-    system = _system(sp, N, L, pos, orient, precision=precision, path=path)
+    announce(f"{sp['shape']} N={N} L={L:.4f} sweeps={n_sweeps} seed={seed} {precision} {path} "
+             f"queue={queue}")
+    system = _system(sp, N, L, pos, orient, precision=precision, path=path, queue=queue)
     if t0:
         system.sweep_counter = t0
     system.sweep(n_sweeps, seed)
@@ -90,13 +92,15 @@ def test_pentagons_dense_interlocked(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("shape", ["cube", "trunc_oct"])
+@pytest.mark.parametrize("shape", ["cube", "trunc_oct", "dodeca"])
 @pytest.mark.parametrize("path", ["grid", "persistent"])
 def test_polyhedra(shape, path, precision):
     if shape == "cube":
         sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
-    else:
+    elif shape == "trunc_oct":
         sp, N, L, pos, orient = inputs.workload_truncated_octahedra(343, 0.45)
+    else:
+        sp, N, L, pos, orient = inputs.workload_dodecahedra(216, 0.50)
     system, gpu, ref = run_pair(sp, L, pos, orient, 10, seed=3, precision=precision, path=path)
     assert_parity(gpu, ref, sp)
     assert system.count_overlaps()[0] == 0
@@ -148,6 +152,56 @@ def test_batched_heterogeneous_replicas(path):
         if sp["shape"] != "disk":
             assert np.array_equal(system.orientations(r), ref_ori), r
     assert np.all(system.count_overlaps() == 0)
+
+
+@pytest.mark.parametrize("queue", ["register", "global"])
+@pytest.mark.parametrize("case", ["disks", "pentagons_fp64", "pentagons_mixed", "cubes_mixed",
+                                  "cubes_fp64", "dodeca_mixed"])
+def test_queue_variants_equal_the_oracle(queue, case):
+    """The register-queue and global-queue schedules of the full tests give
+    the oracle's trajectory; the global queue has no early exit, so it runs
+    at least as many full tests as the wave queue."""
+    shape, precision = (case.split("_") + ["fp64"])[:2]
+    if shape == "disks":
+        sp, N, L, pos, orient = inputs.workload_disks_256()
+        n_sweeps = 200
+    elif shape == "pentagons":
+        sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.676)
+        n_sweeps = 20
+    elif shape == "cubes":
+        sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
+        n_sweeps = 6
+    else:
+        sp, N, L, pos, orient = inputs.workload_dodecahedra(216, 0.50)
+        n_sweeps = 6
+    system, gpu, ref = run_pair(sp, L, pos, orient, n_sweeps, seed=7, precision=precision,
+                                queue=queue)
+    assert_parity(gpu, ref, sp)
+    assert system.count_overlaps()[0] == 0
+    if queue == "global" and shape != "disks":
+        base = _system(sp, N, L, pos, orient, precision=precision, path="grid")
+        base.sweep(n_sweeps, seed=7)
+        assert gpu[2]["pair_tests"] >= base.stats()[0]["pair_tests"]
+
+
+@pytest.mark.parametrize("queue", ["register", "global"])
+def test_queue_variants_on_a_batch(queue):
+    """Per-replica queue slices: uneven disk and pentagon replicas on the grid
+    path, each equal to the oracle with its own replica word."""
+    batch = inputs.screening_batch(n_replicas=5, seed=2027, n_lo=64, n_hi=900)
+    announce(f"queue {queue} batch N={[b[1] for b in batch]}")
+    system = _system([b[0] for b in batch], [b[1] for b in batch], [b[2] for b in batch],
+                     [b[3] for b in batch], [b[4] for b in batch], precision="mixed",
+                     path="grid", queue=queue)
+    system.sweep(15, seed=13)
+    stats = system.stats()
+    for r, (sp, N, L, pos, orient) in enumerate(batch):
+        ref_pos, ref_ori = pos.copy(), orient.copy()
+        ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=13, n_sweeps=15, replica=r)
+        assert [stats[r][k] for k in PARITY] == [int(x) for x in ref_stats], r
+        assert np.array_equal(system.positions(r), ref_pos), r
+        if sp["shape"] != "disk":
+            assert np.array_equal(system.orientations(r), ref_ori), r
 
 
 @pytest.mark.parametrize("path", ["grid", "persistent"])
@@ -301,10 +355,12 @@ def test_full_size_large_pentagons_one_sweep():
         del system
 
 
-def test_full_size_cubes_and_truncated_octahedra():
-    """N=32768 cubes (2 rounds per sweep) and truncated octahedra at phi=0.45."""
+def test_full_size_polyhedra():
+    """N=32768 cubes (2 rounds per sweep) and truncated octahedra at phi=0.45,
+    N=4096 dodecahedra at phi=0.5."""
     for sp, N, L, pos, orient in (inputs.workload_cubes(32768, 0.45),
-                                  inputs.workload_truncated_octahedra(32768, 0.45)):
+                                  inputs.workload_truncated_octahedra(32768, 0.45),
+                                  inputs.workload_dodecahedra(4096, 0.50)):
         for precision in ("fp64", "mixed"):
             system, gpu, ref = run_pair(sp, L, pos, orient, 2, seed=1, precision=precision,
                                         path="grid")

@@ -1,0 +1,68 @@
+"""Pins of the synthetic shape tables and lattice starts.
+
+* Regular dodecahedron (the paper's second benchmark shape, Sec. 4): 20
+  vertices on the circumsphere of radius g sqrt(3)/2 per unit edge, 30 edges of
+  unit length, 12 faces of 5 vertices each at the inradius, and the closed-form
+  volume (15 + 7 sqrt 5)/4.
+* The face-centred cubic start: two aligned copies of a centrally symmetric
+  polytope are disjoint exactly when max_f n_f.t > 2h; this criterion is
+  checked against the oracle's XenoCollide test, and the lattice at packing
+  fraction 0.5 is overlap-free by the oracle's cell-list count.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import ConvexHull
+
+import oracle
+from paper_1509_04692_amd import inputs
+
+G = (1 + math.sqrt(5)) / 2
+
+
+def test_dodecahedron_table():
+    v = inputs.dodecahedron_vertices(1.0)
+    assert v.shape == (20, 3)
+    assert np.allclose(np.linalg.norm(v, axis=1), G * math.sqrt(3) / 2, rtol=1e-15, atol=0)
+    d = np.linalg.norm(v[:, None] - v[None], axis=2)
+    edges = np.argwhere(np.isclose(d, 1.0, rtol=1e-12) & (np.arange(20)[:, None] < np.arange(20)))
+    assert len(edges) == 30
+    assert np.all(d[~np.eye(20, dtype=bool)] > 1.0 - 1e-12)
+    assert math.isclose(ConvexHull(v).volume, (15 + 7 * math.sqrt(5)) / 4, rel_tol=1e-13)
+    n = inputs.dodecahedron_face_normals()
+    p = v @ n.T
+    h = inputs.DODECA_INRADIUS_PER_EDGE
+    assert np.allclose(p.max(axis=0), h, rtol=1e-14)
+    assert np.all(np.sum(np.isclose(p, h, rtol=1e-12), axis=0) == 5)
+    sp = inputs.dodecahedron_species()
+    assert math.isclose(sp["volume"], ConvexHull(sp["verts"]).volume, rel_tol=1e-13)
+
+
+def test_aligned_disjointness_criterion_matches_xenocollide():
+    sp = inputs.dodecahedron_species()
+    n, h = sp["face_normals"], sp["inradius"]
+    rng = np.random.Generator(np.random.PCG64(31))
+    ident = [1.0, 0.0, 0.0, 0.0]
+    checked = hits = 0
+    for _ in range(2000):
+        t = rng.normal(size=3)
+        t *= rng.uniform(1.8, 3.0) / np.linalg.norm(t)
+        gauge = (n @ t).max()
+        if abs(gauge - 2 * h) < 1e-6:
+            continue
+        want = gauge <= 2 * h
+        assert oracle.overlap_full(sp, t, ident, ident) == want, t
+        checked += 1
+        hits += want
+    assert checked > 1900 and 0.1 < hits / checked < 0.9
+
+
+@pytest.mark.parametrize("N", [216, 4096])
+def test_fcc_start_is_overlap_free(N):
+    sp, N, L, pos, orient = inputs.workload_dodecahedra(N, 0.50)
+    assert pos.shape == (3, N) and np.all((pos >= 0) & (pos < L))
+    assert oracle.count_overlaps(sp, L, pos, orient) == 0
+    # the same lattice compressed to contact fails its own check
+    with pytest.raises(ValueError):
+        inputs.fcc_lattice(sp, N, L * 0.75)

@@ -228,7 +228,8 @@ def polyhedron_cases(rng, n, R):
         yield d * rr, random_quat(rng), random_quat(rng)
 
 
-SHAPES_3D = {"cube": inputs.cube_species(), "trunc_oct": inputs.truncated_octahedron_species()}
+SHAPES_3D = {"cube": inputs.cube_species(), "trunc_oct": inputs.truncated_octahedron_species(),
+             "dodeca": inputs.dodecahedron_species()}
 
 
 @pytest.mark.parametrize("name", sorted(SHAPES_3D))

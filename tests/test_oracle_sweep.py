@@ -33,6 +33,7 @@ def closed_form_grid(N, v0, phi, dim, dmax):
     ("pentagons_large", inputs.pentagon_species(), 4194304, 0.60, 2038, 1),
     ("cubes", inputs.cube_species(), 32768, 0.45, 24, 2),
     ("trunc_oct", inputs.truncated_octahedron_species(), 32768, 0.45, 28, 1),
+    ("dodecahedra", inputs.dodecahedron_species(), 4096, 0.50, 14, 1),
 ])
 def test_grid_matches_closed_form(name, sp, N, phi, n_expect, rounds_expect):
     info = oracle.shape_info(sp)
@@ -57,7 +58,7 @@ def test_box_too_small_is_rejected():
 
 def test_circumradius_encloses_every_vertex():
     for sp in (inputs.pentagon_species(), inputs.cube_species(),
-               inputs.truncated_octahedron_species()):
+               inputs.truncated_octahedron_species(), inputs.dodecahedron_species()):
         R = oracle.shape_info(sp)["R"]
         assert np.all(np.linalg.norm(sp["verts"], axis=1) <= R)
         assert R - np.max(np.linalg.norm(sp["verts"], axis=1)) < 1e-15
@@ -70,10 +71,12 @@ def _workloads():
         "pentagons_dense": inputs.workload_pentagons(400, 0.70),
         "cubes": inputs.workload_cubes(512, 0.45),
         "trunc_oct": inputs.workload_truncated_octahedra(216, 0.45),
+        "dodecahedra": inputs.workload_dodecahedra(216, 0.50),
     }
 
 
-@pytest.mark.parametrize("name", ["disks", "pentagons", "pentagons_dense", "cubes", "trunc_oct"])
+@pytest.mark.parametrize("name", ["disks", "pentagons", "pentagons_dense", "cubes", "trunc_oct",
+                                  "dodecahedra"])
 def test_no_overlaps_after_every_sweep(name):
     sp, N, L, pos, orient = _workloads()[name]
     assert oracle.count_overlaps(sp, L, pos, orient) == 0
