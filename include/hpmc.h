@@ -151,7 +151,8 @@ int hpmc_init(hpmc_state **out, const hpmc_init_args *args);
 int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
 
 /* Time the launch configurations this state can use (grid path: lanes per
- * active cell 1, 2, 4, 8; persistent path: which particle data stays in LDS)
+ * active cell 1, 2, 4, ..., 64, or 1 .. 8 with the register queue and 1 with
+ * the global queue; persistent path: which particle data stays in LDS)
  * over trial_sweeps sweeps each, keep the fastest, and restore positions,
  * orientations, counters and the sweep counter exactly.  The trajectory does
  * not depend on the configuration.  With HPMC_MIXED and polyhedra the
@@ -160,6 +161,12 @@ int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
  * receives the chosen lanes per cell (grid) or residency level (persistent)
  * in its low byte, plus 0x100 when MIXED polyhedra walk in binary64. */
 int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
+
+/* Apply a launch configuration in the encoding hpmc_autotune returns, e.g. one
+ * found by an earlier autotuning run of the same kind of system.  Any listed
+ * configuration gives the same trajectory.  Synchronising.  Returns
+ * HPMC_ERR_INVALID_ARG for a configuration this state cannot use. */
+int hpmc_set_config(hpmc_state *st, int32_t config);
 
 /* Histogram of pair separations of one replica, the sampling behind the
  * pressure check of Sec. 4 (the contact value of g(r) for disks, Table 1):

@@ -26,7 +26,7 @@ STAT_FIELDS = ("attempted", "attempted_rot", "cell_reject", "overlap_reject", "a
                "pair_tests", "pair_fp64", "sweeps")
 
 # Every symbol include/hpmc.h declares.
-EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune",
+EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune", "hpmc_set_config",
            "hpmc_count_overlaps", "hpmc_pair_histogram", "hpmc_get_stats", "hpmc_reset_stats",
            "hpmc_sync_to_canonical", "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info",
            "hpmc_uses_graph", "hpmc_last_hip_error", "hpmc_destroy", "hpmc_strerror")
@@ -95,6 +95,7 @@ def load(path=None):
     lib.hpmc_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(InitArgs)]
     lib.hpmc_sweep.argtypes = [st, ctypes.c_uint64, ctypes.c_uint64]
     lib.hpmc_autotune.argtypes = [st, ctypes.c_uint32, ctypes.POINTER(ctypes.c_int32)]
+    lib.hpmc_set_config.argtypes = [st, ctypes.c_int32]
     lib.hpmc_uses_graph.argtypes = [st]
     lib.hpmc_count_overlaps.argtypes = [st, ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_pair_histogram.argtypes = [st, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -261,7 +262,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     list.clear();
     if (path == HPMC_PATH_PERSISTENT) {
         for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
-            BatchGroup g{kind, (int32_t)list.size(), 0, 0, -1, 0, {0, 0, 0}};
+            BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}};
             const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
             size_t need[3] = {0, 0, 0};
             for (int r = 0; r < R; ++r) {
@@ -280,6 +281,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
                     g.resident = lv;
                     break;
                 }
+            g.resident_max = g.resident;
             g.lds_bytes = need[g.resident];
             for (int lv = 0; lv < 3; ++lv) g.need[lv] = need[lv];
             if (g.nv < 0) g.nv = 0;
@@ -288,7 +290,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     } else {
         // grid path: one launch per step for all replicas of a kind
         for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
-            BatchGroup g{kind, (int32_t)list.size(), 0, 0, -1, 0, {0, 0, 0}, 0, 1, 0, 0, 0, 0};
+            BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}, 0, 1, 0, 0, 0, 0};
             int64_t n_act_total = 0;
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
@@ -433,6 +435,56 @@ void capture_graph(hpmc_state* st) {
 }
 
 // Run n_sweeps from the current counter with key (k0, k1).
+// Launch configurations of a state: lanes per cell (grid) or residency level
+// (persistent) in the low byte, plus kWalk64 when MIXED polyhedra take the
+// binary64 walk.
+constexpr int kWalk64 = 0x100;
+
+std::vector<int> config_candidates(const hpmc_state* st) {
+    std::vector<int> cands;
+    if (st->path == HPMC_PATH_PERSISTENT) {
+        int top = 0;
+        for (const BatchGroup& g : st->groups) top = std::max(top, (int)g.resident_max);
+        for (int lv = top; lv >= 0; --lv) cands.push_back(lv);
+    } else if (st->queue == kQueueGlobal) {
+        cands = {1};  // one lane per cell or queued pair: nothing to choose but the walk
+    } else if (st->queue == kQueueWave) {
+        cands = {1, 2, 4, 8, 16, 32, 64};
+    } else {
+        cands = {1, 2, 4, 8};
+    }
+    bool poly_mixed = false;
+    for (const BatchGroup& g : st->groups) poly_mixed |= g.kind == kPolyhedron && st->precision == HPMC_MIXED;
+    if (poly_mixed) {
+        const size_t n0 = cands.size();
+        for (size_t i = 0; i < n0; ++i) cands.push_back(cands[i] | kWalk64);
+    }
+    return cands;
+}
+
+// Switch to configuration cfg (one of config_candidates) and re-capture the
+// sweep graph.
+int apply_config(hpmc_state* st, int cfg) {
+    const std::vector<int> cands = config_candidates(st);
+    if (std::find(cands.begin(), cands.end(), cfg) == cands.end()) return HPMC_ERR_INVALID_ARG;
+    const int c = cfg & 0xff;
+    st->walk64 = (cfg & kWalk64) ? 1 : 0;
+    if (st->path == HPMC_PATH_PERSISTENT) {
+        for (BatchGroup& g : st->groups) {
+            g.resident = std::min<int>(c, g.resident_max);
+            g.lds_bytes = g.need[g.resident];
+            const int rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient,
+                                                           group_precision(st, g), 0, true, st->stream));
+            if (rc) return rc;
+        }
+    } else {
+        for (ReplicaHost& rh : st->rep) rh.lanes_per_cell = c;
+        for (BatchGroup& g : st->groups) g.lanes = c;
+    }
+    capture_graph(st);
+    return HPMC_OK;
+}
+
 int run_sweeps(hpmc_state* st, uint64_t n_sweeps, uint32_t k0, uint32_t k1) {
     int rc = check_hip(st, set_clock(st->ws, (uint32_t)st->t, k0, k1, st->stream));
     const uint32_t unit = sweep_unit(st);
@@ -718,43 +770,8 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
         rc = check_hip(st, hipMemcpyAsync(st->ws.backup_stats, st->ws.stats, 8 * nstat,
                                           hipMemcpyDeviceToDevice, st->stream));
     if (rc) return rc;
-    // configuration = lanes per cell (grid) or residency level (persistent),
-    // plus kWalk64 when MIXED polyhedra take the binary64 walk
-    constexpr int kWalk64 = 0x100;
-    std::vector<int> cands;
-    if (st->path == HPMC_PATH_PERSISTENT) {
-        int top = 0;
-        for (const BatchGroup& g : st->groups) top = std::max(top, (int)g.resident);
-        for (int lv = top; lv >= 0; --lv) cands.push_back(lv);
-    } else if (st->queue == kQueueGlobal) {
-        cands = {1};  // one lane per cell or queued pair: nothing to choose but the walk
-    } else {
-        cands = {1, 2, 4, 8};
-    }
-    bool poly_mixed = false;
-    for (const BatchGroup& g : st->groups) poly_mixed |= g.kind == kPolyhedron && st->precision == HPMC_MIXED;
-    if (poly_mixed) {
-        const size_t n0 = cands.size();
-        for (size_t i = 0; i < n0; ++i) cands.push_back(cands[i] | kWalk64);
-    }
-    const std::vector<BatchGroup> groups0 = st->groups;
-    auto apply = [&](int cfg) {
-        const int c = cfg & 0xff;
-        st->walk64 = (cfg & kWalk64) ? 1 : 0;
-        if (st->path == HPMC_PATH_PERSISTENT) {
-            for (size_t i = 0; i < st->groups.size(); ++i) {
-                BatchGroup& g = st->groups[i];
-                g.resident = std::min<int>(c, groups0[i].resident);
-                g.lds_bytes = g.need[g.resident];
-                (void)persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), 0, true,
-                                        st->stream);
-            }
-        } else {
-            for (ReplicaHost& rh : st->rep) rh.lanes_per_cell = c;
-            for (BatchGroup& g : st->groups) g.lanes = c;
-        }
-        capture_graph(st);
-    };
+    std::vector<int> cands = config_candidates(st);
+    auto apply = [&](int cfg) { (void)apply_config(st, cfg); };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc) rc = check_hip(st, hipEventCreate(&e0));
     if (!rc) rc = check_hip(st, hipEventCreate(&e1));
@@ -789,6 +806,13 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
     if (!rc) apply(best);
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
     if (!rc && out_config) *out_config = best;
+    return rc;
+}
+
+int hpmc_set_config(hpmc_state* st, int32_t config) {
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    int rc = check_hip(st, hipStreamSynchronize(st->stream));
+    if (!rc) rc = apply_config(st, config);
     return rc;
 }
 

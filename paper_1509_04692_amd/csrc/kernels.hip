@@ -861,7 +861,20 @@ static void launch_passes_g(const Workspace& ws, const BatchGroup& g, double* po
 template <int KIND, int PREC, int NV, int Q>
 static void launch_passes_nv(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
                              hipStream_t stream) {
+    // 16 to 64 lanes per cell: the wave queue only (few cells per wave, so a
+    // pass of a small system runs more, shorter waves)
+    if constexpr (Q == kWaveQueue) {
+        switch (g.lanes) {
+            case 64: launch_passes_g<KIND, PREC, 64, NV, Q>(ws, g, pos, orient, stream); return;
+            case 32: launch_passes_g<KIND, PREC, 32, NV, Q>(ws, g, pos, orient, stream); return;
+            case 16: launch_passes_g<KIND, PREC, 16, NV, Q>(ws, g, pos, orient, stream); return;
+            default: break;
+        }
+    }
     switch (g.lanes) {
+        case 64:
+        case 32:
+        case 16:
         case 8: launch_passes_g<KIND, PREC, 8, NV, Q>(ws, g, pos, orient, stream); break;
         case 4: launch_passes_g<KIND, PREC, 4, NV, Q>(ws, g, pos, orient, stream); break;
         case 2: launch_passes_g<KIND, PREC, 2, NV, Q>(ws, g, pos, orient, stream); break;

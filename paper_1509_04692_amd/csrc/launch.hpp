@@ -53,7 +53,7 @@ enum QueueMode : int32_t { kQueueWave = 0, kQueueRegister = 1, kQueueGlobal = 2 
 
 struct ReplicaHost {
     int32_t kind, dim, N, n, ncells, rounds, path;
-    int32_t lanes_per_cell;  // grid path: lanes per active cell (1, 2, 4, 8)
+    int32_t lanes_per_cell;  // grid path: lanes per active cell (1, 2, 4, ..., 64)
     int32_t nv;              // polygon vertex count (compile-time fast path for 5)
     int64_t pos_off, orient_off;
 };
@@ -63,6 +63,7 @@ struct ReplicaHost {
 struct BatchGroup {
     int32_t kind, first, count;
     int32_t resident;  // persistent: 0 none, 1 positions, 2 positions + orientations in LDS
+    int32_t resident_max;  // highest level whose LDS fits
     int32_t nv;        // common polygon vertex count, 0 when mixed or not a polygon
     size_t lds_bytes;
     size_t need[3];    // dynamic LDS per residency level

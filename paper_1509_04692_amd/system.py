@@ -146,6 +146,10 @@ class System:
                     "hpmc_autotune")
         return cfg.value
 
+    def set_config(self, config):
+        """Apply a configuration in the encoding autotune() returns."""
+        self._check(self._lib.hpmc_set_config(self._handle, int(config)), "hpmc_set_config")
+
     @property
     def uses_graph(self):
         return bool(self._lib.hpmc_uses_graph(self._handle))

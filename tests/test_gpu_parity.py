@@ -121,7 +121,7 @@ def test_autotuned_mixed_polyhedra_equal_the_oracle():
     announce("autotune mixed cubes")
     system = _system(sp, N, L, pos, orient, precision="mixed", path="grid")
     cfg = system.autotune(trial_sweeps=2)
-    assert (cfg & 0xff) in (1, 2, 4, 8) and cfg & ~0x1ff == 0
+    assert (cfg & 0xff) in (1, 2, 4, 8, 16, 32, 64) and cfg & ~0x1ff == 0
     system.sweep(8, seed=3)
     ref_pos, ref_ori = pos.copy(), orient.copy()
     ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=3, n_sweeps=8)
@@ -152,6 +152,48 @@ def test_batched_heterogeneous_replicas(path):
         if sp["shape"] != "disk":
             assert np.array_equal(system.orientations(r), ref_ori), r
     assert np.all(system.count_overlaps() == 0)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("shape", ["pentagons", "cubes", "dodeca"])
+def test_every_lane_count_equals_the_oracle(shape, lanes):
+    """Grid path with 1 .. 64 lanes per active cell (set directly): the
+    oracle's trajectory whatever the group size."""
+    if shape == "pentagons":
+        sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.60)
+        prec, n_sweeps = "fp64", 10
+    elif shape == "cubes":
+        sp, N, L, pos, orient = inputs.workload_cubes(1000, 0.45)
+        prec, n_sweeps = "mixed", 4
+    else:
+        sp, N, L, pos, orient = inputs.workload_dodecahedra(216, 0.50)
+        prec, n_sweeps = "mixed", 4
+    announce(f"{shape} lanes={lanes} {prec}")
+    system = _system(sp, N, L, pos, orient, precision=prec, path="grid")
+    system.set_config(lanes)
+    system.sweep(n_sweeps, seed=17)
+    ref_pos, ref_ori = pos.copy(), orient.copy()
+    ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=17, n_sweeps=n_sweeps)
+    assert_parity((system.positions(), system.orientations(), system.stats()[0]),
+                  (ref_pos, ref_ori, ref_stats), sp)
+
+
+def test_set_config_rejects_what_the_state_cannot_use():
+    from paper_1509_04692_amd._lib import HpmcError
+    sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.60)
+    announce("set_config errors")
+    grid = _system(sp, N, L, pos, orient, path="grid")
+    for bad in (0, 3, 128, 0x101, -1):  # walk64 only for mixed polyhedra
+        with pytest.raises(HpmcError):
+            grid.set_config(bad)
+    reg = _system(sp, N, L, pos, orient, path="grid", queue="register")
+    with pytest.raises(HpmcError):
+        reg.set_config(16)
+    reg.set_config(8)
+    pers = _system([sp, sp], [N, N], [L, L], [pos, pos], [orient, orient], path="persistent")
+    pers.set_config(0)
+    with pytest.raises(HpmcError):
+        pers.set_config(3)
 
 
 @pytest.mark.parametrize("queue", ["register", "global"])
@@ -239,7 +281,7 @@ def test_graph_replay_direct_launch_and_autotune_agree(path):
     assert np.array_equal(g.orientations(), d.orientations())
     before = (g.positions().copy(), g.orientations().copy(), g.stats(), g.sweep_counter)
     cfg = g.autotune(trial_sweeps=4)
-    assert cfg in ((0, 1, 2) if path == "persistent" else (1, 2, 4, 8))
+    assert cfg in ((0, 1, 2) if path == "persistent" else (1, 2, 4, 8, 16, 32, 64))
     assert np.array_equal(g.positions(), before[0]) and np.array_equal(g.orientations(), before[1])
     assert g.stats() == before[2] and g.sweep_counter == before[3]
     g.sweep(30, seed=9)
