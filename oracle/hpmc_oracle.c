@@ -166,6 +166,7 @@ typedef struct {
     double nrm[OR_MAXV][2];               /* polygon outward edge normals */
     double pmin[OR_MAXV], pmax[OR_MAXV];  /* own projections onto them */
     double R, dmax, circ2, tol2;
+    double sweep;  /* sweep radius of a spheropolyhedron, 0 otherwise */
 } shape_t;
 
 static int setup_shape(const or_species *sp, shape_t *sh)
@@ -174,7 +175,7 @@ static int setup_shape(const or_species *sp, shape_t *sh)
     sh->dim = sp->dim;
     sh->kind = sp->shape;
     if (sp->shape == OR_DISK) {
-        if (sp->dim != 2 || !(sp->diameter > 0.0))
+        if (sp->dim != 2 || !(sp->diameter > 0.0) || sp->sweep_radius != 0.0)
             return OR_ERR_INVALID_ARG;
         sh->R = sp->diameter * 0.5;
     } else {
@@ -183,7 +184,13 @@ static int setup_shape(const or_species *sp, shape_t *sh)
             return OR_ERR_INVALID_ARG;
         if (sp->dim != want_dim || sp->verts == NULL)
             return OR_ERR_INVALID_ARG;
-        if (sp->n_verts < want_dim + 1 || sp->n_verts > OR_MAXV)
+        if (!(sp->sweep_radius >= 0.0) || !isfinite(sp->sweep_radius))
+            return OR_ERR_INVALID_ARG;
+        if (sp->sweep_radius > 0.0 && sp->shape != OR_POLYHEDRON)
+            return OR_ERR_INVALID_ARG; /* rounded shapes: polyhedra only */
+        sh->sweep = sp->sweep_radius;
+        int min_verts = sh->sweep > 0.0 ? 1 : want_dim + 1;
+        if (sp->n_verts < min_verts || sp->n_verts > OR_MAXV)
             return OR_ERR_INVALID_ARG;
         sh->nv = sp->n_verts;
         double rmax = 0.0;
@@ -197,8 +204,9 @@ static int setup_shape(const or_species *sp, shape_t *sh)
             if (r > rmax)
                 rmax = r;
         }
-        /* one ulp up so that every vertex lies inside the circumsphere */
-        sh->R = nextafter(rmax, INFINITY);
+        /* one ulp up so that every vertex (and, for a spheropolyhedron,
+         * every point within the sweep radius of one) lies inside */
+        sh->R = nextafter(rmax + sh->sweep, INFINITY);
         if (sp->shape == OR_POLYGON) {
             for (int k = 0; k < sh->nv; ++k) {
                 int k1 = (k + 1) % sh->nv, k2 = (k + 2) % sh->nv;
@@ -366,7 +374,9 @@ typedef struct {
 /* Support point of the Minkowski difference B - A in direction n, in A's
  * frame: S_{B-A}(n) = M S_B(M^T n) + t - S_A(-n) (Eq. 2 with the centre
  * offset expressed in A's frame).  S_X(n) is the first vertex attaining the
- * largest n . v. */
+ * largest n . v.  A spheropolyhedron of sweep radius s is its hull plus a
+ * ball of radius s, whose support adds s n/|n|; both particles share s, so
+ * the difference gains (s + s) n/|n| (skipped for n = 0). */
 static void support(const mink_t *mk, const double n[3], double out[3])
 {
     const shape_t *sh = mk->sh;
@@ -395,6 +405,16 @@ static void support(const mink_t *mk, const double n[3], double out[3])
         double sb = ((mk->m[a][0] * sh->v[kb][0] + mk->m[a][1] * sh->v[kb][1])
                      + mk->m[a][2] * sh->v[kb][2]) + mk->t[a];
         out[a] = sb - sh->v[ka][a];
+    }
+    double nn = dot3(n, n);
+    if (sh->sweep > 0.0 && nn > 0.0) {
+#ifdef ORACLE_PLANT_SWEEP_ONE_SIDED
+        double s = sh->sweep / sqrt(nn);
+#else
+        double s = (sh->sweep + sh->sweep) / sqrt(nn);
+#endif
+        for (int a = 0; a < 3; ++a)
+            out[a] = out[a] + s * n[a];
     }
 }
 

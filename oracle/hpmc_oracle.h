@@ -51,6 +51,11 @@ typedef struct {
     double a;             /* rotation size */
     double p_rot;         /* probability that a move is a rotation */
     int32_t rounds;       /* colour rounds per sweep, 0 = automatic */
+    double sweep_radius;  /* polyhedra: the shape is every point within this
+                             distance of the convex hull of verts (a
+                             spheropolyhedron, Sec. 2.3); 0 = the hull itself.
+                             With sweep_radius > 0, 1..OR_MAXV vertices (one
+                             vertex: a sphere, two: a spherocylinder). */
 } or_species;
 
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -49,6 +49,7 @@ class _Species(ctypes.Structure):
         ("a", ctypes.c_double),
         ("p_rot", ctypes.c_double),
         ("rounds", ctypes.c_int32),
+        ("sweep_radius", ctypes.c_double),
     ]
 
 
@@ -148,6 +149,7 @@ def _species(sp):
     s.a = float(sp.get("a", 0.0))
     s.p_rot = float(sp.get("p_rot", 0.0))
     s.rounds = int(sp.get("rounds", 0))
+    s.sweep_radius = float(sp.get("sweep_radius", 0.0))
     return s, verts
 
 

@@ -118,6 +118,36 @@ def dodecahedron_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
             "inradius": DODECA_INRADIUS_PER_EDGE * edge}
 
 
+# -- spheropolyhedra: a vertex hull swept by a ball (sweep_radius > 0) ----------
+
+def sphere_species(diameter=1.0, d=0.1):
+    """A sphere as the one-vertex spheropolyhedron (orientation irrelevant;
+    rotation moves off)."""
+    r = 0.5 * diameter
+    return {"dim": 3, "shape": "polyhedron", "verts": np.zeros((1, 3)), "sweep_radius": r,
+            "d": float(d), "a": 0.0, "p_rot": 0.0, "rounds": 0,
+            "volume": 4.0 / 3.0 * math.pi * r ** 3}
+
+
+def spherocylinder_species(length=1.0, radius=0.5, d=0.08, a=0.1, p_rot=0.5):
+    """Segment of `length` along z swept by a ball of `radius`."""
+    v = np.array([[0.0, 0.0, -0.5 * length], [0.0, 0.0, 0.5 * length]])
+    return {"dim": 3, "shape": "polyhedron", "verts": v, "sweep_radius": float(radius),
+            "d": float(d), "a": float(a), "p_rot": float(p_rot), "rounds": 0,
+            "volume": math.pi * radius ** 2 * length + 4.0 / 3.0 * math.pi * radius ** 3}
+
+
+def rounded_cube_species(edge=1.0, radius=0.1, d=0.08, a=0.1, p_rot=0.5):
+    """Cube of `edge` swept by a ball of `radius`; volume by the Steiner
+    formula V + S r + (pi/4) (sum of edge lengths x dihedral defects) r^2 +
+    (4/3) pi r^3 = a^3 + 6 a^2 r + 3 pi a r^2 + (4/3) pi r^3."""
+    return {"dim": 3, "shape": "polyhedron", "verts": cube_vertices(edge),
+            "sweep_radius": float(radius), "d": float(d), "a": float(a),
+            "p_rot": float(p_rot), "rounds": 0,
+            "volume": edge ** 3 + 6 * edge ** 2 * radius + 3 * math.pi * edge * radius ** 2
+            + 4.0 / 3.0 * math.pi * radius ** 3}
+
+
 def box_length(N, particle_volume, phi, dim):
     """Side of the square / cubic periodic box holding N particles at phi."""
     return (N * particle_volume / phi) ** (1.0 / dim)
@@ -128,7 +158,7 @@ def aligned_extent(sp):
     if sp["shape"] == "disk":
         return np.full(2, sp["diameter"])
     v = np.asarray(sp["verts"])
-    return v.max(axis=0) - v.min(axis=0)
+    return v.max(axis=0) - v.min(axis=0) + 2.0 * sp.get("sweep_radius", 0.0)
 
 
 def identity_orientations(sp, N):
@@ -313,6 +343,27 @@ def workload_dodecahedra(N=4096, phi=0.50):
     """Regular dodecahedra, edge 1, the paper's second benchmark state (fluid
     at packing fraction 0.5, NVT); translation d=0.08, rotation a=0.1."""
     sp = dodecahedron_species(1.0, d=0.08, a=0.1, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_spheres(N=4096, phi=0.40):
+    sp = sphere_species(1.0, d=0.1)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_spherocylinders(N=4096, phi=0.15):
+    """Spherocylinders of aspect (length + 2 radius) / (2 radius) = 2 on a
+    simple cubic lattice (whose pitch the long axis sets, hence the low
+    packing fraction)."""
+    sp = spherocylinder_species(1.0, 0.5, d=0.08, a=0.1, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_rounded_cubes(N=4096, phi=0.45):
+    sp = rounded_cube_species(1.0, 0.1, d=0.08, a=0.1, p_rot=0.5)
     L, pos, orient = initial_state(sp, N, phi)
     return sp, N, L, pos, orient
 

@@ -66,3 +66,26 @@ def test_fcc_start_is_overlap_free(N):
     # the same lattice compressed to contact fails its own check
     with pytest.raises(ValueError):
         inputs.fcc_lattice(sp, N, L * 0.75)
+
+
+@pytest.mark.parametrize("name", ["sphere", "spherocylinder", "rounded_cube"])
+def test_swept_shape_volumes_by_sampling(name):
+    """Closed-form volumes of the swept shapes against the fraction of seeded
+    uniform points of the bounding box within the sweep radius of the core
+    (point, segment, cube), 2e6 points: within 0.5 %."""
+    sp = {"sphere": inputs.sphere_species(1.0),
+          "spherocylinder": inputs.spherocylinder_species(1.0, 0.5),
+          "rounded_cube": inputs.rounded_cube_species(1.0, 0.1)}[name]
+    s = sp["sweep_radius"]
+    half = inputs.aligned_extent(sp) / 2
+    rng = np.random.Generator(np.random.PCG64(51))
+    p = rng.uniform(-half, half, size=(2_000_000, 3))
+    if name == "sphere":
+        dist = np.linalg.norm(p, axis=1)
+    elif name == "spherocylinder":
+        z = np.clip(p[:, 2], -0.5, 0.5)
+        dist = np.linalg.norm(p - np.stack([0 * z, 0 * z, z], axis=1), axis=1)
+    else:
+        dist = np.linalg.norm(np.maximum(np.abs(p) - 0.5, 0.0), axis=1)
+    vol = np.mean(dist <= s) * np.prod(2 * half)
+    assert abs(vol / sp["volume"] - 1) < 5e-3

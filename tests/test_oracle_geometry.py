@@ -324,3 +324,123 @@ def test_xenocollide_pins_detect_planted_mistakes(planted, flag):
             continue
         mismatches += oracle.overlap_full(sp, r, qa, qb, lib=lib) != (gap < 0)
     assert mismatches > 0
+
+
+# -- spheropolyhedra (hull swept by a ball; support gains s n/|n|) -------------
+
+def _rand_unit(rng):
+    d = rng.normal(size=3)
+    return d / np.linalg.norm(d)
+
+
+def test_sphere_closed_form():
+    """One-vertex spheropolyhedron of sweep radius 1/2: the unit-diameter
+    sphere, overlapping exactly when the centres are closer than 1."""
+    sp = inputs.sphere_species(1.0)
+    rng = np.random.Generator(np.random.PCG64(41))
+    hits = 0
+    for _ in range(3000):
+        dist = rng.uniform(0.0, 1.3)
+        if abs(dist - 1.0) < 1e-9:
+            continue
+        want = dist < 1.0
+        assert oracle.overlap_full(sp, _rand_unit(rng) * dist, random_quat(rng), random_quat(rng)) == want
+        hits += want
+    assert 0.6 < hits / 3000 < 0.9
+
+
+def segment_distance(p0, p1, q0, q1):
+    """Distance between segments [p0, p1] and [q0, q1]: the convex quadratic
+    |r + s d1 - t d2|^2 over the unit square is smallest at its interior
+    critical point or on an edge, where the 1D minimiser is clamped."""
+    d1, d2, r = p1 - p0, q1 - q0, p0 - q0
+    a, e, b = d1 @ d1, d2 @ d2, d1 @ d2
+    c, f = d1 @ r, d2 @ r
+    cands = []
+    m = np.array([[a, -b], [b, -e]])
+    if abs(np.linalg.det(m)) > 1e-12:
+        s, t = np.linalg.solve(m, [-c, -f])
+        if 0.0 <= s <= 1.0 and 0.0 <= t <= 1.0:
+            cands.append((s, t))
+    for s in (0.0, 1.0):
+        cands.append((s, float(np.clip((f + b * s) / e, 0.0, 1.0))))
+    for t in (0.0, 1.0):
+        cands.append((float(np.clip((b * t - c) / a, 0.0, 1.0)), t))
+    return min(np.linalg.norm(r + s * d1 - t * d2) for s, t in cands)
+
+
+def test_spherocylinder_closed_form():
+    """Two-vertex spheropolyhedron: overlap exactly when the core segments are
+    closer than twice the sweep radius."""
+    sp = inputs.spherocylinder_species(1.0, 0.5)
+    rng = np.random.Generator(np.random.PCG64(42))
+    ax = np.array([0.0, 0.0, 0.5])
+    checked = hits = 0
+    for _ in range(3000):
+        r = _rand_unit(rng) * rng.uniform(0.0, 2.2)
+        qa, qb = random_quat(rng), random_quat(rng)
+        ma, mb = quat_matrix(qa), quat_matrix(qb)
+        dist = segment_distance(-ma @ ax, ma @ ax, r - mb @ ax, r + mb @ ax)
+        if abs(dist - 1.0) < 1e-8:
+            continue
+        want = dist < 1.0
+        assert oracle.overlap_full(sp, r, qa, qb) == want, (r, qa, qb, dist)
+        checked += 1
+        hits += want
+    assert checked > 2900 and 0.2 < hits / checked < 0.8
+
+
+def test_rounded_cube_bounds_and_sampling():
+    """Rounded cubes: cores separated by more than twice the sweep radius on
+    some axis never overlap; overlapping cores always do; a sample point
+    within the sweep radius of both cores proves an overlap."""
+    s = 0.1
+    sp = inputs.rounded_cube_species(1.0, s)
+    v = sp["verts"]
+    rng = np.random.Generator(np.random.PCG64(43))
+    apart = cores = proved = 0
+    for _ in range(600):
+        r = _rand_unit(rng) * rng.uniform(0.5, 2.0)
+        qa, qb = random_quat(rng), random_quat(rng)
+        ma, mb = quat_matrix(qa), quat_matrix(qb)
+        gap = sat_gap_3d(v @ ma.T, v @ mb.T + r)
+        got = oracle.overlap_full(sp, r, qa, qb)
+        if gap > 2 * s + 1e-9:
+            assert not got
+            apart += 1
+        elif gap < -1e-9:
+            assert got
+            cores += 1
+        else:
+            pts = rng.uniform(-1.0, 1.0, size=(4000, 3)) + 0.5 * r
+            da = np.linalg.norm(np.maximum(np.abs(pts @ ma) - 0.5, 0.0), axis=1)
+            db = np.linalg.norm(np.maximum(np.abs((pts - r) @ mb) - 0.5, 0.0), axis=1)
+            if np.any((da < s - 1e-9) & (db < s - 1e-9)):
+                assert got
+                proved += 1
+    assert apart > 50 and cores > 50 and proved > 10
+
+
+def test_sweep_radius_shape_rules():
+    sph = inputs.sphere_species(1.0)
+    assert oracle.shape_info(sph)["R"] == math.nextafter(0.5, math.inf)
+    rc = inputs.rounded_cube_species(1.0, 0.1)
+    assert oracle.shape_info(rc)["R"] == math.nextafter(math.sqrt(0.75) + 0.1, math.inf)
+    with pytest.raises(ValueError):  # a swept polygon is not supported
+        oracle.shape_info(dict(inputs.pentagon_species(), sweep_radius=0.1))
+    with pytest.raises(ValueError):  # fewer than 4 vertices need a sweep radius
+        oracle.shape_info(dict(inputs.spherocylinder_species(), sweep_radius=0.0))
+    with pytest.raises(ValueError):
+        oracle.shape_info(dict(inputs.cube_species(), sweep_radius=-0.1))
+
+
+def test_sweep_pins_detect_a_one_sided_sweep(planted):
+    lib = planted("ORACLE_PLANT_SWEEP_ONE_SIDED")
+    sp = inputs.sphere_species(1.0)
+    rng = np.random.Generator(np.random.PCG64(44))
+    mismatches = 0
+    for _ in range(300):
+        dist = rng.uniform(0.0, 1.3)
+        r = _rand_unit(rng) * dist
+        mismatches += oracle.overlap_full(sp, r, random_quat(rng), random_quat(rng), lib=lib) != (dist < 1.0)
+    assert mismatches > 0

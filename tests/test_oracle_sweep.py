@@ -72,11 +72,14 @@ def _workloads():
         "cubes": inputs.workload_cubes(512, 0.45),
         "trunc_oct": inputs.workload_truncated_octahedra(216, 0.45),
         "dodecahedra": inputs.workload_dodecahedra(216, 0.50),
+        "spheres": inputs.workload_spheres(512, 0.40),
+        "spherocylinders": inputs.workload_spherocylinders(512, 0.15),
+        "rounded_cubes": inputs.workload_rounded_cubes(512, 0.45),
     }
 
 
 @pytest.mark.parametrize("name", ["disks", "pentagons", "pentagons_dense", "cubes", "trunc_oct",
-                                  "dodecahedra"])
+                                  "dodecahedra", "spheres", "spherocylinders", "rounded_cubes"])
 def test_no_overlaps_after_every_sweep(name):
     sp, N, L, pos, orient = _workloads()[name]
     assert oracle.count_overlaps(sp, L, pos, orient) == 0
