@@ -93,7 +93,8 @@ typedef enum { HPMC_PATH_AUTO = 0, HPMC_PATH_GRID = 1, HPMC_PATH_PERSISTENT = 2 
 typedef struct {
     int32_t dim;          /* 2 (disk, polygon) or 3 (polyhedron) */
     int32_t shape;        /* hpmc_shape */
-    int32_t n_verts;      /* polygon: 3..8 (CCW, strictly convex); polyhedron: 4..64 */
+    int32_t n_verts;      /* polygon: 3..8 (CCW, strictly convex); polyhedron: 4..64,
+                             or 1..64 with sweep_radius > 0 */
     const double *verts;  /* host, n_verts x dim row-major; NULL for disks */
     double diameter;      /* disks */
     double d;             /* translation: each component uniform in [-d, d] */
@@ -101,6 +102,12 @@ typedef struct {
                              v uniform in [-a, a]^3, renormalised */
     double p_rot;         /* probability that a move is a rotation (0 for disks) */
     int32_t rounds;       /* colour rounds per sweep; 0 = max(1, round(N / cells)) */
+    double sweep_radius;  /* polyhedra: the particle is every point within this
+                             distance of the vertices' convex hull (a
+                             spheropolyhedron, Sec. 2.3; one vertex gives a
+                             sphere, two a spherocylinder); 0 for the hull
+                             itself and for disks and polygons.  Swept shapes
+                             always walk XenoCollide in binary64. */
 } hpmc_species;
 
 typedef struct {

@@ -54,6 +54,7 @@ class Species(ctypes.Structure):
         ("a", ctypes.c_double),
         ("p_rot", ctypes.c_double),
         ("rounds", ctypes.c_int32),
+        ("sweep_radius", ctypes.c_double),
     ]
 
 

@@ -75,6 +75,9 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
     if (!(s.d >= 0.0) || !(s.a >= 0.0) || !(s.p_rot >= 0.0) || !(s.p_rot <= 1.0))
         return HPMC_ERR_INVALID_ARG;
     if (s.rounds < 0) return HPMC_ERR_INVALID_ARG;
+    if (!(s.sweep_radius >= 0.0) || !std::isfinite(s.sweep_radius)) return HPMC_ERR_INVALID_ARG;
+    if (s.sweep_radius > 0.0 && s.shape != HPMC_POLYHEDRON) return HPMC_ERR_INVALID_ARG;
+    P.sweep = s.sweep_radius;
     if (s.shape == HPMC_DISK) {
         if (s.dim != 2 || !(s.diameter > 0.0) || s.p_rot != 0.0) return HPMC_ERR_INVALID_ARG;
         P.R = s.diameter * 0.5;
@@ -82,7 +85,8 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
         const int want_dim = s.shape == HPMC_POLYGON ? 2 : 3;
         const int maxv = s.shape == HPMC_POLYGON ? kMaxPolyVerts : kMaxPolyhedronVerts;
         if (s.dim != want_dim || s.verts == nullptr) return HPMC_ERR_INVALID_ARG;
-        if (s.n_verts < want_dim + 1 || s.n_verts > maxv) return HPMC_ERR_INVALID_ARG;
+        const int minv = P.sweep > 0.0 ? 1 : want_dim + 1;
+        if (s.n_verts < minv || s.n_verts > maxv) return HPMC_ERR_INVALID_ARG;
         P.nv = s.n_verts;
         double rmax = 0.0;
         for (int k = 0; k < P.nv; ++k) {
@@ -97,7 +101,8 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
             const double r = std::sqrt(r2);
             if (r > rmax) rmax = r;
         }
-        P.R = std::nextafter(rmax, INFINITY);  // every vertex inside the circumsphere
+        // every vertex, and every point within the sweep radius of one, inside
+        P.R = std::nextafter(rmax + P.sweep, INFINITY);
         if (s.shape == HPMC_POLYGON && !fill_polygon_tables(P)) return HPMC_ERR_INVALID_ARG;
     } else {
         return HPMC_ERR_INVALID_ARG;
@@ -107,6 +112,7 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
     const double tol = 1e-12 * dmax;
     P.tol2 = tol * tol;
     if (s.shape == HPMC_POLYHEDRON) fill_mpr32_tables(P, tol);
+    if (P.sweep > 0.0) P.mpr32_ok = 0;  // the binary32 walk has no bound for the swept term
     P.d = s.d;
     P.a = s.a;
     P.p_rot = s.p_rot;

@@ -130,9 +130,17 @@ __device__ __forceinline__ V3 support64(const SpeciesDev& P, const Minkowski64& 
         if (pa > ba) { ba = pa; ka = k; }
     }
     const double bx = P.vx[kb], by = P.vy[kb], bz = P.vz[kb];
-    return V3{(((m[0][0] * bx + m[0][1] * by) + m[0][2] * bz) + mk.t.x) - P.vx[ka],
-              (((m[1][0] * bx + m[1][1] * by) + m[1][2] * bz) + mk.t.y) - P.vy[ka],
-              (((m[2][0] * bx + m[2][1] * by) + m[2][2] * bz) + mk.t.z) - P.vz[ka]};
+    V3 out{(((m[0][0] * bx + m[0][1] * by) + m[0][2] * bz) + mk.t.x) - P.vx[ka],
+           (((m[1][0] * bx + m[1][1] * by) + m[1][2] * bz) + mk.t.y) - P.vy[ka],
+           (((m[2][0] * bx + m[2][1] * by) + m[2][2] * bz) + mk.t.z) - P.vz[ka]};
+    // spheropolyhedra: each particle's ball adds sweep n/|n| to its support,
+    // so the difference gains (sweep + sweep) n/|n| (none for n = 0)
+    const double nn = dot(n, n);
+    if (P.sweep > 0.0 && nn > 0.0) {
+        const double s = (P.sweep + P.sweep) / sqrt(nn);
+        out = V3{out.x + s * n.x, out.y + s * n.y, out.z + s * n.z};
+    }
+    return out;
 }
 
 constexpr int kMprMaxIter = 1024;

@@ -35,6 +35,7 @@ struct alignas(16) SpeciesDev {
     double circ2;    // circumsphere threshold (R + R)^2
     double tol2;     // squared XenoCollide tolerance
     double d, a, p_rot;
+    double sweep;    // sweep radius of a spheropolyhedron, 0 otherwise
     double vx[kMaxPolyhedronVerts], vy[kMaxPolyhedronVerts], vz[kMaxPolyhedronVerts];
     double nx[kMaxPolyVerts], ny[kMaxPolyVerts];      // polygon outward edge normals
     double pmin[kMaxPolyVerts], pmax[kMaxPolyVerts];  // own projections onto them

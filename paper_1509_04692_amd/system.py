@@ -11,7 +11,8 @@ block work queue, per wave64 in LDS; the default), or the paper's two
 comparison variants "register" and "global" (grid path only).
 
 ``species`` is a dict (or one per replica) with keys dim, shape ("disk",
-"polygon", "polyhedron"), verts (n x dim), diameter, d, a, p_rot and rounds,
+"polygon", "polyhedron"), verts (n x dim), diameter, d, a, p_rot, rounds and
+(polyhedra) sweep_radius,
 as produced by ``paper_1509_04692_amd.inputs``.
 """
 import ctypes
@@ -93,6 +94,7 @@ class System:
             s.a = float(sp.get("a", 0.0))
             s.p_rot = float(sp.get("p_rot", 0.0))
             s.rounds = int(sp.get("rounds", 0))
+            s.sweep_radius = float(sp.get("sweep_radius", 0.0))
         self._sp_arr = sp_arr
         self._N_arr = (ctypes.c_int32 * n_rep)(*self.N)
         self._L_arr = (ctypes.c_double * n_rep)(*self.L)

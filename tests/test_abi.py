@@ -58,6 +58,7 @@ def _args(species_list, Ns, Ls, precision=0, path=0, flags=0):
             s.verts = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         s.diameter = sp.get("diameter", 0.0)
         s.d, s.a, s.p_rot, s.rounds = sp["d"], sp["a"], sp["p_rot"], sp.get("rounds", 0)
+        s.sweep_radius = sp.get("sweep_radius", 0.0)
     a = _lib.InitArgs()
     a.n_replicas = n
     a.species = sp_arr
@@ -126,3 +127,13 @@ def test_queue_variant_flags(lib):
     for q in ("register", "global"):
         assert ws_bytes(lib, *two, path=2, flags=_lib.QUEUE_FLAGS[q])[0] == -7  # grid path only
         assert ws_bytes(lib, *two, path=0, flags=_lib.QUEUE_FLAGS[q])[0] == 0   # auto: grid
+
+
+def test_sweep_radius_rules(lib):
+    sph = inputs.sphere_species(1.0)
+    assert ws_bytes(lib, [sph], [512], [8.75])[0] == 0           # one vertex, swept
+    assert ws_bytes(lib, [dict(sph, sweep_radius=0.0)], [512], [8.75])[0] == -1
+    assert ws_bytes(lib, [dict(sph, sweep_radius=-0.5)], [512], [8.75])[0] == -1
+    pent = dict(inputs.pentagon_species(), sweep_radius=0.1)
+    assert ws_bytes(lib, [pent], [1024], [32.0])[0] == -1          # polyhedra only
+    assert ws_bytes(lib, [inputs.spherocylinder_species()], [512], [16.5])[0] == 0

@@ -114,6 +114,25 @@ def test_polyhedra(shape, path, precision):
         assert st["pair_fp64"] == st["pair_tests"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["spheres", "spherocylinders", "rounded_cubes"])
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_spheropolyhedra(shape, path, precision):
+    """Swept shapes (XenoCollide with the sweep term, binary64 walk in both
+    precisions) against the oracle."""
+    if shape == "spheres":
+        sp, N, L, pos, orient = inputs.workload_spheres(512, 0.40)
+    elif shape == "spherocylinders":
+        sp, N, L, pos, orient = inputs.workload_spherocylinders(512, 0.15)
+    else:
+        sp, N, L, pos, orient = inputs.workload_rounded_cubes(512, 0.45)
+    system, gpu, ref = run_pair(sp, L, pos, orient, 10, seed=19, precision=precision, path=path)
+    assert_parity(gpu, ref, sp)
+    assert system.count_overlaps()[0] == 0
+    st = system.stats()[0]
+    assert st["pair_fp64"] == st["pair_tests"] > 0
+
+
 def test_autotuned_mixed_polyhedra_equal_the_oracle():
     """The autotuner may move mixed-precision polyhedra to the binary64 walk;
     either way the trajectory is the oracle's."""
