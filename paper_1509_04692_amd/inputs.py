@@ -205,26 +205,27 @@ def fcc_lattice(sp, N, L, seed=INIT_SEED):
 
     Two aligned copies of a centrally symmetric convex body K = {x : n_f.x <= h}
     are disjoint exactly when their displacement t has max_f n_f.t > 2 h, so
-    every lattice vector shorter than the circumsphere diameter is checked
-    against the face normals; raises if one fails.
+    with face normals given every lattice vector shorter than the
+    circumsphere diameter is checked against them; without, no lattice vector
+    may be that short.  Raises if one fails.
     """
-    if sp["dim"] != 3 or "face_normals" not in sp:
-        raise ValueError("fcc_lattice needs a 3D species with face normals")
+    if sp["dim"] != 3:
+        raise ValueError("fcc_lattice needs a 3D species")
     m = 1
     while 4 * m ** 3 < N:
         m += 1
     a = L / m
     basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
-    R = float(np.linalg.norm(sp["verts"], axis=1).max())
-    normals, h = sp["face_normals"], sp["inradius"]
+    R = float(np.linalg.norm(sp["verts"], axis=1).max()) + sp.get("sweep_radius", 0.0)
+    normals, h = sp.get("face_normals"), sp.get("inradius")
     rng3 = range(-2, 3)
     for i, j, k in ((i, j, k) for i in rng3 for j in rng3 for k in rng3):
         for b in basis:
             t = (np.array([i, j, k], dtype=np.float64) + b) * a
             dist = np.linalg.norm(t)
-            if dist == 0.0 or dist >= 2.0 * R:
+            if dist == 0.0 or dist > 2.0 * R * (1 + 1e-9):
                 continue
-            if (normals @ t).max() <= 2.0 * h * (1 + 1e-9):
+            if normals is None or (normals @ t).max() <= 2.0 * h * (1 + 1e-9):
                 raise ValueError(f"fcc spacing {a:.4f} too small for the shape")
     cells = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"),
                      axis=0).reshape(3, -1, order="F").T
@@ -304,7 +305,7 @@ def initial_state(sp, N, phi, seed=INIT_SEED):
             pos, orient = disk_triangular_lattice(sp, N, L, seed)
         elif sp["shape"] == "polygon" and len(sp["verts"]) == 5:
             pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
-        elif "face_normals" in sp:
+        elif sp["shape"] == "polyhedron":
             pos, orient = fcc_lattice(sp, N, L, seed)
         else:
             raise

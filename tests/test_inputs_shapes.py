@@ -89,3 +89,20 @@ def test_swept_shape_volumes_by_sampling(name):
         dist = np.linalg.norm(np.maximum(np.abs(p) - 0.5, 0.0), axis=1)
     vol = np.mean(dist <= s) * np.prod(2 * half)
     assert abs(vol / sp["volume"] - 1) < 5e-3
+
+
+def test_fcc_spheres_at_the_table_1_density():
+    """Hard spheres at packing fraction 0.60 (the paper's solid state point,
+    Sec. 4) start on an FCC lattice without overlaps; nearest neighbours sit
+    at (4 v0 / phi)^(1/3) / sqrt 2 = 1.073 diameters."""
+    sp = inputs.sphere_species(1.0)
+    N = 4 * 6 ** 3
+    L = inputs.box_length(N, sp["volume"], 0.60, 3)
+    pos, orient = inputs.fcc_lattice(sp, N, L)
+    d = pos[:, :, None] - pos[:, None, :]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d ** 2).sum(axis=0))[~np.eye(N, dtype=bool)]
+    assert abs(r.min() - (4 * sp["volume"] / 0.60) ** (1 / 3) / math.sqrt(2)) < 1e-9
+    assert oracle.count_overlaps(sp, L, pos, orient) == 0
+    with pytest.raises(ValueError):
+        inputs.fcc_lattice(sp, N, L * 0.9)  # nearest neighbours closer than sigma
