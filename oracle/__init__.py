@@ -24,6 +24,7 @@ from .oracle import (  # noqa: F401
     load_counting,
     overlap_full,
     pair_histogram,
+    scale_counts,
     pair_overlaps,
     philox4x32_10,
     reset_events,

@@ -941,6 +941,41 @@ int or_pair_histogram(int32_t dim, int32_t N, double L, const double *pos,
     return OR_OK;
 }
 
+int or_scale_counts(const or_species *sp, int32_t N, double L, const double *pos,
+                    const double *orient, const double *s, int32_t n_s, int64_t *out)
+{
+    shape_t sh;
+    int rc = setup_shape(sp, &sh);
+    if (rc) return rc;
+    if (N < 0 || !(L > 0.0) || n_s < 1 || !s || !out || !pos)
+        return OR_ERR_INVALID_ARG;
+    for (int b = 0; b < n_s; ++b)
+        if (!(s[b] >= 0.0 && s[b] < 1.0) || (b > 0 && !(s[b - 1] < s[b])))
+            return OR_ERR_INVALID_ARG;
+    grid_t g;
+    memset(&g, 0, sizeof(g));
+    g.L = L;
+    g.inv_L = 1.0 / L;
+    for (int b = 0; b < n_s; ++b)
+        out[b] = 0;
+    for (int i = 0; i < N; ++i) {
+        double qi[4] = { 1, 0, 0, 0 };
+        load_orient(&sh, N, orient, i, qi);
+        for (int k = i + 1; k < N; ++k) {
+            double r[3] = { 0.0, 0.0, 0.0 }, qk[4] = { 1, 0, 0, 0 };
+            for (int a = 0; a < sh.dim; ++a)
+                r[a] = min_image(&g, pos[a * N + k] - pos[a * N + i]);
+            load_orient(&sh, N, orient, k, qk);
+            for (int b = 0; b < n_s; ++b) {
+                double f = 1.0 - s[b];
+                double rs[3] = { r[0] * f, r[1] * f, r[2] * f };
+                out[b] += pair_overlaps(&sh, rs, qi, qk);
+            }
+        }
+    }
+    return OR_OK;
+}
+
 int64_t or_count_overlaps(const or_species *sp, int32_t N, double L, const double *pos,
                           const double *orient)
 {

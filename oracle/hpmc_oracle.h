@@ -93,6 +93,15 @@ int64_t or_count_overlaps(const or_species *sp, int32_t N, double L,
 int or_pair_histogram(int32_t dim, int32_t N, double L, const double *pos,
                       const double *edges2, int32_t n_bins, int64_t *out);
 
+/* Compressions behind the volume-perturbation pressure of Sec. 4: out[b] =
+ * number of unordered pairs i < k that overlap (circumsphere test, then the
+ * full test) once their minimum-image separation r is replaced by r (1 - s[b])
+ * with orientations unchanged, i.e. after the box is shrunk by the scale
+ * factor s[b].  s: n_s strictly ascending values in [0, 1).  Every pair is
+ * visited (no cell list). */
+int or_scale_counts(const or_species *sp, int32_t N, double L, const double *pos,
+                    const double *orient, const double *s, int32_t n_s, int64_t *out);
+
 /* n_sweeps checkerboard sweeps of one system, sweep counter t0, t0+1, ...
  * Updates pos / orient in place and ADDS to stats[OR_NSTATS]. */
 int or_sweep(const or_species *sp, int32_t N, double L, double *pos,

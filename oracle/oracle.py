@@ -81,6 +81,9 @@ def _declare(lib):
     lib.or_pair_histogram.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P_D, _P_D,
                                       ctypes.c_int32, _P_I64]
     lib.or_pair_histogram.restype = ctypes.c_int
+    lib.or_scale_counts.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D, _P_D,
+                                    ctypes.c_int32, _P_I64]
+    lib.or_scale_counts.restype = ctypes.c_int
     lib.or_count_overlaps.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D]
     lib.or_count_overlaps.restype = ctypes.c_int64
     lib.or_sweep.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D,
@@ -253,6 +256,19 @@ def pair_histogram(L, pos, edges2, lib=None):
     _check((lib or load()).or_pair_histogram(pos.shape[0], pos.shape[1], float(L), _dptr(pos),
                                              _dptr(edges2), len(out),
                                              out.ctypes.data_as(_P_I64)), "pair_histogram")
+    return out
+
+
+def scale_counts(sp, L, pos, orient, scales, lib=None):
+    """Unordered pairs overlapping once their separation is scaled by
+    1 - scales[b], for each b (volume-perturbation pressure, Sec. 4)."""
+    s, _keep = _species(sp)
+    N, pos, orient = _state(sp, pos, orient)
+    sc = np.ascontiguousarray(scales, dtype=np.float64)
+    out = np.zeros(len(sc), dtype=np.int64)
+    _check((lib or load()).or_scale_counts(ctypes.byref(s), N, float(L), _dptr(pos), _dptr(orient),
+                                           _dptr(sc), len(sc), out.ctypes.data_as(_P_I64)),
+           "scale_counts")
     return out
 
 

@@ -103,9 +103,17 @@ def cube_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
 
 
 def truncated_octahedron_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
+    """Truncated octahedra; the face normals and offsets (6 squares at
+    sqrt(2) edge, 8 hexagons at 3/sqrt(6) edge) serve the lattice starts only."""
+    ax = np.vstack([np.eye(3), -np.eye(3)])
+    diag = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)],
+                    dtype=np.float64) / math.sqrt(3.0)
     return {"dim": 3, "shape": "polyhedron", "verts": truncated_octahedron_vertices(edge),
             "d": float(d), "a": float(a), "p_rot": float(p_rot), "rounds": 0,
-            "volume": TRUNC_OCT_VOLUME_PER_EDGE3 * edge ** 3}
+            "volume": TRUNC_OCT_VOLUME_PER_EDGE3 * edge ** 3,
+            "face_normals": np.vstack([ax, diag]),
+            "face_offsets": np.concatenate([np.full(6, math.sqrt(2.0) * edge),
+                                            np.full(8, 3.0 / math.sqrt(6.0) * edge)])}
 
 
 def dodecahedron_species(edge=1.0, d=0.08, a=0.1, p_rot=0.5):
@@ -199,25 +207,20 @@ def simple_lattice(sp, N, L, seed=INIT_SEED):
     return pos, identity_orientations(sp, N)
 
 
-def fcc_lattice(sp, N, L, seed=INIT_SEED):
-    """Aligned polyhedra on a face-centred cubic lattice of 4 m^3 >= N sites
-    (a seeded random subset if larger).
+def _check_aligned_lattice(sp, basis, a):
+    """Raise unless aligned copies of the shape at every lattice vector of a
+    cubic lattice (constant a, sites basis * a) are disjoint.
 
-    Two aligned copies of a centrally symmetric convex body K = {x : n_f.x <= h}
-    are disjoint exactly when their displacement t has max_f n_f.t > 2 h, so
-    with face normals given every lattice vector shorter than the
-    circumsphere diameter is checked against them; without, no lattice vector
-    may be that short.  Raises if one fails.
+    Two aligned copies of a centrally symmetric convex body
+    K = {x : n_f.x <= h_f} are disjoint exactly when their displacement t has
+    max_f n_f.t / h_f > 2, so with face normals given every lattice vector
+    shorter than the circumsphere diameter is checked against them; without,
+    no lattice vector may be that short.
     """
-    if sp["dim"] != 3:
-        raise ValueError("fcc_lattice needs a 3D species")
-    m = 1
-    while 4 * m ** 3 < N:
-        m += 1
-    a = L / m
-    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
     R = float(np.linalg.norm(sp["verts"], axis=1).max()) + sp.get("sweep_radius", 0.0)
-    normals, h = sp.get("face_normals"), sp.get("inradius")
+    normals = sp.get("face_normals")
+    if normals is not None:
+        h = np.asarray(sp.get("face_offsets", np.full(len(normals), sp.get("inradius", 0.0))))
     rng3 = range(-2, 3)
     for i, j, k in ((i, j, k) for i in rng3 for j in rng3 for k in rng3):
         for b in basis:
@@ -225,8 +228,15 @@ def fcc_lattice(sp, N, L, seed=INIT_SEED):
             dist = np.linalg.norm(t)
             if dist == 0.0 or dist > 2.0 * R * (1 + 1e-9):
                 continue
-            if normals is None or (normals @ t).max() <= 2.0 * h * (1 + 1e-9):
-                raise ValueError(f"fcc spacing {a:.4f} too small for the shape")
+            if normals is None or ((normals @ t) / h).max() <= 2.0 * (1 + 1e-9):
+                raise ValueError(f"lattice constant {a:.4f} too small for the shape")
+
+
+def _cubic_lattice_sites(basis, N, L, seed):
+    m = 1
+    while len(basis) * m ** 3 < N:
+        m += 1
+    a = L / m
     cells = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"),
                      axis=0).reshape(3, -1, order="F").T
     sites = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3).T.astype(np.float64)
@@ -234,8 +244,32 @@ def fcc_lattice(sp, N, L, seed=INIT_SEED):
         rng = np.random.Generator(np.random.PCG64(seed))
         keep = np.sort(rng.choice(sites.shape[1], size=N, replace=False))
         sites = sites[:, keep]
-    pos = np.ascontiguousarray((sites + 0.25) * a)
-    return pos, identity_orientations(sp, N)
+    return sites, a
+
+
+_FCC = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+_BCC = np.array([[0, 0, 0], [0.5, 0.5, 0.5]])
+
+
+def fcc_lattice(sp, N, L, seed=INIT_SEED):
+    """Aligned particles on a face-centred cubic lattice of 4 m^3 >= N sites
+    (a seeded random subset if larger); raises if aligned copies at the
+    lattice vectors would overlap."""
+    if sp["dim"] != 3:
+        raise ValueError("fcc_lattice needs a 3D species")
+    sites, a = _cubic_lattice_sites(_FCC, N, L, seed)
+    _check_aligned_lattice(sp, _FCC, a)
+    return np.ascontiguousarray((sites + 0.25) * a), identity_orientations(sp, N)
+
+
+def bcc_lattice(sp, N, L, seed=INIT_SEED):
+    """Aligned particles on a body-centred cubic lattice of 2 m^3 >= N sites
+    (truncated octahedra tile space on it), checked like fcc_lattice."""
+    if sp["dim"] != 3:
+        raise ValueError("bcc_lattice needs a 3D species")
+    sites, a = _cubic_lattice_sites(_BCC, N, L, seed)
+    _check_aligned_lattice(sp, _BCC, a)
+    return np.ascontiguousarray((sites + 0.25) * a), identity_orientations(sp, N)
 
 
 # Up / down interlocked rows for regular pentagons: alternating columns hold
@@ -306,7 +340,10 @@ def initial_state(sp, N, phi, seed=INIT_SEED):
         elif sp["shape"] == "polygon" and len(sp["verts"]) == 5:
             pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
         elif sp["shape"] == "polyhedron":
-            pos, orient = fcc_lattice(sp, N, L, seed)
+            try:
+                pos, orient = fcc_lattice(sp, N, L, seed)
+            except ValueError:
+                pos, orient = bcc_lattice(sp, N, L, seed)
         else:
             raise
     return L, pos, orient
@@ -345,6 +382,15 @@ def workload_dodecahedra(N=4096, phi=0.50):
     at packing fraction 0.5, NVT); translation d=0.08, rotation a=0.1."""
     sp = dodecahedron_species(1.0, d=0.08, a=0.1, p_rot=0.5)
     L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_truncated_octahedra_solid(N=16000, phi=0.70):
+    """The paper's truncated-octahedron validation state (Sec. 4, Table 1):
+    BCC solid at packing fraction 0.7, aligned; small moves for the solid."""
+    sp = truncated_octahedron_species(1.0, d=0.04, a=0.04, p_rot=0.5)
+    L = box_length(N, sp["volume"], phi, 3)
+    pos, orient = bcc_lattice(sp, N, L)
     return sp, N, L, pos, orient
 
 

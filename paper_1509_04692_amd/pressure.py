@@ -7,8 +7,14 @@ contact.  For hard disks of diameter sigma the virial theorem gives
     beta P / rho = 1 + (pi / 2) rho sigma^2 g(sigma+),   P* = beta P sigma^2,
 
 and for hard spheres beta P / rho = 1 + (2 pi / 3) rho sigma^3 g(sigma+).
-This is host-side arithmetic on the sampled counts; the counts come from the
-library's histogram kernel.
+
+For particles with shape the paper uses volume perturbations (Sec. 4): shrink
+the box (every separation) by a factor 1 - s; C(s), the number of pairs that
+then overlap, grows linearly at small s, and since the volume shrinks by
+about dim * s * V, beta P / rho = 1 + C'(0) / (dim N).  The counts come from
+``System.scale_counts``; C'(0) is the intercept of a polynomial fit of
+C(s) / s.  This is host-side arithmetic on the sampled counts; the counts
+come from the library's kernels.
 """
 import math
 
@@ -56,3 +62,23 @@ def sphere_pressure(N, L, sigma, g_contact):
     """beta P sigma^3 of N hard spheres in an L^3 box."""
     rho_s3 = N * sigma ** 3 / L ** 3
     return rho_s3 * (1.0 + 2.0 * math.pi / 3.0 * rho_s3 * g_contact)
+
+
+def scale_slope(scales, mean_counts, degree=2, n_samples=None):
+    """C'(0) from mean overlap counts C(s) at scale factors s > 0: intercept
+    of a least-squares polynomial in s through C(s) / s (weights from
+    Poisson counting errors when n_samples is given)."""
+    s = np.asarray(scales, dtype=np.float64)
+    c = np.asarray(mean_counts, dtype=np.float64)
+    if np.any(s <= 0.0):
+        raise ValueError("scale factors must be positive")
+    w = None
+    if n_samples:
+        w = s * np.sqrt(np.maximum(c * n_samples, 1.0)) / np.maximum(c, 1e-300)
+    coef = np.polynomial.polynomial.polyfit(s, c / s, degree, w=w)
+    return float(coef[0])
+
+
+def scale_pressure(N, dim, scales, mean_counts, degree=2, n_samples=None):
+    """beta P / rho of N hard particles from volume-perturbation counts."""
+    return 1.0 + scale_slope(scales, mean_counts, degree, n_samples) / (dim * N)

@@ -106,3 +106,19 @@ def test_fcc_spheres_at_the_table_1_density():
     assert oracle.count_overlaps(sp, L, pos, orient) == 0
     with pytest.raises(ValueError):
         inputs.fcc_lattice(sp, N, L * 0.9)  # nearest neighbours closer than sigma
+
+
+def test_truncated_octahedron_faces_and_bcc_start():
+    """Face table of the truncated octahedron (6 squares at sqrt 2, 8 hexagons
+    at 3/sqrt 6 per unit edge, each plane holding 4 or 6 vertices) and the
+    paper's BCC solid at packing fraction 0.7 (Sec. 4), overlap-free by the
+    oracle; at packing fraction 1 the BCC tiling touches and is refused."""
+    sp = inputs.truncated_octahedron_species(1.0)
+    p = sp["verts"] @ sp["face_normals"].T
+    assert np.allclose(p.max(axis=0), sp["face_offsets"], rtol=1e-14)
+    on = np.sum(np.isclose(p, sp["face_offsets"], rtol=1e-12), axis=0)
+    assert list(on) == [4] * 6 + [6] * 8
+    sp, N, L, pos, orient = inputs.workload_truncated_octahedra_solid(250, 0.70)
+    assert oracle.count_overlaps(sp, L, pos, orient) == 0
+    with pytest.raises(ValueError):
+        inputs.bcc_lattice(sp, N, inputs.box_length(N, sp["volume"], 1.0, 3))

@@ -444,3 +444,56 @@ def test_sweep_pins_detect_a_one_sided_sweep(planted):
         r = _rand_unit(rng) * dist
         mismatches += oracle.overlap_full(sp, r, random_quat(rng), random_quat(rng), lib=lib) != (dist < 1.0)
     assert mismatches > 0
+
+
+# -- volume-perturbation counts (pairs overlapping after shrinking by 1 - s) ---
+
+def _random_state(dim, N, L, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.ascontiguousarray(rng.uniform(0.0, L, size=(dim, N)))
+
+
+def test_scale_counts_of_spheres_closed_form():
+    """One-vertex spheropolyhedra (unit spheres): pairs with
+    |r| (1 - s) < 1 by numpy brute force over the minimum image."""
+    sp = inputs.sphere_species(1.0)
+    N, L = 300, 9.0
+    pos = _random_state(3, N, L, 61)
+    ori = inputs.identity_orientations(sp, N)
+    s = np.array([0.0, 0.01, 0.05, 0.1, 0.3])
+    d = pos[:, None, :] - pos[:, :, None]
+    d -= L * np.rint(d / L)
+    r = np.sqrt((d ** 2).sum(axis=0))[np.triu_indices(N, 1)]
+    for f in 1.0 - s:
+        assert np.min(np.abs(r * f - 1.0)) > 1e-9  # no ties in this sample
+    want = [int(np.sum(r * (1.0 - x) < 1.0)) for x in s]
+    assert list(oracle.scale_counts(sp, L, pos, ori, s)) == want
+    assert want[0] < want[-1]
+
+
+def test_scale_counts_of_aligned_cubes_closed_form():
+    """Aligned unit cubes overlap exactly when every |r_a| (1 - s) < 1."""
+    sp = inputs.cube_species(1.0)
+    N, L = 250, 8.0
+    pos = _random_state(3, N, L, 62)
+    ori = inputs.identity_orientations(sp, N)
+    s = np.array([0.0, 0.02, 0.1, 0.25])
+    d = pos[:, None, :] - pos[:, :, None]
+    d -= L * np.rint(d / L)
+    iu = np.triu_indices(N, 1)
+    a = np.abs(d[:, iu[0], iu[1]])
+    want = []
+    for x in s:
+        m = np.max(a * (1.0 - x), axis=0)
+        assert np.min(np.abs(m - 1.0)) > 1e-9
+        want.append(int(np.sum(m < 1.0)))
+    assert list(oracle.scale_counts(sp, L, pos, ori, s)) == want
+
+
+def test_scale_counts_reject_bad_scales():
+    sp = inputs.sphere_species(1.0)
+    pos = _random_state(3, 10, 9.0, 63)
+    ori = inputs.identity_orientations(sp, 10)
+    for bad in ([0.1, 0.05], [1.0], [-0.01]):
+        with pytest.raises(ValueError):
+            oracle.scale_counts(sp, 9.0, pos, ori, bad)

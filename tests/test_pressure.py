@@ -77,3 +77,29 @@ def test_disk_pressure_virial_limits():
     # the disk state point of Table 1: phi = 0.698, P* = 9.1707 <-> g(sigma+) = 6.676
     L698 = math.sqrt(65536 * math.pi / 4 / 0.698)
     assert abs(pressure.disk_pressure(65536, L698, 1.0, 6.676) - 9.1707) < 1e-3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_scale_route_recovers_the_contact_slope(dim):
+    """Counts C(s) of pairs closer than sigma / (1 - s) for a prescribed
+    g(r) = g0 + g1 (r - sigma), integrated exactly over the shells, give
+    C'(0) = (N (N - 1) / 2V) S_dim sigma^dim g0 (S = 2 pi, 4 pi), hence
+    beta P / rho = 1 + C'(0) / (dim N): the virial form of the contact route."""
+    N, L, sigma, g0, g1 = 4096, 60.0 if dim == 2 else 20.0, 1.0, 6.0, -9.0
+    V = L ** dim
+    pref = 0.5 * N * (N - 1) / V
+    s = 0.001 * np.arange(1, 21)
+    r1 = sigma / (1.0 - s)
+    if dim == 2:  # int 2 pi r g(r) dr
+        F = lambda r: 2 * math.pi * ((g0 - g1 * sigma) * r ** 2 / 2 + g1 * r ** 3 / 3)
+        slope = pref * 2 * math.pi * sigma ** 2 * g0
+    else:         # int 4 pi r^2 g(r) dr
+        F = lambda r: 4 * math.pi * ((g0 - g1 * sigma) * r ** 3 / 3 + g1 * r ** 4 / 4)
+        slope = pref * 4 * math.pi * sigma ** 3 * g0
+    counts = pref * (F(r1) - F(sigma))
+    got = pressure.scale_slope(s, counts, degree=3)
+    assert abs(got / slope - 1) < 1e-6
+    rho = N / V
+    contact = (pressure.disk_pressure(N, L, sigma, g0 * (N - 1) / N) if dim == 2
+               else pressure.sphere_pressure(N, L, sigma, g0 * (N - 1) / N)) / rho
+    assert abs(pressure.scale_pressure(N, dim, s, counts, degree=3) - contact) < 1e-6
