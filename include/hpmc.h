@@ -175,6 +175,18 @@ int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
  * HPMC_ERR_INVALID_ARG for a configuration this state cannot use. */
 int hpmc_set_config(hpmc_state *st, int32_t config);
 
+/* Volume-perturbation counts of one replica, the sampling behind the
+ * pressure of particles with shape (Sec. 4): out[b] = number of unordered
+ * pairs i < k that overlap (circumsphere test, then the full binary64 test)
+ * once their minimum-image separation r is replaced by r (1 - scales[b]) --
+ * the box shrunk by that factor -- with orientations unchanged.  scales:
+ * host, n_scales (1..64) strictly ascending values in [0, 1); out: host,
+ * n_scales counts.  HPMC_ERR_UNSUPPORTED when 2R / (1 - scales[n_scales - 1])
+ * exceeds two cell widths (or one, with fewer than 5 cells per side).
+ * Synchronising; the state is unchanged. */
+int hpmc_scale_counts(hpmc_state *st, int32_t replica, const double *scales, int32_t n_scales,
+                      uint64_t *out);
+
 /* Histogram of pair separations of one replica, the sampling behind the
  * pressure check of Sec. 4 (the contact value of g(r) for disks, Table 1):
  * out[b] = number of unordered pairs i < k with

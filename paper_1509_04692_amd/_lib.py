@@ -27,7 +27,7 @@ STAT_FIELDS = ("attempted", "attempted_rot", "cell_reject", "overlap_reject", "a
 
 # Every symbol include/hpmc.h declares.
 EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune", "hpmc_set_config",
-           "hpmc_count_overlaps", "hpmc_pair_histogram", "hpmc_get_stats", "hpmc_reset_stats",
+           "hpmc_count_overlaps", "hpmc_pair_histogram", "hpmc_scale_counts", "hpmc_get_stats", "hpmc_reset_stats",
            "hpmc_sync_to_canonical", "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info",
            "hpmc_uses_graph", "hpmc_last_hip_error", "hpmc_destroy", "hpmc_strerror")
 FLAG_NO_GRAPH = 1
@@ -101,6 +101,8 @@ def load(path=None):
     lib.hpmc_count_overlaps.argtypes = [st, ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_pair_histogram.argtypes = [st, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.hpmc_scale_counts.argtypes = [st, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_get_stats.argtypes = [st, ctypes.POINTER(Stats)]
     lib.hpmc_reset_stats.argtypes = [st]
     lib.hpmc_sync_to_canonical.argtypes = [st]

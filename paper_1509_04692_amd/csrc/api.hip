@@ -693,6 +693,39 @@ int hpmc_pair_histogram(hpmc_state* st, int32_t replica, const double* edges2, i
     return rc;
 }
 
+int hpmc_scale_counts(hpmc_state* st, int32_t replica, const double* scales, int32_t n_scales,
+                      uint64_t* out) {
+    if (st == nullptr || scales == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
+    if (replica < 0 || replica >= st->n_replicas || n_scales < 1 || n_scales > kMaxHistBins)
+        return HPMC_ERR_INVALID_ARG;
+    for (int b = 0; b < n_scales; ++b)
+        if (!(scales[b] >= 0.0 && scales[b] < 1.0) || (b > 0 && !(scales[b - 1] < scales[b])))
+            return HPMC_ERR_INVALID_ARG;
+    // a pair can overlap at the largest compression only if |r| < 2R / f_min;
+    // such pairs lie within `reach` cells of each other
+    const ReplicaHost& rh = st->rep[replica];
+    const double w = st->sys[replica].w, f_min = 1.0 - scales[n_scales - 1];
+    const double circ2 = st->spc[replica].circ2, guard = 1.0 - 0x1p-30;
+    int reach = 0;
+    if (circ2 <= w * w * f_min * f_min * guard)
+        reach = 1;
+    else if (circ2 <= 4.0 * w * w * f_min * f_min * guard && rh.n >= 5)
+        reach = 2;
+    else
+        return HPMC_ERR_UNSUPPORTED;
+    int rc = check_hip(st, hipMemcpyAsync(st->ws.hist_edges, scales, sizeof(double) * n_scales,
+                                          hipMemcpyHostToDevice, st->stream));
+    if (!rc) rc = check_hip(st, build_cells_one(st->ws, rh, replica, st->pos, 0, st->stream));
+    if (!rc)
+        rc = check_hip(st, scale_counts(st->ws, rh, replica, st->pos, st->orient, n_scales, reach,
+                                        st->stream));
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(out, st->ws.hist_out, sizeof(uint64_t) * n_scales,
+                                          hipMemcpyDeviceToHost, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    return rc;
+}
+
 int hpmc_get_stats(hpmc_state* st, hpmc_stats* out) {
     if (st == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
     std::vector<unsigned long long> raw((size_t)kStatsPerReplica * st->n_replicas);

@@ -545,6 +545,82 @@ __global__ void __launch_bounds__(256) k_count(const SysDev* __restrict__ sys,
     if (__lane_id() == 0 && s) atomicAdd(out + r, (unsigned long long)s);
 }
 
+// Volume-perturbation counts: out[b] += number of pairs i < k that overlap
+// (binary64 circumsphere test, then the full test) once their minimum-image
+// separation r is scaled by 1 - scales[b], orientations unchanged.  The
+// unshifted cell list is searched `reach` cells around each particle (the
+// host checks that 2R / (1 - scales[n - 1]) stays within that reach).  A pair
+// whose separation fails the circumsphere test at the largest scale factor
+// fails it at every smaller one, so it is skipped whole.
+template <int KIND>
+__global__ void __launch_bounds__(256) k_scale_count(const SysDev* __restrict__ sys,
+                                                     const SpeciesDev* __restrict__ spc, int r,
+                                                     const double* __restrict__ pos_base,
+                                                     const double* __restrict__ ori_base,
+                                                     const uint32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ members,
+                                                     const uint32_t* __restrict__ cell_of,
+                                                     const double* __restrict__ scales, int n_s,
+                                                     int reach, unsigned long long* __restrict__ out) {
+    constexpr int D = Traits<KIND>::dim;
+    __shared__ uint32_t hist[kMaxHistBins];
+    const SysDev S = sys[r];
+    const SpeciesDev& P = spc[S.species];
+    const double* pos = pos_base + S.pos_off;
+    const double* ori = ori_base + S.orient_off;
+    start += S.cell_off;
+    members += S.slot_off;
+    cell_of += S.slot_off;
+    const int N = S.N, n = S.n;
+    for (int b = threadIdx.x; b < n_s; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    Counters dummy = {};
+    if (i < N) {
+        const uint32_t c = cell_of[i];
+        const int cc[3] = {(int)(c % (uint32_t)n), (int)((c / (uint32_t)n) % (uint32_t)n),
+                           (int)(c / ((uint32_t)n * (uint32_t)n))};
+        double xi[3] = {0.0, 0.0, 0.0}, qi[4];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xi[a] = pos[a * N + i];
+        load_orient<KIND>(ori, N, (uint32_t)i, qi);
+        const double f_min = 1.0 - scales[n_s - 1];
+        const int zlo = D == 3 ? -reach : 0, zhi = D == 3 ? reach : 0;
+        for (int oz = zlo; oz <= zhi; ++oz)
+            for (int oy = -reach; oy <= reach; ++oy)
+                for (int ox = -reach; ox <= reach; ++ox) {
+                    const int x = (cc[0] + ox + n) % n, y = (cc[1] + oy + n) % n,
+                              z = D == 3 ? (cc[2] + oz + n) % n : 0;
+                    const uint32_t cn = (uint32_t)(x + n * (y + n * z));
+                    for (uint32_t p = start[cn]; p < start[cn + 1]; ++p) {
+                        const uint32_t k = members[p];
+                        if (k <= (uint32_t)i) continue;
+                        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int a = 0; a < D; ++a) rr[a] = min_image(pos[a * N + k] - xi[a], S.L, S.inv_L);
+                        double m2 = (rr[0] * f_min) * (rr[0] * f_min) + (rr[1] * f_min) * (rr[1] * f_min);
+                        if constexpr (D == 3) m2 = m2 + (rr[2] * f_min) * (rr[2] * f_min);
+                        if (!(m2 < P.circ2)) continue;
+                        double qk[4];
+                        load_orient<KIND>(ori, N, k, qk);
+                        for (int b = 0; b < n_s; ++b) {
+                            const double f = 1.0 - scales[b];
+                            double rs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                            for (int a = 0; a < D; ++a) rs[a] = rr[a] * f;
+                            double s2 = rs[0] * rs[0] + rs[1] * rs[1];
+                            if constexpr (D == 3) s2 = s2 + rs[2] * rs[2];
+                            if (s2 < P.circ2 && full_test<KIND, 0, 0>(P, rs, qi, qk, dummy))
+                                atomicAdd(hist + b, 1u);
+                        }
+                    }
+                }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_s; b += blockDim.x)
+        if (hist[b]) atomicAdd(out + b, (unsigned long long)hist[b]);
+}
+
 // Histogram of pair separations (pairs i < k with edges2[b] <= r^2 <
 // edges2[b + 1]) over the unshifted cell list; cells within `reach` of the
 // particle's cell are searched (edges2[n_bins] < (reach * w)^2 keeps the
@@ -996,6 +1072,27 @@ hipError_t pair_histogram(const Workspace& ws, const ReplicaHost& rh, int r, con
         k_pair_hist<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, ws.start, ws.members,
                                                                ws.cell_of, ws.hist_edges, n_bins,
                                                                reach, ws.hist_out);
+    return hipGetLastError();
+}
+
+hipError_t scale_counts(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                        const double* orient, int n_s, int reach, hipStream_t stream) {
+    const int N = rh.N;
+    hipError_t e = fill_u64(ws.hist_out, 0ull, (size_t)n_s, stream);
+    if (e != hipSuccess) return e;
+    const dim3 grid(blocks_for(N, 256));
+    if (rh.kind == kDisk)
+        k_scale_count<kDisk><<<grid, 256, 0, stream>>>(ws.sys, ws.species, r, pos, orient, ws.start,
+                                                       ws.members, ws.cell_of, ws.hist_edges, n_s,
+                                                       reach, ws.hist_out);
+    else if (rh.kind == kPolygon)
+        k_scale_count<kPolygon><<<grid, 256, 0, stream>>>(ws.sys, ws.species, r, pos, orient,
+                                                          ws.start, ws.members, ws.cell_of,
+                                                          ws.hist_edges, n_s, reach, ws.hist_out);
+    else
+        k_scale_count<kPolyhedron><<<grid, 256, 0, stream>>>(ws.sys, ws.species, r, pos, orient,
+                                                             ws.start, ws.members, ws.cell_of,
+                                                             ws.hist_edges, n_s, reach, ws.hist_out);
     return hipGetLastError();
 }
 

@@ -113,6 +113,10 @@ hipError_t pair_histogram(const Workspace& ws, const ReplicaHost& rh, int r, con
                           int n_bins, int reach, hipStream_t stream);
 hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
                           const double* orient, hipStream_t stream);
+// Volume-perturbation counts of replica r (scale factors already in
+// ws.hist_edges, cell list unshifted), written to ws.hist_out[0 .. n_s).
+hipError_t scale_counts(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
+                        const double* orient, int n_s, int reach, hipStream_t stream);
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream);
 

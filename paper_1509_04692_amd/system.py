@@ -171,6 +171,16 @@ class System:
                                                   len(e) - 1, out), "hpmc_pair_histogram")
         return np.array(out[:], dtype=np.uint64)
 
+    def scale_counts(self, scales, r=0):
+        """Pairs of replica r that overlap once every separation is scaled by
+        1 - scales[b] (volume perturbation); scales ascending in [0, 1)."""
+        sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64))
+        out = (ctypes.c_uint64 * len(sc))()
+        self._check(self._lib.hpmc_scale_counts(self._handle, int(r),
+                                                sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                len(sc), out), "hpmc_scale_counts")
+        return np.array(out[:], dtype=np.uint64)
+
     def stats(self):
         out = (_lib.Stats * self.n_replicas)()
         self._check(self._lib.hpmc_get_stats(self._handle, out), "hpmc_get_stats")
