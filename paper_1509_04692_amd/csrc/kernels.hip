@@ -95,6 +95,86 @@ __global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys,
     slot_of[S.slot_off + i] = atomicAdd(count + S.cell_off + c, 1u);
 }
 
+// The whole cell list of a small replica in one work-group of 1024 lanes
+// (blockIdx.x picks the replica): the same arrays as the multi-kernel build
+// (cell_of, slot_of, start, members in ascending tag order, and the sorted
+// binary32 copy when shifted) with the histogram and its scan in LDS, in one
+// launch instead of nine.  Used when every replica of the launch has at most
+// kSmallBuildN particles and kSmallBuildCells cells.
+template <int D>
+__global__ void __launch_bounds__(1024) k_build_small(const SysDev* __restrict__ sys,
+                                                      const int32_t* __restrict__ list,
+                                                      const double* __restrict__ pos_base,
+                                                      const Clock* __restrict__ clock, int shifted,
+                                                      uint32_t* __restrict__ cell_of,
+                                                      uint32_t* __restrict__ slot_of,
+                                                      uint32_t* __restrict__ start,
+                                                      uint32_t* __restrict__ members,
+                                                      float* __restrict__ xs) {
+    __shared__ uint32_t cnt[kSmallBuildCells + 1];
+    __shared__ uint32_t sm[16];
+    const SysDev S = sys[list[blockIdx.x]];
+    const int N = S.N, nc = S.ncells, tid = threadIdx.x;
+    const Clock ck = *clock;
+    double sh[3];
+    grid_shift(S, ck.t, ck.k0, ck.k1, shifted, sh);
+    const PosView pos{const_cast<double*>(pos_base) + S.pos_off, N};
+    uint32_t* cof = cell_of + S.slot_off;
+    uint32_t* sof = slot_of + S.slot_off;
+    uint32_t* st = start + S.cell_off;
+    uint32_t* mem = members + S.slot_off;
+    for (int c = tid; c < nc; c += 1024) cnt[c] = 0u;
+    __syncthreads();
+    for (int i = tid; i < N; i += 1024) {
+        const uint32_t c = particle_cell<D>(S, pos, (uint32_t)i, sh);
+        cof[i] = c;
+        sof[i] = atomicAdd(&cnt[c], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the histogram: lane t owns cells [t chunk, (t + 1) chunk)
+    const int chunk = (nc + 1023) / 1024, c0 = tid * chunk;
+    uint32_t sum = 0;
+    for (int j = 0; j < chunk; ++j) sum += c0 + j < nc ? cnt[c0 + j] : 0u;
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, sm, total);
+    for (int j = 0; j < chunk; ++j) {
+        if (c0 + j < nc) {
+            const uint32_t v = cnt[c0 + j];
+            cnt[c0 + j] = run;
+            st[c0 + j] = run;
+            run += v;
+        }
+    }
+    if (tid == 0) {
+        cnt[nc] = (uint32_t)N;
+        st[nc] = (uint32_t)N;
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += 1024) mem[cnt[cof[i]] + sof[i]] = (uint32_t)i;
+    __syncthreads();
+    // occupants of each cell in ascending tag order (a handful per cell)
+    for (int c = tid; c < nc; c += 1024) {
+        const uint32_t b = cnt[c], e = cnt[c + 1];
+        for (uint32_t p = b + 1; p < e; ++p) {
+            const uint32_t v = mem[p];
+            uint32_t q = p;
+            while (q > b && mem[q - 1] > v) {
+                mem[q] = mem[q - 1];
+                --q;
+            }
+            mem[q] = v;
+        }
+    }
+    if (!shifted) return;
+    __syncthreads();
+    const XsView<D> xv{xs + kXsStride * S.slot_off};
+    for (int p = tid; p < N; p += 1024) {
+        double y[3];
+        particle_grid<D>(S, pos, mem[p], sh, y);
+        xv.store((uint32_t)p, y);
+    }
+}
+
 // Counts particles of replica r with a coordinate outside [0, L) or a
 // non-finite orientation component (rejected by hpmc_init).
 template <int NCOMP>
@@ -890,6 +970,15 @@ hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream) {
 
 hipError_t build_cells(const Workspace& ws, const int32_t* list, int count, int dim, int64_t n_max,
                        int64_t nc_max, const double* pos, int shifted, hipStream_t stream) {
+    if (n_max <= kSmallBuildN && nc_max <= kSmallBuildCells) {
+        if (dim == 3)
+            k_build_small<3><<<count, 1024, 0, stream>>>(ws.sys, list, pos, ws.clock, shifted, ws.cell_of,
+                                                        ws.slot_of, ws.start, ws.members, ws.xs);
+        else
+            k_build_small<2><<<count, 1024, 0, stream>>>(ws.sys, list, pos, ws.clock, shifted, ws.cell_of,
+                                                        ws.slot_of, ws.start, ws.members, ws.xs);
+        return hipGetLastError();
+    }
     const dim3 by_cell(blocks_for(nc_max, 256), count), by_particle(blocks_for(n_max, 256), count);
     const dim3 by_tile(blocks_for(nc_max, kScanTile), count), one(1, count);
     k_zero_counts<<<by_cell, 256, 0, stream>>>(ws.sys, list, ws.count);

@@ -73,6 +73,10 @@ struct BatchGroup {
 };
 
 constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
+// Replicas up to this size build their cell list in one work-group (LDS
+// histogram of at most kSmallBuildCells cells).
+constexpr int64_t kSmallBuildN = 8192;
+constexpr int kSmallBuildCells = 16000;  // 64 KB of LDS with the scan scratch
 
 // Cell lists of the replicas list[0 .. count) in global memory (one launch
 // per step, blockIdx.y picks the replica; all of dimension dim, at most
