@@ -152,6 +152,13 @@ def cpu_baseline(wl, warmup, steps, budget_s=12.0):
         moves += int(st[0])
         t_sweep += chunk
     dt = time.perf_counter() - t0
+    # the separate serial one-move-at-a-time Metropolis reference, timed alongside
+    p, o = pos.copy(), ori.copy()
+    s_moves, t1 = 0, time.perf_counter()
+    while time.perf_counter() - t1 < budget_s / 4:
+        oracle.serial_metropolis(sp, L, p, o, seed=1, n_moves=20000, move0=s_moves)
+        s_moves += 20000
+    s_dt = time.perf_counter() - t1
     lib = oracle.load_counting()
     p, o = pos.copy(), ori.copy()
     oracle.sweep(sp, L, p, o, seed=1, n_sweeps=warmup, lib=lib)
@@ -186,6 +193,9 @@ def cpu_baseline(wl, warmup, steps, budget_s=12.0):
         "all_cores": {"value": all_moves / all_dt, "cores": n_proc,
                       "sample": f"{n_proc} oracle processes, one replica word each, "
                                 f"{all_dt:.1f} s"},
+        "serial_metropolis": {"value": s_moves / s_dt, "cores": 1,
+                              "sample": f"{s_moves} one-at-a-time moves of replica 0 from the "
+                                        f"initial state, {s_dt:.1f} s"},
     }, opm, {k: v / max(int(st[0]), 1) for k, v in ev.items()}, n_count
 
 
