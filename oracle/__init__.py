@@ -23,8 +23,10 @@ from .oracle import (  # noqa: F401
     index,
     load_counting,
     overlap_full,
+    npt_cycles,
     pair_histogram,
     scale_counts,
+    scale_positions,
     pair_overlaps,
     philox4x32_10,
     reset_events,

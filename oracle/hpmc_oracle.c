@@ -941,6 +941,17 @@ int or_pair_histogram(int32_t dim, int32_t N, double L, const double *pos,
     return OR_OK;
 }
 
+int or_scale_positions(int32_t dim, int32_t N, double L, double L_new, double *pos)
+{
+    if ((dim != 2 && dim != 3) || N < 0 || !(L > 0.0) || !(L_new > 0.0) || !pos)
+        return OR_ERR_INVALID_ARG;
+    double k = L_new / L;
+    for (int a = 0; a < dim; ++a)
+        for (int i = 0; i < N; ++i)
+            pos[a * N + i] = wrap(pos[a * N + i] * k, L_new);
+    return OR_OK;
+}
+
 int or_scale_counts(const or_species *sp, int32_t N, double L, const double *pos,
                     const double *orient, const double *s, int32_t n_s, int64_t *out)
 {

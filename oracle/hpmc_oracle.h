@@ -102,6 +102,12 @@ int or_pair_histogram(int32_t dim, int32_t N, double L, const double *pos,
 int or_scale_counts(const or_species *sp, int32_t N, double L, const double *pos,
                     const double *orient, const double *s, int32_t n_s, int64_t *out);
 
+/* Isotropic box change of an NPT volume move (Sec. 1 names the NPT
+ * ensemble): every coordinate x in [0, L) becomes x * (L_new / L), wrapped
+ * into [0, L_new) (x' >= L_new gives x' - L_new, and 0 if still >= L_new).
+ * The scale factor is one binary64 division, each coordinate one product. */
+int or_scale_positions(int32_t dim, int32_t N, double L, double L_new, double *pos);
+
 /* n_sweeps checkerboard sweeps of one system, sweep counter t0, t0+1, ...
  * Updates pos / orient in place and ADDS to stats[OR_NSTATS]. */
 int or_sweep(const or_species *sp, int32_t N, double L, double *pos,

@@ -3,6 +3,7 @@
 Argument marshalling only: every computation happens in ``hpmc_oracle.c``.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -84,6 +85,9 @@ def _declare(lib):
     lib.or_scale_counts.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D, _P_D,
                                     ctypes.c_int32, _P_I64]
     lib.or_scale_counts.restype = ctypes.c_int
+    lib.or_scale_positions.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_double, _P_D]
+    lib.or_scale_positions.restype = ctypes.c_int
     lib.or_count_overlaps.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D]
     lib.or_count_overlaps.restype = ctypes.c_int64
     lib.or_sweep.argtypes = [sp, ctypes.c_int32, ctypes.c_double, _P_D, _P_D,
@@ -270,6 +274,52 @@ def scale_counts(sp, L, pos, orient, scales, lib=None):
                                            _dptr(sc), len(sc), out.ctypes.data_as(_P_I64)),
            "scale_counts")
     return out
+
+
+def scale_positions(pos, L, L_new, lib=None):
+    """Scale (dim, N) positions in place from box L to box L_new."""
+    _check((lib or load()).or_scale_positions(pos.shape[0], pos.shape[1], float(L), float(L_new),
+                                              _dptr(pos)), "scale_positions")
+
+
+def npt_cycles(sp, L, pos, orient, seed, uniforms, sweeps_per_cycle, beta_p, delta_v, L_max,
+               t0=0, replica=0, lib=None):
+    """Isothermal-isobaric chain: each cycle runs sweeps_per_cycle checkerboard
+    sweeps, then one isotropic volume move V -> V + delta_v (2 u1 - 1) with
+    the uniforms (u1, u2) of that cycle.  The move is rejected if V' <= 0,
+    L' = V'^(1/dim) exceeds L_max or gives fewer than 4 cells per side, or
+    (when shrinking) the scaled state has an overlapping pair; otherwise it
+    is accepted when u2 < exp(-beta_p dV + N ln(V'/V)) (Frenkel & Smit's NPT
+    volume move for hard particles).  pos/orient are updated in place;
+    returns (L, sweep stats, accepted box moves)."""
+    dim, N = sp["dim"], pos.shape[1]
+    stats = np.zeros(N_STATS, dtype=np.int64)
+    t, accepted = t0, 0
+    for u1, u2 in uniforms:
+        stats += sweep(sp, L, pos, orient, seed, sweeps_per_cycle, t0=t, replica=replica, lib=lib)
+        t += sweeps_per_cycle
+        V = L ** dim
+        dV = delta_v * (2.0 * u1 - 1.0)
+        V2 = V + dV
+        if not V2 > 0.0:
+            continue
+        L2 = V2 ** (1.0 / dim)
+        if L2 > L_max:
+            continue
+        try:
+            grid(sp, N, L2, lib=lib)
+        except ValueError:
+            continue
+        trial = pos.copy()
+        scale_positions(trial, L, L2, lib=lib)
+        if dV < 0.0 and count_overlaps(sp, L2, trial, orient, lib=lib) > 0:
+            continue
+        if not u2 < math.exp(-beta_p * dV + N * math.log(V2 / V)):
+            continue
+        pos[...] = trial
+        L = L2
+        accepted += 1
+    return L, stats, accepted
 
 
 def sweep(sp, L, pos, orient, seed, n_sweeps, t0=0, replica=0, lib=None):

@@ -190,8 +190,6 @@ struct Layout {
     size_t pos_total, ori_total;
 };
 
-// Lanes per active cell on the grid path: enough waves to cover the chip
-// (256 CUs x 8 waves) when a pass has few active cells.
 // Queue mode from hpmc_init_args.flags; -1 when both variants are asked for.
 int queue_mode(int32_t flags) {
     const bool reg = (flags & HPMC_FLAG_REGISTER_QUEUE) != 0, glob = (flags & HPMC_FLAG_GLOBAL_QUEUE) != 0;
@@ -199,6 +197,8 @@ int queue_mode(int32_t flags) {
     return glob ? kQueueGlobal : (reg ? kQueueRegister : kQueueWave);
 }
 
+// Lanes per active cell on the grid path: enough waves to cover the chip
+// (256 CUs x 8 waves) when a pass has few active cells.
 int choose_lanes_per_cell(int64_t n_act) {
     const int64_t target_waves = 256 * 8;
     int g = 1;

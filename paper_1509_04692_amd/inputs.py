@@ -349,6 +349,12 @@ def initial_state(sp, N, phi, seed=INIT_SEED):
     return L, pos, orient
 
 
+def box_move_uniforms(n, seed=2028):
+    """(n, 2) seeded uniforms in [0, 1) for n NPT volume moves (the proposal
+    and the acceptance draw), a PCG64 stream shared by every implementation."""
+    return np.random.Generator(np.random.PCG64(seed)).random((n, 2))
+
+
 # -- workloads -----------------------------------------------------------------
 
 def workload_disks_256():
