@@ -129,6 +129,9 @@ typedef struct {
     size_t workspace_bytes;
     void *stream;                  /* hipStream_t or NULL */
     int32_t flags;                 /* HPMC_FLAG_* */
+    const double *L_max;           /* host, per replica: largest box side that
+                                      hpmc_scale_box may set (>= L; the cell
+                                      lists are sized for it); NULL = L */
 } hpmc_init_args;
 
 /* Per-replica counters since init or the last hpmc_reset_stats. */
@@ -174,6 +177,24 @@ int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
  * configuration gives the same trajectory.  Synchronising.  Returns
  * HPMC_ERR_INVALID_ARG for a configuration this state cannot use. */
 int hpmc_set_config(hpmc_state *st, int32_t config);
+
+/* Box change of an NPT volume move (Sec. 1: the paper runs NVT and NPT
+ * ensembles): every coordinate of replica r becomes x * (L_new / L) (one
+ * binary64 division for the factor, one product per coordinate), wrapped into
+ * [0, L_new) (x' >= L_new gives x' - L_new, and 0 if still >= L_new); the
+ * replica's grid is rebuilt for L_new (largest even n with cells at least
+ * d_max wide) and *overlaps (host, may be NULL) receives the number of
+ * overlapping pairs of the scaled state.  The previous positions and box are
+ * kept until the next hpmc_scale_box, hpmc_restore_box or hpmc_autotune of
+ * the state.  HPMC_ERR_INVALID_ARG for L_new <= 0 or above the replica's
+ * L_max, HPMC_ERR_BOX_TOO_SMALL below 4 cells per side (nothing changes then).
+ * Orientations are unchanged.  Synchronising. */
+int hpmc_scale_box(hpmc_state *st, int32_t replica, double L_new, uint64_t *overlaps);
+
+/* Undo the last hpmc_scale_box of replica r exactly (positions and box), as
+ * after a rejected volume move.  HPMC_ERR_INVALID_ARG when there is nothing
+ * to undo.  Synchronising. */
+int hpmc_restore_box(hpmc_state *st, int32_t replica);
 
 /* Volume-perturbation counts of one replica, the sampling behind the
  * pressure of particles with shape (Sec. 4): out[b] = number of unordered

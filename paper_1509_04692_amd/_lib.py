@@ -27,7 +27,8 @@ STAT_FIELDS = ("attempted", "attempted_rot", "cell_reject", "overlap_reject", "a
 
 # Every symbol include/hpmc.h declares.
 EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune", "hpmc_set_config",
-           "hpmc_count_overlaps", "hpmc_pair_histogram", "hpmc_scale_counts", "hpmc_get_stats", "hpmc_reset_stats",
+           "hpmc_count_overlaps", "hpmc_pair_histogram", "hpmc_scale_counts", "hpmc_scale_box",
+           "hpmc_restore_box", "hpmc_get_stats", "hpmc_reset_stats",
            "hpmc_sync_to_canonical", "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info",
            "hpmc_uses_graph", "hpmc_last_hip_error", "hpmc_destroy", "hpmc_strerror")
 FLAG_NO_GRAPH = 1
@@ -72,6 +73,7 @@ class InitArgs(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
         ("flags", ctypes.c_int32),
+        ("L_max", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -103,6 +105,9 @@ def load(path=None):
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_scale_counts.argtypes = [st, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.hpmc_scale_box.argtypes = [st, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    lib.hpmc_restore_box.argtypes = [st, ctypes.c_int32]
     lib.hpmc_get_stats.argtypes = [st, ctypes.POINTER(Stats)]
     lib.hpmc_reset_stats.argtypes = [st]
     lib.hpmc_sync_to_canonical.argtypes = [st]

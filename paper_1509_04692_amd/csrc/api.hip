@@ -38,6 +38,11 @@ struct hpmc_state {
     int flags = 0;
     size_t pos_total = 0, ori_total = 0;  // doubles in the caller's arrays
     hipStream_t cap_stream = nullptr;     // private stream used only for capture
+    std::vector<hpmc_species> spec_host;  // species as given (vertex pointer cleared)
+    std::vector<int32_t> list;            // host copy of the launch groups' replica list
+    std::vector<SysDev> sys_saved;        // box before the last hpmc_scale_box, per replica
+    std::vector<ReplicaHost> rep_saved;
+    std::vector<uint8_t> box_saved;
     hipGraphExec_t graph = nullptr;       // one sweep (grid) / one chunk (persistent)
 };
 
@@ -178,6 +183,7 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
     rh.n = n;
     rh.ncells = S.ncells;
     rh.rounds = S.rounds;
+    rh.L = L;
     return HPMC_OK;
 }
 
@@ -229,6 +235,15 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         if (rc) return rc;
         rc = build_grid(a->species[r], spc[r], a->N[r], a->L[r], sys[r], rep[r]);
         if (rc) return rc;
+        // cell lists are sized for the largest box a volume move may reach
+        const double L_max = a->L_max ? a->L_max[r] : a->L[r];
+        if (!(L_max >= a->L[r]) || !std::isfinite(L_max)) return HPMC_ERR_INVALID_ARG;
+        SysDev smax;
+        ReplicaHost hmax;
+        rc = build_grid(a->species[r], spc[r], a->N[r], L_max, smax, hmax);
+        if (rc) return rc;
+        rep[r].ncells_cap = std::max(smax.ncells, sys[r].ncells);
+        rep[r].L_max = L_max;
         sys[r].species = r;
         sys[r].replica = r;
         sys[r].pos_off = pos_off;
@@ -242,11 +257,11 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         sys[r].cell_off = cell_total;
         sys[r].slot_off = slot_total;
         sys[r].part_off = part_total;
-        cell_total += (int64_t)sys[r].ncells + 1;
+        cell_total += (int64_t)rep[r].ncells_cap + 1;
         slot_total += sys[r].N;
-        part_total += ((int64_t)sys[r].ncells + kScanTile - 1) / kScanTile;
+        part_total += ((int64_t)rep[r].ncells_cap + kScanTile - 1) / kScanTile;
         const int ncomp_r = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
-        const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, sys[r].ncells, sys[r].N, 0);
+        const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, rep[r].ncells_cap, sys[r].N, 0);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
         const int half = sys[r].n / 2;
         const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
@@ -277,8 +292,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
                 g.count++;
                 g.nv = (g.nv == -1 || g.nv == spc[r].nv) ? spc[r].nv : 0;
                 for (int lv = 0; lv < 3; ++lv)
-                    need[lv] = std::max(need[lv], persistent_lds_bytes(sys[r].dim, ncomp, sys[r].ncells,
-                                                                       sys[r].N, lv));
+                    need[lv] = std::max(need[lv], persistent_lds_bytes(sys[r].dim, ncomp,
+                                                                       rep[r].ncells_cap, sys[r].N, lv));
             }
             if (g.count == 0) continue;
             g.resident = 0;
@@ -491,6 +506,36 @@ int apply_config(hpmc_state* st, int cfg) {
     return HPMC_OK;
 }
 
+// Grid-path launch sizes of each group after a replica's box changed.
+void refresh_grid_groups(hpmc_state* st) {
+    if (st->path != HPMC_PATH_GRID) return;
+    for (BatchGroup& g : st->groups) {
+        g.rounds_max = 0;
+        g.nc_max = 0;
+        g.n_act_max = 0;
+        for (int j = g.first; j < g.first + g.count; ++j) {
+            const SysDev& S = st->sys[st->list[j]];
+            const int half = S.n / 2;
+            const int64_t n_act = S.dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
+            g.rounds_max = std::max<int32_t>(g.rounds_max, S.rounds);
+            g.nc_max = std::max<int64_t>(g.nc_max, S.ncells);
+            g.n_act_max = std::max<int64_t>(g.n_act_max, n_act);
+        }
+    }
+}
+
+// Replace replica r's box description (host and device) and re-capture.
+int set_replica_box(hpmc_state* st, int r, const SysDev& S, const ReplicaHost& rh) {
+    st->sys[r] = S;
+    st->rep[r] = rh;
+    int rc = check_hip(st, hipMemcpyAsync(st->ws.sys + r, &st->sys[r], sizeof(SysDev),
+                                          hipMemcpyHostToDevice, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    refresh_grid_groups(st);
+    if (!rc) capture_graph(st);
+    return rc;
+}
+
 int run_sweeps(hpmc_state* st, uint64_t n_sweeps, uint32_t k0, uint32_t k1) {
     int rc = check_hip(st, set_clock(st->ws, (uint32_t)st->t, k0, k1, st->stream));
     const uint32_t unit = sweep_unit(st);
@@ -581,6 +626,12 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     st->ori_total = lay.ori_total;
     st->flags = args->flags;
     st->queue = queue_mode(args->flags);
+    st->list = list;
+    st->spec_host.assign(args->species, args->species + args->n_replicas);
+    for (hpmc_species& sp : st->spec_host) sp.verts = nullptr;  // not kept by the caller
+    st->sys_saved.assign(st->n_replicas, SysDev{});
+    st->rep_saved.assign(st->n_replicas, ReplicaHost{});
+    st->box_saved.assign(st->n_replicas, 0);
     if (st->queue == kQueueGlobal) {
         GlobalQueue& q = st->ws.gq;
         q.trial = (double*)(base + lay.gq_trial);
@@ -693,6 +744,68 @@ int hpmc_pair_histogram(hpmc_state* st, int32_t replica, const double* edges2, i
     return rc;
 }
 
+int hpmc_scale_box(hpmc_state* st, int32_t replica, double L_new, uint64_t* overlaps) {
+    if (st == nullptr || replica < 0 || replica >= st->n_replicas) return HPMC_ERR_INVALID_ARG;
+    const int r = replica;
+    if (!(L_new > 0.0) || !std::isfinite(L_new) || L_new > st->rep[r].L_max)
+        return HPMC_ERR_INVALID_ARG;
+    SysDev S = st->sys[r];
+    ReplicaHost rh = st->rep[r];
+    int rc = build_grid(st->spec_host[r], st->spc[r], rh.N, L_new, S, rh);
+    if (rc) return rc;
+    if (rh.ncells > st->rep[r].ncells_cap) return HPMC_ERR_INVALID_ARG;
+    // keep what build_grid does not know: offsets, indices, launch settings
+    const SysDev& old = st->sys[r];
+    S.species = old.species;
+    S.replica = old.replica;
+    S.path = old.path;
+    S.pos_off = old.pos_off;
+    S.orient_off = old.orient_off;
+    S.cell_off = old.cell_off;
+    S.slot_off = old.slot_off;
+    S.part_off = old.part_off;
+    const ReplicaHost& oh = st->rep[r];
+    rh.path = oh.path;
+    rh.lanes_per_cell = oh.lanes_per_cell;
+    rh.nv = oh.nv;
+    rh.pos_off = oh.pos_off;
+    rh.orient_off = oh.orient_off;
+    rh.ncells_cap = oh.ncells_cap;
+    rh.L_max = oh.L_max;
+    const int64_t nval = (int64_t)rh.dim * rh.N;
+    double* p = st->pos + oh.pos_off;
+    rc = check_hip(st, hipMemcpyAsync(st->ws.backup_pos + oh.pos_off, p, 8 * (size_t)nval,
+                                      hipMemcpyDeviceToDevice, st->stream));
+    if (!rc) rc = check_hip(st, scale_box(p, nval, L_new / old.L, L_new, st->stream));
+    if (rc) return rc;
+    st->sys_saved[r] = st->sys[r];
+    st->rep_saved[r] = st->rep[r];
+    st->box_saved[r] = 1;
+    rc = set_replica_box(st, r, S, rh);
+    if (rc || overlaps == nullptr) return rc;
+    rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
+    if (!rc) rc = check_hip(st, build_cells_one(st->ws, st->rep[r], r, st->pos, 0, st->stream));
+    if (!rc) rc = check_hip(st, count_pairs(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(overlaps, st->ws.overlap_out + r, sizeof(uint64_t),
+                                          hipMemcpyDeviceToHost, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    return rc;
+}
+
+int hpmc_restore_box(hpmc_state* st, int32_t replica) {
+    if (st == nullptr || replica < 0 || replica >= st->n_replicas || !st->box_saved[replica])
+        return HPMC_ERR_INVALID_ARG;
+    const int r = replica;
+    const ReplicaHost& rh = st->rep_saved[r];
+    const int64_t nval = (int64_t)rh.dim * rh.N;
+    int rc = check_hip(st, hipMemcpyAsync(st->pos + rh.pos_off, st->ws.backup_pos + rh.pos_off,
+                                          8 * (size_t)nval, hipMemcpyDeviceToDevice, st->stream));
+    if (rc) return rc;
+    st->box_saved[r] = 0;
+    return set_replica_box(st, r, st->sys_saved[r], st->rep_saved[r]);
+}
+
 int hpmc_scale_counts(hpmc_state* st, int32_t replica, const double* scales, int32_t n_scales,
                       uint64_t* out) {
     if (st == nullptr || scales == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
@@ -798,6 +911,7 @@ int hpmc_uses_graph(hpmc_state* st) { return (st && st->graph) ? 1 : 0; }
 
 int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
     if (st == nullptr || trial_sweeps == 0) return HPMC_ERR_INVALID_ARG;
+    std::fill(st->box_saved.begin(), st->box_saved.end(), 0);  // its snapshot reuses that buffer
     const size_t nstat = (size_t)kStatsPerReplica * st->n_replicas;
     // snapshot the caller's state
     int rc = check_hip(st, hipMemcpyAsync(st->ws.backup_pos, st->pos, 8 * st->pos_total,

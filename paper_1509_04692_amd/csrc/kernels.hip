@@ -1185,6 +1185,27 @@ hipError_t scale_counts(const Workspace& ws, const ReplicaHost& rh, int r, const
     return hipGetLastError();
 }
 
+// Isotropic box change: x -> x k, wrapped into [0, L_new).
+__global__ void __launch_bounds__(256) k_scale_box(double* __restrict__ p, int64_t n, double k,
+                                                   double L_new) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = p[i] * k;
+    double y = x;
+    if (x >= L_new)
+        y = x - L_new;
+    else if (x < 0.0)
+        y = x + L_new;
+    if (y >= L_new) y = 0.0;
+    p[i] = y;
+}
+
+hipError_t scale_box(double* pos, int64_t n, double k, double L_new, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    k_scale_box<<<blocks_for(n, 256), 256, 0, stream>>>(pos, n, k, L_new);
+    return hipGetLastError();
+}
+
 hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
                           const double* orient, hipStream_t stream) {
     const int N = rh.N;

@@ -53,6 +53,8 @@ enum QueueMode : int32_t { kQueueWave = 0, kQueueRegister = 1, kQueueGlobal = 2 
 
 struct ReplicaHost {
     int32_t kind, dim, N, n, ncells, rounds, path;
+    int32_t ncells_cap;      // cells allocated for this replica (grid of its largest box)
+    double L, L_max;         // current box side, largest allowed (NPT box moves)
     int32_t lanes_per_cell;  // grid path: lanes per active cell (1, 2, 4, ..., 64)
     int32_t nv;              // polygon vertex count (compile-time fast path for 5)
     int64_t pos_off, orient_off;
@@ -123,6 +125,8 @@ hipError_t scale_counts(const Workspace& ws, const ReplicaHost& rh, int r, const
                         const double* orient, int n_s, int reach, hipStream_t stream);
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream);
+// n coordinates x -> x k wrapped into [0, L_new) (NPT box change).
+hipError_t scale_box(double* pos, int64_t n, double k, double L_new, hipStream_t stream);
 
 // Dynamic LDS of a persistent work-group (positions resident or not).
 size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res);

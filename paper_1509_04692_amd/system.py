@@ -6,6 +6,9 @@ every step of the sweep runs in the library's HIP kernels.
     sys.count_overlaps()              # system-level overlap check (Sec. 4)
     sys.stats()
 
+``L_max`` (per replica, default L) bounds the box sides that volume moves
+(``scale_box``, the NPT driver in ``npt.py``) may reach.
+
 ``queue`` picks how a pass schedules its full overlap tests: "wave" (the
 block work queue, per wave64 in LDS; the default), or the paper's two
 comparison variants "register" and "global" (grid path only).
@@ -34,7 +37,7 @@ def _as_list(x, n):
 
 class System:
     def __init__(self, species, N, L, pos, orient=None, precision="fp64", path="auto",
-                 device="cuda", stream=None, graphs=True, queue="wave"):
+                 device="cuda", stream=None, graphs=True, queue="wave", L_max=None):
         import torch
 
         self._torch = torch
@@ -98,6 +101,9 @@ class System:
         self._sp_arr = sp_arr
         self._N_arr = (ctypes.c_int32 * n_rep)(*self.N)
         self._L_arr = (ctypes.c_double * n_rep)(*self.L)
+        self.L_max = ([float(x) for x in _as_list(L_max, n_rep)] if L_max is not None
+                      else list(self.L))
+        self._Lmax_arr = (ctypes.c_double * n_rep)(*self.L_max)
 
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -115,6 +121,7 @@ class System:
         if queue not in _lib.QUEUE_FLAGS:
             raise ValueError(f"queue must be one of {sorted(_lib.QUEUE_FLAGS)}")
         args.flags = (0 if graphs else _lib.FLAG_NO_GRAPH) | _lib.QUEUE_FLAGS[queue]
+        args.L_max = self._Lmax_arr
         nbytes = ctypes.c_size_t()
         self._check(self._lib.hpmc_workspace_bytes(ctypes.byref(args), ctypes.byref(nbytes)),
                     "hpmc_workspace_bytes")
@@ -180,6 +187,21 @@ class System:
                                                 sc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                                 len(sc), out), "hpmc_scale_counts")
         return np.array(out[:], dtype=np.uint64)
+
+    def scale_box(self, r, L_new):
+        """Scale replica r's box (and positions) to side L_new; returns the
+        number of overlapping pairs after scaling.  restore_box(r) undoes it."""
+        out = ctypes.c_uint64()
+        self._check(self._lib.hpmc_scale_box(self._handle, int(r), float(L_new), ctypes.byref(out)),
+                    "hpmc_scale_box")
+        self._L_prev = getattr(self, "_L_prev", {})
+        self._L_prev[r] = self.L[r]
+        self.L[r] = float(L_new)
+        return int(out.value)
+
+    def restore_box(self, r):
+        self._check(self._lib.hpmc_restore_box(self._handle, int(r)), "hpmc_restore_box")
+        self.L[r] = self._L_prev.pop(r)
 
     def stats(self):
         out = (_lib.Stats * self.n_replicas)()

@@ -44,7 +44,7 @@ def test_strerror(lib):
     assert lib.hpmc_strerror(-99) == b"unknown error"
 
 
-def _args(species_list, Ns, Ls, precision=0, path=0, flags=0):
+def _args(species_list, Ns, Ls, precision=0, path=0, flags=0, L_max=None):
     n = len(species_list)
     keep = []
     sp_arr = (_lib.Species * n)()
@@ -66,7 +66,11 @@ def _args(species_list, Ns, Ls, precision=0, path=0, flags=0):
     Larr = (ctypes.c_double * n)(*Ls)
     a.N, a.L = Narr, Larr
     a.precision, a.path, a.flags = precision, path, flags
-    return a, (keep, sp_arr, Narr, Larr)
+    Lmax = None
+    if L_max is not None:
+        Lmax = (ctypes.c_double * n)(*L_max)
+        a.L_max = Lmax
+    return a, (keep, sp_arr, Narr, Larr, Lmax)
 
 
 def ws_bytes(lib, *args, **kw):
@@ -137,3 +141,15 @@ def test_sweep_radius_rules(lib):
     pent = dict(inputs.pentagon_species(), sweep_radius=0.1)
     assert ws_bytes(lib, [pent], [1024], [32.0])[0] == -1          # polyhedra only
     assert ws_bytes(lib, [inputs.spherocylinder_species()], [512], [16.5])[0] == 0
+
+
+def test_box_growth_limit(lib):
+    """Cell lists are sized for the largest box a volume move may reach."""
+    sp = inputs.pentagon_species()
+    L = 63.70118630129784
+    rc0, b0 = ws_bytes(lib, [sp], [4096], [L])
+    rc1, b1 = ws_bytes(lib, [sp], [4096], [L], L_max=[L])
+    rc2, b2 = ws_bytes(lib, [sp], [4096], [L], L_max=[1.5 * L])
+    assert rc0 == rc1 == rc2 == 0 and b0 == b1 and b2 > b1
+    assert ws_bytes(lib, [sp], [4096], [L], L_max=[0.9 * L])[0] == -1  # below L
+    assert ws_bytes(lib, [sp], [4096], [L], L_max=[float("inf")])[0] == -1

@@ -404,6 +404,60 @@ def test_scale_counts_match_oracle(kind):
         assert got[0] == 0 and got[-1] > 0
 
 
+@pytest.mark.parametrize("case", ["disks_grid", "disks_persistent", "pentagons_mixed",
+                                  "cubes_mixed"])
+def test_npt_volume_moves_equal_the_oracle(case):
+    """Sweeps interleaved with volume moves (box scaling and the overlap count
+    in the kernels, acceptance on the host): final positions, orientations,
+    box side, accepted moves and sweep counters equal the oracle's NPT chain
+    bit for bit, with the grid rebuilt as the box changes."""
+    shape, path = case.split("_")
+    if shape == "disks":
+        sp, N, L, pos, orient = inputs.workload_disks_256()
+        beta_p, prec = 2.6, "fp64"
+    elif shape == "pentagons":
+        sp, N, L, pos, orient = inputs.workload_pentagons(400, 0.60)
+        beta_p, prec, path = 5.0, "mixed", "grid"
+    else:
+        sp, N, L, pos, orient = inputs.workload_cubes(512, 0.45)
+        beta_p, prec, path = 2.0, "mixed", "grid"
+    from paper_1509_04692_amd import npt
+    u = inputs.box_move_uniforms(40, seed=81)
+    delta_v = 0.004 * L ** sp["dim"]
+    announce(f"npt {case} N={N} L={L:.4f}")
+    system = _system(sp, N, L, pos, orient, precision=prec, path=path, L_max=1.2 * L)
+    acc = npt.npt_cycles(system, 0, seed=5, uniforms=u, sweeps_per_cycle=3, beta_p=beta_p,
+                         delta_v=delta_v)
+    ref_pos, ref_ori = pos.copy(), orient.copy()
+    ref_L, ref_stats, ref_acc = oracle.npt_cycles(sp, L, ref_pos, ref_ori, 5, u, 3, beta_p, delta_v,
+                                                  L_max=1.2 * L)
+    assert acc == ref_acc and 0 < acc < len(u)
+    assert system.L[0] == ref_L
+    assert_parity((system.positions(), system.orientations(), system.stats()[0]),
+                  (ref_pos, ref_ori, ref_stats), sp)
+    assert system.count_overlaps()[0] == 0
+
+
+def test_box_move_errors():
+    from paper_1509_04692_amd._lib import HpmcError
+    sp, N, L, pos, orient = inputs.workload_disks_256()
+    announce("box move errors")
+    system = _system(sp, N, L, pos, orient, path="grid", L_max=1.1 * L)
+    with pytest.raises(HpmcError):
+        system.restore_box(0)  # nothing to undo
+    with pytest.raises(HpmcError):
+        system.scale_box(0, 1.2 * L)  # beyond L_max
+    with pytest.raises(HpmcError):
+        system.scale_box(0, 3.0)  # fewer than 4 cells per side
+    before = system.positions().copy()
+    # the 16 x 16 square lattice (pitch 1.253) overlaps once scaled by 0.75,
+    # with every nearest-neighbour pair (512 of them) at distance 0.94
+    assert system.scale_box(0, 0.75 * L) == 512
+    system.restore_box(0)
+    assert np.array_equal(system.positions(), before) and system.L[0] == L
+    assert system.count_overlaps()[0] == 0
+
+
 def test_initial_overlap_and_box_errors():
     from paper_1509_04692_amd._lib import HpmcError
     sp, N, L, pos, orient = inputs.workload_disks_256()
