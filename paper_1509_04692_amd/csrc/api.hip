@@ -660,6 +660,9 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
         rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kStatsPerReplica * st->n_replicas,
                                     st->stream));
     if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
+    if (!rc)  // cell histograms start at zero; every build leaves them so
+        rc = check_hip(st, fill_u64((unsigned long long*)st->ws.count, 0ull,
+                                    ((size_t)lay.cell_total + 1) / 2, st->stream));
     if (!rc && st->queue == kQueueGlobal)  // queue lengths start at zero; each pass leaves them so
         rc = check_hip(st, fill_u64((unsigned long long*)st->ws.gq.count, 0ull, (size_t)st->n_replicas,
                                     st->stream));

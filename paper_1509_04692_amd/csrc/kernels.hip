@@ -68,14 +68,6 @@ __global__ void k_advance_clock(Clock* __restrict__ clock, uint32_t n) {
 // replicas list[0 .. gridDim.y): blockIdx.y picks the replica, whose slice
 // of the arrays starts at the offsets in its SysDev; blocks beyond the
 // replica's size return at once (whole blocks, before any barrier).
-__global__ void __launch_bounds__(256) k_zero_counts(const SysDev* __restrict__ sys,
-                                                     const int32_t* __restrict__ list,
-                                                     uint32_t* __restrict__ count) {
-    const SysDev S = sys[list[blockIdx.y]];
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < S.ncells) count[S.cell_off + c] = 0u;
-}
-
 template <int D>
 __global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys,
                                                 const int32_t* __restrict__ list,
@@ -217,46 +209,35 @@ __global__ void __launch_bounds__(256) k_scan_tiles(const SysDev* __restrict__ s
     if (threadIdx.x == 0) partial[S.part_off + blockIdx.x] = total;
 }
 
-// Exclusive scan of a replica's tile sums in place (one work-group each).
-__global__ void __launch_bounds__(256) k_scan_partials(const SysDev* __restrict__ sys,
-                                                       const int32_t* __restrict__ list,
-                                                       uint32_t* __restrict__ partial) {
-    __shared__ uint32_t sm[16];
-    const SysDev S = sys[list[blockIdx.y]];
-    const int ntiles = (S.ncells + kScanTile - 1) / kScanTile;
-    uint32_t* part = partial + S.part_off;
-    uint32_t carry = 0;
-    for (int base = 0; base < ntiles; base += blockDim.x) {
-        const int j = base + threadIdx.x;
-        const uint32_t v = j < ntiles ? part[j] : 0u;
-        uint32_t total;
-        const uint32_t ex = block_exclusive_scan(v, sm, total);
-        if (j < ntiles) part[j] = carry + ex;
-        carry += total;
-        __syncthreads();
-    }
-}
-
+// Start offsets of a tile's cells: the tile's exclusive scan plus the sum of
+// the earlier tiles' totals (read straight from the tile sums, so no separate
+// scan of them is launched).  The histogram is cleared behind the read, so
+// the next build starts from zero counts.
 __global__ void __launch_bounds__(256) k_scan_apply(const SysDev* __restrict__ sys,
                                                     const int32_t* __restrict__ list,
-                                                    const uint32_t* __restrict__ count,
+                                                    uint32_t* __restrict__ count,
                                                     const uint32_t* __restrict__ partial,
                                                     uint32_t* __restrict__ start) {
     __shared__ uint32_t sm[16];
     const SysDev S = sys[list[blockIdx.y]];
     const int nc = S.ncells;
     if ((int)blockIdx.x * kScanTile >= nc) return;
-    const uint32_t* cnt = count + S.cell_off;
+    uint32_t* cnt = count + S.cell_off;
     uint32_t* st = start + S.cell_off;
+    uint32_t before = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += blockDim.x) before += partial[S.part_off + j];
+    uint32_t prefix;
+    (void)block_exclusive_scan(before, sm, prefix);
     const int base = blockIdx.x * kScanTile + threadIdx.x * 8;
     uint32_t v[8], s = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         v[j] = base + j < nc ? cnt[base + j] : 0u;
+        if (base + j < nc) cnt[base + j] = 0u;
         s += v[j];
     }
     uint32_t total;
-    uint32_t run = block_exclusive_scan(s, sm, total) + partial[S.part_off + blockIdx.x];
+    uint32_t run = block_exclusive_scan(s, sm, total) + prefix;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         if (base + j < nc) st[base + j] = run;
@@ -980,8 +961,8 @@ hipError_t build_cells(const Workspace& ws, const int32_t* list, int count, int 
         return hipGetLastError();
     }
     const dim3 by_cell(blocks_for(nc_max, 256), count), by_particle(blocks_for(n_max, 256), count);
-    const dim3 by_tile(blocks_for(nc_max, kScanTile), count), one(1, count);
-    k_zero_counts<<<by_cell, 256, 0, stream>>>(ws.sys, list, ws.count);
+    const dim3 by_tile(blocks_for(nc_max, kScanTile), count);
+    // the histogram is all zero here: cleared at init and by every k_scan_apply
     if (dim == 3)
         k_assign<3><<<by_particle, 256, 0, stream>>>(ws.sys, list, pos, ws.clock, shifted, ws.count,
                                                      ws.cell_of, ws.slot_of);
@@ -989,7 +970,6 @@ hipError_t build_cells(const Workspace& ws, const int32_t* list, int count, int 
         k_assign<2><<<by_particle, 256, 0, stream>>>(ws.sys, list, pos, ws.clock, shifted, ws.count,
                                                      ws.cell_of, ws.slot_of);
     k_scan_tiles<<<by_tile, 256, 0, stream>>>(ws.sys, list, ws.count, ws.partial);
-    k_scan_partials<<<one, 256, 0, stream>>>(ws.sys, list, ws.partial);
     k_scan_apply<<<by_tile, 256, 0, stream>>>(ws.sys, list, ws.count, ws.partial, ws.start);
     k_scatter<<<by_particle, 256, 0, stream>>>(ws.sys, list, ws.cell_of, ws.slot_of, ws.start,
                                                ws.members);

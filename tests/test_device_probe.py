@@ -18,6 +18,11 @@ LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libdevice
 
 @pytest.fixture(scope="module")
 def probe():
+    # initialise the GPU through PyTorch first, as the library's own users do,
+    # so that one HIP runtime serves the process
+    import torch
+    assert torch.cuda.is_available(), "the device probe needs a GPU"
+    torch.cuda.init()
     if not os.path.exists(LIB):
         raise RuntimeError(f"{LIB} is missing: build with __graft_entry__.build()")
     lib = ctypes.CDLL(LIB)
