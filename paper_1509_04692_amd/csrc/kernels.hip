@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_assign(const SysDev* __restrict__ sys,
 // (blockIdx.x picks the replica): the same arrays as the multi-kernel build
 // (cell_of, slot_of, start, members in ascending tag order, and the sorted
 // binary32 copy when shifted) with the histogram and its scan in LDS, in one
-// launch instead of nine.  Used when every replica of the launch has at most
+// launch instead of six.  Used when every replica of the launch has at most
 // kSmallBuildN particles and kSmallBuildCells cells.
 template <int D>
 __global__ void __launch_bounds__(1024) k_build_small(const SysDev* __restrict__ sys,
