@@ -240,14 +240,18 @@ __device__ __forceinline__ int div_floor(int a, int m, double inv_m) {
 }
 
 // Cell of active index a in colour `colour`: the active cells of a colour
-// are every other cell along each axis, offset by the colour's bits.
+// are every other cell along each axis, offset by the colour's bits.  The
+// index runs fastest along x, or along y when Y_FIRST (consecutive lanes then
+// share an x column, so few waves hold a cell at the periodic x edge).
+template <bool Y_FIRST = false>
 __device__ __forceinline__ void active_cell(const SysDev& S, int D, uint32_t colour, int a,
                                             double inv_half, int (&cc)[3], uint32_t& c) {
     const int half = S.n / 2;
     const int q1 = div_floor(a, half, inv_half);
     const int q2 = D == 3 ? div_floor(q1, half, inv_half) : 0;
-    cc[0] = 2 * (a - q1 * half) + (int)(colour & 1u);
-    cc[1] = 2 * (q1 - q2 * half) + (int)((colour >> 1) & 1u);
+    const int fast = a - q1 * half, mid = q1 - q2 * half;
+    cc[0] = 2 * (Y_FIRST ? mid : fast) + (int)(colour & 1u);
+    cc[1] = 2 * (Y_FIRST ? fast : mid) + (int)((colour >> 1) & 1u);
     cc[2] = D == 3 ? 2 * q2 + (int)((colour >> 2) & 1u) : 0;
     c = (uint32_t)(cc[0] + S.n * (cc[1] + S.n * cc[2]));
 }
@@ -539,7 +543,9 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     double qn[4] = {1.0, 0.0, 0.0, 0.0};
     bool c_rot = false, c_moved = false;  // rotation attempted / translation attempted
     if (sub == 0 && a < n_act) {
-        active_cell(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
+        // LDS-resident tiles (PARK) index y first: data locality does not
+        // matter there, and most waves then skip the x-wrapped ranges
+        active_cell<PARK>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
         const uint32_t beg = cl.begin(c), fin = cl.end(c);
         if (beg != fin) {
             ct.attempted++;
@@ -618,7 +624,11 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         bool flagged = false;  // this lane's cell already has an overlap (register copy)
         uint32_t queued = 0;   // wave-uniform
         uint32_t queued2 = 0;  // wave-uniform, polygons only
+        // with one lane per cell, the x-wrapped (odd) ranges are empty unless a
+        // live cell of the wave sits at the periodic x edge: skip them then
+        const bool x_edge = G > 1 || wave_ballot(live && (cc[0] == 0 || cc[0] == n - 1)) != 0ull;
         for (int kr = 0; kr < NK; ++kr) {
+            if (G == 1 && (kr & 1) && !x_edge) continue;
             const int ri = sub + kr * G;
             uint32_t p = 0, e = 0;
             float ref[3] = {0.0f, 0.0f, 0.0f};
