@@ -184,9 +184,9 @@ int hpmc_set_config(hpmc_state *st, int32_t config);
  * [0, L_new) (x' >= L_new gives x' - L_new, and 0 if still >= L_new); the
  * replica's grid is rebuilt for L_new (largest even n with cells at least
  * d_max wide) and *overlaps (host, may be NULL) receives the number of
- * overlapping pairs of the scaled state.  The previous positions and box are
- * kept until the next hpmc_scale_box, hpmc_restore_box or hpmc_autotune of
- * the state.  HPMC_ERR_INVALID_ARG for L_new <= 0 or above the replica's
+ * overlapping pairs of the scaled state.  The replica's previous positions
+ * and box are kept until its next hpmc_scale_box or hpmc_restore_box, or
+ * any hpmc_autotune of the state.  HPMC_ERR_INVALID_ARG for L_new <= 0 or above the replica's
  * L_max, HPMC_ERR_BOX_TOO_SMALL below 4 cells per side (nothing changes then).
  * Orientations are unchanged.  Synchronising. */
 int hpmc_scale_box(hpmc_state *st, int32_t replica, double L_new, uint64_t *overlaps);
