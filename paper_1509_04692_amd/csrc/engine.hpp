@@ -543,9 +543,10 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     double qn[4] = {1.0, 0.0, 0.0, 0.0};
     bool c_rot = false, c_moved = false;  // rotation attempted / translation attempted
     if (sub == 0 && a < n_act) {
-        // LDS-resident tiles (PARK) index y first: data locality does not
-        // matter there, and most waves then skip the x-wrapped ranges
-        active_cell<PARK>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
+        // LDS-resident 2D tiles (PARK) index y first: data locality does not
+        // matter there, and most waves then skip the x-wrapped ranges (in 3D
+        // a wave spans several x columns, so nearly every wave holds an edge)
+        active_cell<PARK && D == 2>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
         const uint32_t beg = cl.begin(c), fin = cl.end(c);
         if (beg != fin) {
             ct.attempted++;

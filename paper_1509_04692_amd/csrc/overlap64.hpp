@@ -135,10 +135,12 @@ __device__ __forceinline__ V3 support64(const SpeciesDev& P, const Minkowski64& 
            (((m[2][0] * bx + m[2][1] * by) + m[2][2] * bz) + mk.t.z) - P.vz[ka]};
     // spheropolyhedra: each particle's ball adds sweep n/|n| to its support,
     // so the difference gains (sweep + sweep) n/|n| (none for n = 0)
-    const double nn = dot(n, n);
-    if (P.sweep > 0.0 && nn > 0.0) {
-        const double s = (P.sweep + P.sweep) / sqrt(nn);
-        out = V3{out.x + s * n.x, out.y + s * n.y, out.z + s * n.z};
+    if (P.sweep > 0.0) {  // uniform per species: plain polyhedra skip it whole
+        const double nn = dot(n, n);
+        if (nn > 0.0) {
+            const double s = (P.sweep + P.sweep) / sqrt(nn);
+            out = V3{out.x + s * n.x, out.y + s * n.y, out.z + s * n.z};
+        }
     }
     return out;
 }
