@@ -1,6 +1,7 @@
 """Pins of the pair-separation histogram (oracle) and of the contact-value
 pressure estimator (Sec. 4, Table 1)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -103,3 +104,30 @@ def test_scale_route_recovers_the_contact_slope(dim):
     contact = (pressure.disk_pressure(N, L, sigma, g0 * (N - 1) / N) if dim == 2
                else pressure.sphere_pressure(N, L, sigma, g0 * (N - 1) / N)) / rho
     assert abs(pressure.scale_pressure(N, dim, s, counts, degree=3) - contact) < 1e-6
+
+
+def _table1():
+    rows = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_pressures.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            shape, N, phi, serial, one_gpu = line.split()
+            rows[shape] = (int(N), float(phi), float(serial.split("(")[0]))
+    return rows
+
+
+def test_validation_drivers_use_the_table_1_state_points():
+    """The pressure and NPT checks run the paper's state points and compare
+    with its serial values (tests/golden/table1_pressures.txt)."""
+    import inspect
+    from paper_1509_04692_amd import validate_npt, validate_pressure
+    t = _table1()
+    src = inspect.getsource(validate_pressure)
+    for shape, key in (("disk", "disk"), ("sphere", "sphere"), ("truncated_oct", "trunc_oct")):
+        N, phi, p = t[shape]
+        assert f"{p}" in src and f"{N}" in src, shape
+    npt_src = inspect.getsource(validate_npt)
+    assert f'{t["disk"][2]}' in npt_src and f'{t["disk"][1]}' in npt_src
+    # the disk state point maps to the contact value used by the pin above
+    L = math.sqrt(t["disk"][0] * math.pi / 4 / t["disk"][1])
+    assert abs(pressure.disk_pressure(t["disk"][0], L, 1.0, 6.676) - t["disk"][2]) < 1e-3
