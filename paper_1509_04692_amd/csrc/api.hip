@@ -524,15 +524,22 @@ void refresh_grid_groups(hpmc_state* st) {
     }
 }
 
-// Replace replica r's box description (host and device) and re-capture.
+// Replace replica r's box description (host and device).  The kernels read
+// the descriptor from device memory, so the captured sweep stays valid
+// unless a launch size changed; only then is it captured again.
 int set_replica_box(hpmc_state* st, int r, const SysDev& S, const ReplicaHost& rh) {
     st->sys[r] = S;
     st->rep[r] = rh;
     int rc = check_hip(st, hipMemcpyAsync(st->ws.sys + r, &st->sys[r], sizeof(SysDev),
                                           hipMemcpyHostToDevice, st->stream));
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    std::vector<BatchGroup> before = st->groups;
     refresh_grid_groups(st);
-    if (!rc) capture_graph(st);
+    bool same = before.size() == st->groups.size();
+    for (size_t i = 0; same && i < before.size(); ++i)
+        same = before[i].rounds_max == st->groups[i].rounds_max &&
+               before[i].nc_max == st->groups[i].nc_max && before[i].n_act_max == st->groups[i].n_act_max;
+    if (!rc && !same) capture_graph(st);
     return rc;
 }
 
