@@ -11,13 +11,17 @@ moves are counted on the device (attempted moves, cell rejects included).
 
 Prints one JSON line.  Extra fields: the other three precision x batching
 combinations, the re-checked pair fraction, a roofline object for the
-timed kernel and the reference oracle timed on one host core.
+timed kernel and the reference oracle timed on one host core.  Each
+configuration is timed --repeats times (default 5) over --steps sweeps;
+`value` is the first of these runs and every run's rate is listed beside the
+median.
 """
 import argparse
 import json
 import math
 import os
 import platform
+import statistics
 import subprocess
 import sys
 import time
@@ -276,6 +280,8 @@ def main():
     ap.add_argument("--queue", default="wave", choices=["wave", "register", "global"],
                     help="schedule of the full overlap tests (register/global: grid path, "
                          "single-system runs only; for comparison with the default)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of --steps sweeps per configuration (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -283,6 +289,8 @@ def main():
     ap.add_argument("--only", default=None,
                     help="comma list of runs: mixed_batched,fp64_single,fp64_batched,mixed_single")
     args = ap.parse_args()
+    if args.repeats < 1:
+        ap.error("--repeats must be at least 1")
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -321,6 +329,12 @@ def main():
         system = make_system(wl, precision, path, batched, args.queue)
         tuned = system.autotune(trial_sweeps=8) if not args.no_autotune else None
         ms, diff = timed_run(system, args.steps, args.warmup, args.seed)
+        # further timed runs of the same length continue the chain; the line's
+        # value stays the first one, the median of all is reported beside it
+        rep = [diff["attempted"] / (ms * 1e-3)]
+        for _ in range(args.repeats - 1):
+            ms_k, diff_k = timed_run(system, args.steps, 0, args.seed)
+            rep.append(diff_k["attempted"] / (ms_k * 1e-3))
         n_launch = (math.ceil(args.steps / PERSISTENT_SWEEPS_PER_LAUNCH) if path == "persistent"
                     else None)
         results[name] = {
@@ -337,6 +351,8 @@ def main():
             "autotuned": tuned,
             "graph": system.uses_graph,
             "ms_total": ms,
+            "repeats": rep,
+            "median_of_repeats": statistics.median(rep),
         }
         del system
         torch.cuda.synchronize()
