@@ -27,7 +27,10 @@
  * Streams and threads: a state is bound to one HIP stream (passed as void*,
  * NULL = the default stream) and is not thread safe.  Distinct states on
  * distinct streams are independent.  hpmc_sweep is asynchronous; calls that
- * return data to the host synchronise the stream.
+ * return data to the host synchronise the stream.  A batch of several shape
+ * kinds on the persistent path runs the kinds' launches on private streams
+ * of the state, forked from and joined back to its stream, so work enqueued
+ * on that stream afterwards still sees every sweep complete.
  *
  * Errors: every call returns HPMC_OK (0) or a negative HPMC_ERR_* code and
  * never throws.  Device faults surface at the next synchronising call.

@@ -38,6 +38,12 @@ struct hpmc_state {
     int flags = 0;
     size_t pos_total = 0, ori_total = 0;  // doubles in the caller's arrays
     hipStream_t cap_stream = nullptr;     // private stream used only for capture
+    // persistent path with several launch groups: private streams that run
+    // the groups after the first beside it, forked from and joined back to
+    // the stream a sweep is enqueued on
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_done;
+    hipEvent_t fork = nullptr;
     std::vector<hpmc_species> spec_host;  // species as given (vertex pointer cleared)
     std::vector<int32_t> list;            // host copy of the launch groups' replica list
     std::vector<SysDev> sys_saved;        // box before the last hpmc_scale_box, per replica
@@ -296,6 +302,10 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
                                                                        rep[r].ncells_cap, sys[r].N, lv));
             }
             if (g.count == 0) continue;
+            // largest replicas first: work-groups start in list order, so the
+            // longest ones do not wait behind short ones for a compute unit
+            std::stable_sort(list.begin() + g.first, list.end(),
+                             [&](int32_t x, int32_t y) { return sys[x].N > sys[y].N; });
             g.resident = 0;
             for (int lv = (kind == kDisk ? 1 : 2); lv >= 1; --lv)
                 if (need[lv] <= lds_limit) {
@@ -399,11 +409,35 @@ int group_precision(const hpmc_state* st, const BatchGroup& g) {
 int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
     int rc = HPMC_OK;
     if (st->path == HPMC_PATH_PERSISTENT) {
-        for (const BatchGroup& g : st->groups) {
+        // the groups (one per shape kind) share no replica, so with side
+        // streams they run concurrently: the compute units that the small
+        // replicas of one kind leave idle take work of another kind
+        const size_t ng = st->groups.size();
+        const bool fork = ng > 1 && st->side.size() + 1 == ng;
+        size_t forked = 0;  // side streams that wait on the fork event
+        if (fork) {
+            rc = check_hip(st, hipEventRecord(st->fork, s));
+            for (size_t k = 1; !rc && k < ng; ++k) {
+                rc = check_hip(st, hipStreamWaitEvent(st->side[k - 1], st->fork, 0));
+                if (rc) break;
+                forked = k;
+                const BatchGroup& g = st->groups[k];
+                rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g),
+                                                     chunk, false, st->side[k - 1]));
+            }
+        }
+        for (size_t k = 0; !rc && k < (fork ? 1 : ng); ++k) {
+            const BatchGroup& g = st->groups[k];
             rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), chunk,
                                                  false, s));
-            if (rc) return rc;
         }
+        // every forked stream joins back, also after a failed launch
+        for (size_t k = 1; k <= forked; ++k) {
+            int rj = check_hip(st, hipEventRecord(st->side_done[k - 1], st->side[k - 1]));
+            if (!rj) rj = check_hip(st, hipStreamWaitEvent(s, st->side_done[k - 1], 0));
+            if (!rc) rc = rj;
+        }
+        if (rc) return rc;
         return check_hip(st, advance_clock(st->ws, chunk, s));
     }
     for (const BatchGroup& g : st->groups) {
@@ -425,6 +459,37 @@ uint32_t sweep_unit(const hpmc_state* st) {
 void drop_graph(hpmc_state* st) {
     if (st->graph) (void)hipGraphExecDestroy(st->graph);
     st->graph = nullptr;
+}
+
+void drop_side_streams(hpmc_state* st) {
+    for (hipStream_t q : st->side) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : st->side_done) (void)hipEventDestroy(e);
+    if (st->fork) (void)hipEventDestroy(st->fork);
+    st->side.clear();
+    st->side_done.clear();
+    st->fork = nullptr;
+}
+
+// Side streams (default priority) and events of a persistent state with
+// more than one launch group.  Failure leaves the groups on one stream, one
+// after another (not an error).
+void make_side_streams(hpmc_state* st) {
+    drop_side_streams(st);
+    if (st->path != HPMC_PATH_PERSISTENT || st->groups.size() < 2) return;
+    bool ok = hipEventCreateWithFlags(&st->fork, hipEventDisableTiming) == hipSuccess;
+    if (!ok) st->fork = nullptr;
+    for (size_t k = 1; ok && k < st->groups.size(); ++k) {
+        hipStream_t q = nullptr;
+        hipEvent_t e = nullptr;
+        ok = hipStreamCreateWithFlags(&q, hipStreamNonBlocking) == hipSuccess;
+        if (ok) st->side.push_back(q);
+        ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (ok) st->side_done.push_back(e);
+    }
+    if (!ok) {
+        drop_side_streams(st);
+        (void)hipGetLastError();
+    }
 }
 
 // Capture one sweep unit into a hipGraph on the private stream.  Failure
@@ -699,6 +764,7 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
             for (uint64_t c : counts)
                 if (c != 0) rc = HPMC_ERR_INITIAL_OVERLAP;
     }
+    if (!rc) make_side_streams(st);
     if (!rc) capture_graph(st);
     if (rc) {
         hpmc_destroy(st);
@@ -913,6 +979,7 @@ void hpmc_destroy(hpmc_state* st) {
     if (st == nullptr) return;
     (void)hipStreamSynchronize(st->stream);
     drop_graph(st);
+    drop_side_streams(st);
     if (st->cap_stream) (void)hipStreamDestroy(st->cap_stream);
     delete st;
 }

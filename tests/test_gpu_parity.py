@@ -173,6 +173,33 @@ def test_batched_heterogeneous_replicas(path):
     assert np.all(system.count_overlaps() == 0)
 
 
+@pytest.mark.parametrize("graphs", [True, False])
+def test_three_kind_groups_on_their_own_streams(graphs):
+    """Disk, pentagon and cube replicas on the persistent path: one launch
+    per kind, the later kinds on side streams beside the first, in the
+    captured graph (two whole 64-sweep chunks) and in direct launches (the
+    remaining sweeps); every replica equals the oracle with its own replica
+    word, and the replicas are launched largest first."""
+    batch = inputs.screening_batch(n_replicas=4, seed=2031, n_lo=64, n_hi=600)
+    batch.append(inputs.workload_cubes(216, 0.45))
+    announce(f"kind groups graphs={graphs} N={[b[1] for b in batch]}")
+    system = _system([b[0] for b in batch], [b[1] for b in batch], [b[2] for b in batch],
+                     [b[3] for b in batch], [b[4] for b in batch], precision="mixed",
+                     path="persistent", graphs=graphs)
+    assert system.uses_graph == graphs
+    n_sweeps = 2 * 64 + 3
+    system.sweep(n_sweeps, seed=19)
+    stats = system.stats()
+    for r, (sp, N, L, pos, orient) in enumerate(batch):
+        ref_pos, ref_ori = pos.copy(), orient.copy()
+        ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=19, n_sweeps=n_sweeps, replica=r)
+        assert [stats[r][k] for k in PARITY] == [int(x) for x in ref_stats], r
+        assert np.array_equal(system.positions(r), ref_pos), r
+        if sp["shape"] != "disk":
+            assert np.array_equal(system.orientations(r), ref_ori), r
+    assert np.all(system.count_overlaps() == 0)
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("shape", ["pentagons", "cubes", "dodeca"])
 def test_every_lane_count_equals_the_oracle(shape, lanes):
