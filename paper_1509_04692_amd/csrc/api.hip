@@ -288,7 +288,10 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     groups.clear();
     list.clear();
     if (path == HPMC_PATH_PERSISTENT) {
-        for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
+        // kinds with the costlier overlap test first: their launch is captured
+        // first and takes the compute units first, and the cheaper kinds'
+        // work-groups fill in as they free up
+        for (int kind = kPolyhedron; kind >= kDisk; --kind) {
             BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}};
             const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
             size_t need[3] = {0, 0, 0};
@@ -414,22 +417,21 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
         // replicas of one kind leave idle take work of another kind
         const size_t ng = st->groups.size();
         const bool fork = ng > 1 && st->side.size() + 1 == ng;
+        // the groups are captured in their order (costliest kind first)
         size_t forked = 0;  // side streams that wait on the fork event
-        if (fork) {
-            rc = check_hip(st, hipEventRecord(st->fork, s));
-            for (size_t k = 1; !rc && k < ng; ++k) {
-                rc = check_hip(st, hipStreamWaitEvent(st->side[k - 1], st->fork, 0));
-                if (rc) break;
-                forked = k;
-                const BatchGroup& g = st->groups[k];
-                rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g),
-                                                     chunk, false, st->side[k - 1]));
-            }
-        }
+        if (fork) rc = check_hip(st, hipEventRecord(st->fork, s));
         for (size_t k = 0; !rc && k < (fork ? 1 : ng); ++k) {
             const BatchGroup& g = st->groups[k];
             rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), chunk,
                                                  false, s));
+        }
+        for (size_t k = 1; fork && !rc && k < ng; ++k) {
+            rc = check_hip(st, hipStreamWaitEvent(st->side[k - 1], st->fork, 0));
+            if (rc) break;
+            forked = k;
+            const BatchGroup& g = st->groups[k];
+            rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g),
+                                                 chunk, false, st->side[k - 1]));
         }
         // every forked stream joins back, also after a failed launch
         for (size_t k = 1; k <= forked; ++k) {
