@@ -267,7 +267,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         slot_total += sys[r].N;
         part_total += ((int64_t)rep[r].ncells_cap + kScanTile - 1) / kScanTile;
         const int ncomp_r = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
-        const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, rep[r].ncells_cap, sys[r].N, 0);
+        const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, rep[r].ncells_cap, sys[r].N, 0, kBatchBlock);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
         const int half = sys[r].n / 2;
         const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
@@ -294,6 +294,14 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         for (int kind = kPolyhedron; kind >= kDisk; --kind) {
             BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}};
             const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
+            int64_t n_max = 0, n_act_max = 0;
+            for (int r = 0; r < R; ++r) {
+                if (spc[r].kind != kind) continue;
+                const int64_t half = sys[r].n / 2;
+                n_max = std::max<int64_t>(n_max, sys[r].N);
+                n_act_max = std::max<int64_t>(n_act_max, sys[r].dim == 3 ? half * half * half : half * half);
+            }
+            g.block = persistent_block(n_act_max, n_max);
             size_t need[3] = {0, 0, 0};
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
@@ -301,8 +309,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
                 g.count++;
                 g.nv = (g.nv == -1 || g.nv == spc[r].nv) ? spc[r].nv : 0;
                 for (int lv = 0; lv < 3; ++lv)
-                    need[lv] = std::max(need[lv], persistent_lds_bytes(sys[r].dim, ncomp,
-                                                                       rep[r].ncells_cap, sys[r].N, lv));
+                    need[lv] = std::max(need[lv], persistent_lds_bytes(sys[r].dim, ncomp, rep[r].ncells_cap,
+                                                                       sys[r].N, lv, g.block));
             }
             if (g.count == 0) continue;
             // largest replicas first: work-groups start in list order, so the

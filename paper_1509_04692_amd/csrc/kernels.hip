@@ -828,7 +828,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         // counting sort of the shifted grid (ascending tags within a cell); the
         // first kOwn particles of each thread keep their cell and binary32
         // shifted-frame coordinates in registers between the passes
-        constexpr int kOwn = 4;
+        constexpr int kOwn = kBatchOwn;
         uint32_t own_cell[kOwn];
         float own_y[kOwn][3];
         uint32_t* count = uni;
@@ -929,8 +929,8 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
-size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res) {
-    return batch_layout(dim, ncomp, N, ncells, kBatchBlock / 64, res).total;
+size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res, int block) {
+    return batch_layout(dim, ncomp, N, ncells, block / 64, res).total;
 }
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream) {
@@ -1084,15 +1084,15 @@ hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, do
 }
 
 template <int KIND, int PREC, int RES, int NV>
-static hipError_t launch_batch(const Workspace& ws, const int32_t* list, int n, size_t lds,
+static hipError_t launch_batch(const Workspace& ws, const int32_t* list, int n, int block, size_t lds,
                                double* pos, double* orient, uint32_t n_sweeps, bool prepare,
                                hipStream_t stream) {
     auto kern = k_batch<KIND, PREC, RES, NV>;
     if (prepare)  // raise the dynamic-LDS limit (not a stream operation; done before capture)
         return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds);
-    kern<<<n, kBatchBlock, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats,
-                                          ws.clock, n_sweeps);
+    if (block < 64 || block > kBatchBlock || block % 64 != 0) return hipErrorInvalidValue;
+    kern<<<n, block, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats, ws.clock, n_sweeps);
     return hipGetLastError();
 }
 
@@ -1102,12 +1102,12 @@ static hipError_t launch_batch_res(const Workspace& ws, const BatchGroup& g, dou
                                    hipStream_t stream) {
     const int32_t* list = ws.batch_list + g.first;
     if (g.resident >= 2 && KIND != kDisk)
-        return launch_batch<KIND, PREC, 2, NV>(ws, list, g.count, g.lds_bytes, pos, orient,
+        return launch_batch<KIND, PREC, 2, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
                                                n_sweeps, prepare, stream);
     if (g.resident >= 1)
-        return launch_batch<KIND, PREC, 1, NV>(ws, list, g.count, g.lds_bytes, pos, orient,
+        return launch_batch<KIND, PREC, 1, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
                                                n_sweeps, prepare, stream);
-    return launch_batch<KIND, PREC, 0, NV>(ws, list, g.count, g.lds_bytes, pos, orient,
+    return launch_batch<KIND, PREC, 0, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
                                            n_sweeps, prepare, stream);
 }
 

@@ -9,7 +9,20 @@
 
 namespace hpmc {
 
-constexpr int kBatchBlock = 1024;  // lanes per persistent work-group (16 waves)
+constexpr int kBatchBlock = 1024;  // most lanes of a persistent work-group (16 waves)
+constexpr int kBatchOwn = 4;       // particles per lane the persistent build keeps in registers
+
+// Lanes of a persistent work-group for replicas of at most n_max particles
+// and n_act_max active cells per colour: one 64-cell tile per wave covers a
+// pass, and every particle of the cell-list build stays in registers; a
+// multiple of 64 from 64 to kBatchBlock.  Smaller replicas take fewer lanes,
+// so more of their work-groups share a compute unit.
+inline int persistent_block(int64_t n_act_max, int64_t n_max) {
+    int64_t need = n_act_max > (n_max + kBatchOwn - 1) / kBatchOwn ? n_act_max
+                                                                   : (n_max + kBatchOwn - 1) / kBatchOwn;
+    need = (need + 63) / 64 * 64;
+    return need < 64 ? 64 : (need > kBatchBlock ? kBatchBlock : (int)need);
+}
 
 constexpr int64_t kGqPerSlot = 8;  // queue entries reserved per particle (2^dim, dim <= 3)
 
@@ -72,6 +85,7 @@ struct BatchGroup {
     // grid path: largest replica of the group and the lanes per active cell
     int32_t dim, lanes, rounds_max;
     int64_t n_max, nc_max, n_act_max;
+    int32_t block = kBatchBlock;  // persistent: lanes per work-group
 };
 
 constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
@@ -129,6 +143,6 @@ hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipSt
 hipError_t scale_box(double* pos, int64_t n, double k, double L_new, hipStream_t stream);
 
 // Dynamic LDS of a persistent work-group (positions resident or not).
-size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res);
+size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res, int block);
 
 }  // namespace hpmc
