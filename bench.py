@@ -10,8 +10,9 @@ replica.  Inputs are resident on the GPU before the timed region; trial
 moves are counted on the device (attempted moves, cell rejects included).
 
 Prints one JSON line.  Extra fields: the other three precision x batching
-combinations, the re-checked pair fraction, a roofline object for the
-timed kernel and the reference oracle timed on one host core.  Each
+combinations, the re-checked pair fraction, the overlap count of the state
+each timed run left, the sweeps that replayed the captured graph, a roofline
+object for the timed kernel and the reference oracle timed on the host.  Each
 configuration is timed --repeats times (default 5) over --steps sweeps;
 `value` is the first of these runs and every run's rate is listed beside the
 median.
@@ -30,10 +31,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# MI355X's published dense FP64 vector peak (an FMA counts as two flops).
+FP64_PEAK_TFLOPS = 78.6
 # One VALU operation per lane per clock: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
-# (non-packed fp32 and fp64 run at this rate; an FMA counts as one operation,
-# i.e. this is half the 78.6 TFLOP/s fp64 figure, which counts FMA as two).
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# (non-packed fp32 and fp64 issue at this rate): half the published figure,
+# the ceiling for code whose operations are not FMAs.  Reported beside it.
+VALU_ISSUE_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBPS = 8000.0
 PERSISTENT_SWEEPS_PER_LAUNCH = 64  # HPMC_PERSISTENT_SWEEPS_PER_LAUNCH
 
 
@@ -123,11 +127,14 @@ def make_system(wl, precision, path, batched, queue="wave"):
 
 def timed_run(system, steps, warmup, seed):
     """Warm up, then time exactly `steps` sweeps with HIP events on the
-    library's stream, synchronised on both sides."""
+    library's stream, synchronised on both sides.  Returns the time, the
+    counter differences and the sweeps of the timed call that replayed the
+    captured graph."""
     import torch
     system.sweep(warmup, seed)
     torch.cuda.synchronize()
     before = system.stats()
+    g0 = system.graph_sweeps
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(system.stream):
         start.record(system.stream)
@@ -137,6 +144,7 @@ def timed_run(system, steps, warmup, seed):
     after = system.stats()
     ms = start.elapsed_time(end)
     diff = {k: sum(a[k] - b[k] for a, b in zip(after, before)) for k in after[0] if k != "sweeps"}
+    diff["graph_sweeps"] = system.graph_sweeps - g0
     return ms, diff
 
 
@@ -241,20 +249,23 @@ def _csrc_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_sweeps):
-    """HBM bytes per launch of the timed kernel from the rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs recorded under profiles/, each scaled by the same counter's
-    reading for a plain copy of known size; None when the kernel sources
-    changed since the counters were taken."""
+def recorded_counters():
+    """The rocprofv3 counters recorded under profiles/ for the headline kernel
+    (FETCH_SIZE / WRITE_SIZE over one launch of `launch_sweeps` sweeps, each
+    scaled by the same counter's reading for a plain copy of known size;
+    VALUBusy, VALUUtilization, waves per SIMD), or None when the kernel
+    sources changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "traffic_k_batch_pentagons.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except OSError:
         return None
-    if d.get("csrc_sha256") != _csrc_hash() or d.get("launch_sweeps") != kernel_sweeps:
+    if d.get("csrc_sha256") != _csrc_hash():
         return None
-    return (d["fetch_kib"] * d["fetch_factor"] + d["write_kib"] * d["write_factor"]) * 1024.0
+    d["bytes_per_sweep"] = ((d["fetch_kib"] * d["fetch_factor"] + d["write_kib"] * d["write_factor"])
+                            * 1024.0 / d["launch_sweeps"])
+    return d
 
 
 def _device_info():
@@ -271,7 +282,7 @@ def main():
         return 0
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1024, help="timed sweeps (multiple of 64: whole launches)")
+    ap.add_argument("--steps", type=int, default=1024, help="timed sweeps (64 per persistent launch, a remainder as one shorter launch)")
     ap.add_argument("--warmup", type=int, default=128, help="untimed sweeps first")
     ap.add_argument("--workload", default="pentagons",
                     choices=["pentagons", "pentagons676", "disks", "cubes", "trunc_oct", "dodecahedra",
@@ -286,6 +297,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer once (calibrates HBM byte counters)")
+    ap.add_argument("--phase-trace", action="store_true",
+                    help="with HPMC_LIBRARY=<lib/libhpmc_trace.so>: report where each kernel's "
+                         "waves spend their cycles over the timed runs (the clock reads slow the "
+                         "kernels: not a timing run)")
     ap.add_argument("--only", default=None,
                     help="comma list of runs: mixed_batched,fp64_single,fp64_batched,mixed_single")
     args = ap.parse_args()
@@ -328,13 +343,29 @@ def main():
         path = "persistent" if batched else "grid"
         system = make_system(wl, precision, path, batched, args.queue)
         tuned = system.autotune(trial_sweeps=8) if not args.no_autotune else None
-        ms, diff = timed_run(system, args.steps, args.warmup, args.seed)
+        if args.phase_trace:
+            from paper_1509_04692_amd.system import phase_trace
+            system.sweep(args.warmup, args.seed)
+            phase_trace(reset=True)
+        ms, diff = timed_run(system, args.steps, 0 if args.phase_trace else args.warmup, args.seed)
         # further timed runs of the same length continue the chain; the line's
         # value stays the first one, the median of all is reported beside it
         rep = [diff["attempted"] / (ms * 1e-3)]
         for _ in range(args.repeats - 1):
             ms_k, diff_k = timed_run(system, args.steps, 0, args.seed)
             rep.append(diff_k["attempted"] / (ms_k * 1e-3))
+        trace = None
+        if args.phase_trace:
+            trace = {}
+            for kern, d in phase_trace(reset=True).items():
+                total = sum(v for k, v in d.items() if k != "waves")
+                if d["waves"]:
+                    trace[kern] = {"waves": d["waves"], "cycles_per_wave": total / d["waves"],
+                                   "fractions": {k: v / total for k, v in d.items() if k != "waves"}}
+        # the state the timed sweeps left, checked outside the timed region
+        overlaps = int(system.count_overlaps().sum())
+        if overlaps:
+            print(f"# {name}: {overlaps} overlapping pairs after the timed sweeps", file=sys.stderr)
         n_launch = (math.ceil(args.steps / PERSISTENT_SWEEPS_PER_LAUNCH) if path == "persistent"
                     else None)
         results[name] = {
@@ -350,6 +381,9 @@ def main():
             "launches": n_launch,
             "autotuned": tuned,
             "graph": system.uses_graph,
+            "graph_replayed_sweeps": diff["graph_sweeps"],
+            "phase_trace": trace,
+            "overlaps_after": overlaps,
             "ms_total": ms,
             "repeats": rep,
             "median_of_repeats": statistics.median(rep),
@@ -373,14 +407,29 @@ def main():
             launch_s = h["ms_total"] * 1e-3
             ops_per_launch = opm * h["moves"]
         achieved = ops_per_launch / launch_s / 1e12
-        traffic = None
+        traffic, rec = None, None
         if head == "mixed_batched" and args.workload == "pentagons" and h["launches"]:
-            if args.steps % PERSISTENT_SWEEPS_PER_LAUNCH == 0:
-                traffic = measured_traffic(PERSISTENT_SWEEPS_PER_LAUNCH)
-        roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                    "traffic_unit": "bytes per launch",
-                    "ops_per_move": opm, "kernel": "k_batch" if h["launches"] else "k_update",
+            rec = recorded_counters()
+        hbm = None
+        if rec is not None:
+            # counters of a recorded launch, per sweep, times the sweeps of an
+            # average timed launch
+            traffic = rec["bytes_per_sweep"] * args.steps / h["launches"]
+            gbps = traffic / launch_s / 1e9
+            hbm = {"achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                   "bytes_per_sweep": rec["bytes_per_sweep"],
+                   "recorded_launch_sweeps": rec["launch_sweeps"]}
+        roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (recorded per-sweep counters x sweeps per launch)",
+                    "issue_rate": {"peak": VALU_ISSUE_TOPS, "unit": "T VALU op/s (one per lane per clock)",
+                                   "frac": achieved / VALU_ISSUE_TOPS},
+                    "hbm": hbm,
+                    "valu_busy": rec.get("valu_busy") if rec else None,
+                    "valu_utilization": rec.get("valu_utilization") if rec else None,
+                    "waves_per_simd": rec.get("waves_per_simd") if rec else None,
+                    "ops_per_move": opm, "ops_counted": "every + - * / sqrt rint min max compare, one each",
+                    "kernel": "k_batch" if h["launches"] else "k_update",
                     "avg_launch_ms": launch_s * 1e3, "events_per_move": ev_per_move,
                     "events_counted_sweeps": n_count}
     line = {

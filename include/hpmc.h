@@ -54,8 +54,16 @@ extern "C" {
 #define HPMC_ERR_SWEEP_OVERFLOW (-6)      /* sweep counter would reach 2^32 */
 #define HPMC_ERR_UNSUPPORTED (-7)         /* valid request the library does not support */
 
-/* The persistent path launches one kernel per this many sweeps. */
+/* The persistent path launches one kernel per this many sweeps (a call of
+ * n sweeps: n / 64 such launches, then one launch of the n % 64 left). */
 #define HPMC_PERSISTENT_SWEEPS_PER_LAUNCH 64
+
+/* Largest rotation size a (radians) of a polygon species.  The 2D move
+ * rotates the unit complex orientation by cos/sin polynomials truncated after
+ * the delta^16 / delta^15 terms and never renormalises it; below this bound
+ * the first dropped term (delta^17 / 17!) is under 2^-53, so |z| drifts only
+ * by rounding.  Larger a: HPMC_ERR_INVALID_ARG. */
+#define HPMC_MAX_POLYGON_ROTATION 0.75
 
 /* hpmc_init_args.flags */
 #define HPMC_FLAG_NO_GRAPH 1 /* launch kernels directly instead of replaying a hipGraph */
@@ -101,7 +109,8 @@ typedef struct {
     const double *verts;  /* host, n_verts x dim row-major; NULL for disks */
     double diameter;      /* disks */
     double d;             /* translation: each component uniform in [-d, d] */
-    double a;             /* rotation: 2D angle uniform in [-a, a]; 3D dq = (1, v),
+    double a;             /* rotation: 2D angle uniform in [-a, a], a at most
+                             HPMC_MAX_POLYGON_ROTATION; 3D dq = (1, v),
                              v uniform in [-a, a]^3, renormalised */
     double p_rot;         /* probability that a move is a rotation (0 for disks) */
     int32_t rounds;       /* colour rounds per sweep; 0 = max(1, round(N / cells)) */
@@ -199,6 +208,22 @@ int hpmc_scale_box(hpmc_state *st, int32_t replica, double L_new, uint64_t *over
  * to undo.  Synchronising. */
 int hpmc_restore_box(hpmc_state *st, int32_t replica);
 
+/* One isotropic volume move of replica r in the isobaric ensemble (Sec. 1:
+ * the paper samples NVT and NPT; the move is the textbook one for hard
+ * particles).  With V = L^dim (pow) and the caller's uniforms u1, u2 in
+ * [0, 1): dV = delta_v (2 u1 - 1), V' = V + dV, L' = V'^(1/dim) (pow).  The
+ * move is rejected, leaving the replica unchanged, when V' <= 0, L' > L_max,
+ * the box L' has fewer than 4 cells per side, or dV < 0 and the scaled state
+ * (hpmc_scale_box) has an overlapping pair; otherwise it is accepted iff
+ * arg >= 0 or u2 < exp(arg), arg = -beta_p dV + N log(V' / V) (beta_p =
+ * pressure / kT).  *accepted (host) receives 1 or 0 and *L_after (host, may
+ * be NULL) the box side afterwards.  An accepted move leaves the previous box
+ * restorable with hpmc_restore_box.  HPMC_ERR_INVALID_ARG for u1 or u2
+ * outside [0, 1), a non-finite beta_p or a negative or non-finite delta_v.
+ * Synchronising. */
+int hpmc_volume_move(hpmc_state *st, int32_t replica, double u1, double u2, double beta_p,
+                     double delta_v, int32_t *accepted, double *L_after);
+
 /* Volume-perturbation counts of one replica, the sampling behind the
  * pressure of particles with shape (Sec. 4): out[b] = number of unordered
  * pairs i < k that overlap (circumsphere test, then the full binary64 test)
@@ -249,7 +274,22 @@ int hpmc_replica_info(hpmc_state *st, int32_t r, int32_t *cells_per_side, int32_
 /* 1 if sweeps replay a captured hipGraph, 0 if kernels are launched directly. */
 int hpmc_uses_graph(hpmc_state *st);
 
-/* The hipError_t of the last failed HIP call of this state (0 if none). */
+/* Sweeps run since hpmc_init by replaying the captured hipGraph (the rest ran
+ * as direct launches: HPMC_FLAG_NO_GRAPH, or a failed capture or replay). */
+int hpmc_graph_sweeps(hpmc_state *st, uint64_t *out);
+
+/* Per-wave phase clock of a trace build (compiled with -DHPMC_TRACE; the
+ * normal build returns HPMC_ERR_UNSUPPORTED).  out (host, n >= 16 words)
+ * receives, for the persistent batch kernel and then the grid path's colour
+ * pass, the shader-clock cycles that all their waves together spent in each
+ * of 7 phases -- cell-list build, trial move, pre-filter scan, queued full
+ * tests, write-back, waiting at the barrier after a pass, other -- followed
+ * by the number of waves, summed over every launch since the last reset.
+ * The device is synchronised first; reset != 0 clears the totals. */
+int hpmc_phase_trace(uint64_t *out, int32_t n, int32_t reset);
+
+/* The hipError_t of the last failed HIP call of this state (0 if none); with
+ * st = NULL, that of the last hpmc_init that failed in a HIP call. */
 int hpmc_last_hip_error(hpmc_state *st);
 
 void hpmc_destroy(hpmc_state *st);

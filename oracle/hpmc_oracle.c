@@ -793,7 +793,11 @@ static int propose(const or_species *sp, const shape_t *sh, const grid_t *g, con
         for (int a = 0; a < 3; ++a)
             dq[1 + a] = sp->a * (2.0 * or_u01(m[1 + a]) - 1.0);
         double p[4];
+#ifdef ORACLE_PLANT_LEFT_ROTATION
+        quat_mul(dq, q, p);
+#else
         quat_mul(q, dq, p);
+#endif
         double nrm = sqrt(((p[0] * p[0] + p[1] * p[1]) + p[2] * p[2]) + p[3] * p[3]);
         for (int k = 0; k < 4; ++k)
             qn[k] = p[k] / nrm;

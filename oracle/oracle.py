@@ -289,8 +289,9 @@ def npt_cycles(sp, L, pos, orient, seed, uniforms, sweeps_per_cycle, beta_p, del
     the uniforms (u1, u2) of that cycle.  The move is rejected if V' <= 0,
     L' = V'^(1/dim) exceeds L_max or gives fewer than 4 cells per side, or
     (when shrinking) the scaled state has an overlapping pair; otherwise it
-    is accepted when u2 < exp(-beta_p dV + N ln(V'/V)) (Frenkel & Smit's NPT
-    volume move for hard particles).  pos/orient are updated in place;
+    is accepted with probability min(1, exp(arg)), arg = -beta_p dV +
+    N ln(V'/V) (Frenkel & Smit's NPT volume move for hard particles): since
+    u2 < 1, arg >= 0 always accepts, else u2 < exp(arg) decides.  pos/orient are updated in place;
     returns (L, sweep stats, accepted box moves)."""
     dim, N = sp["dim"], pos.shape[1]
     stats = np.zeros(N_STATS, dtype=np.int64)
@@ -314,7 +315,8 @@ def npt_cycles(sp, L, pos, orient, seed, uniforms, sweeps_per_cycle, beta_p, del
         scale_positions(trial, L, L2, lib=lib)
         if dV < 0.0 and count_overlaps(sp, L2, trial, orient, lib=lib) > 0:
             continue
-        if not u2 < math.exp(-beta_p * dV + N * math.log(V2 / V)):
+        arg = -beta_p * dV + N * math.log(V2 / V)
+        if not (arg >= 0.0 or u2 < math.exp(arg)):
             continue
         pos[...] = trial
         L = L2

@@ -30,7 +30,8 @@ EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune", "
            "hpmc_count_overlaps", "hpmc_pair_histogram", "hpmc_scale_counts", "hpmc_scale_box",
            "hpmc_restore_box", "hpmc_get_stats", "hpmc_reset_stats",
            "hpmc_sync_to_canonical", "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info",
-           "hpmc_uses_graph", "hpmc_last_hip_error", "hpmc_destroy", "hpmc_strerror")
+           "hpmc_uses_graph", "hpmc_graph_sweeps", "hpmc_volume_move", "hpmc_last_hip_error",
+           "hpmc_destroy", "hpmc_strerror", "hpmc_phase_trace")
 FLAG_NO_GRAPH = 1
 QUEUE_FLAGS = {"wave": 0, "register": 2, "global": 4}  # HPMC_FLAG_*_QUEUE
 
@@ -84,12 +85,18 @@ class Stats(ctypes.Structure):
 _lib = None
 
 
+PHASES = ("build", "propose", "scan", "drain", "write", "barrier", "other")
+TRACED_KERNELS = ("k_batch", "k_update")
+
+
 def load(path=None):
-    """Load libhpmc.so; raises OSError if it has not been built."""
+    """Load libhpmc.so; raises OSError if it has not been built.  The
+    environment variable HPMC_LIBRARY names another build to load instead
+    (the phase-trace build, lib/libhpmc_trace.so)."""
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or LIB_PATH
+    p = path or os.environ.get("HPMC_LIBRARY") or LIB_PATH
     if not os.path.exists(p):
         raise OSError(f"{p} is missing: build it with python -m paper_1509_04692_amd.build")
     lib = ctypes.CDLL(p)
@@ -108,6 +115,11 @@ def load(path=None):
     lib.hpmc_scale_box.argtypes = [st, ctypes.c_int32, ctypes.c_double,
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_restore_box.argtypes = [st, ctypes.c_int32]
+    lib.hpmc_volume_move.argtypes = [st, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.hpmc_graph_sweeps.argtypes = [st, ctypes.POINTER(ctypes.c_uint64)]
+    lib.hpmc_phase_trace.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.c_int32]
     lib.hpmc_get_stats.argtypes = [st, ctypes.POINTER(Stats)]
     lib.hpmc_reset_stats.argtypes = [st]
     lib.hpmc_sync_to_canonical.argtypes = [st]

@@ -13,6 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libhpmc.so")
+# the same sources with the per-wave phase clock compiled in (-DHPMC_TRACE)
+TRACE_LIB_PATH = os.path.join(LIB_DIR, "libhpmc_trace.so")
 SOURCES = ["api.hip", "kernels.hip"]
 ARCH = "gfx950"
 
@@ -32,10 +34,14 @@ def hipcc_path():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build_library(verbose=True, extra_flags=()):
-    """Compile every HIP source into lib/libhpmc.so (always recompiles)."""
+def build_library(verbose=True, extra_flags=(), trace=False):
+    """Compile every HIP source into lib/libhpmc.so (always recompiles);
+    trace=True builds lib/libhpmc_trace.so with the phase clock."""
     os.makedirs(LIB_DIR, exist_ok=True)
-    tmp = LIB_PATH + ".tmp"
+    out = TRACE_LIB_PATH if trace else LIB_PATH
+    if trace:
+        extra_flags = (*extra_flags, "-DHPMC_TRACE")
+    tmp = out + ".tmp"
     cmd = [hipcc_path(), *HIPCC_FLAGS, *extra_flags, "-o", tmp,
            *[os.path.join(CSRC, s) for s in SOURCES]]
     if verbose:
@@ -43,10 +49,10 @@ def build_library(verbose=True, extra_flags=()):
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed to build libhpmc.so")
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        raise RuntimeError(f"hipcc failed to build {os.path.basename(out)}")
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    build_library()
+    build_library(trace="--trace" in sys.argv)

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -50,6 +51,7 @@ struct hpmc_state {
     std::vector<ReplicaHost> rep_saved;
     std::vector<uint8_t> box_saved;
     hipGraphExec_t graph = nullptr;       // one sweep (grid) / one chunk (persistent)
+    uint64_t graph_sweeps = 0;            // sweeps run by replaying `graph` since init
 };
 
 namespace {
@@ -85,6 +87,10 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
     P.dim = s.dim;
     if (!(s.d >= 0.0) || !(s.a >= 0.0) || !(s.p_rot >= 0.0) || !(s.p_rot <= 1.0))
         return HPMC_ERR_INVALID_ARG;
+    // the 2D rotation's sine and cosine are truncated series, and the unit
+    // complex orientation is never renormalised: angles are bounded so that
+    // the first dropped term stays below binary64 rounding (Sec. 2.1 move)
+    if (s.shape == HPMC_POLYGON && !(s.a <= HPMC_MAX_POLYGON_ROTATION)) return HPMC_ERR_INVALID_ARG;
     if (s.rounds < 0) return HPMC_ERR_INVALID_ARG;
     if (!(s.sweep_radius >= 0.0) || !std::isfinite(s.sweep_radius)) return HPMC_ERR_INVALID_ARG;
     if (s.sweep_radius > 0.0 && s.shape != HPMC_POLYHEDRON) return HPMC_ERR_INVALID_ARG;
@@ -202,6 +208,10 @@ struct Layout {
     size_t pos_total, ori_total;
 };
 
+// hipError_t of the last hpmc_init that failed in a HIP call (the state it
+// was building is gone by then).
+std::atomic<int> g_last_init_hip{0};
+
 // Queue mode from hpmc_init_args.flags; -1 when both variants are asked for.
 int queue_mode(int32_t flags) {
     const bool reg = (flags & HPMC_FLAG_REGISTER_QUEUE) != 0, glob = (flags & HPMC_FLAG_GLOBAL_QUEUE) != 0;
@@ -218,9 +228,10 @@ int choose_lanes_per_cell(int64_t n_act) {
     return g;
 }
 
+// backups = false leaves out the snapshot buffers of autotuning and box moves.
 int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<SysDev>& sys,
          std::vector<SpeciesDev>& spc, Layout& lay, int& path, std::vector<BatchGroup>& groups,
-         std::vector<int32_t>& list, size_t lds_limit) {
+         std::vector<int32_t>& list, size_t lds_limit, bool backups = true) {
     if (a == nullptr || a->n_replicas < 1 || a->species == nullptr || a->N == nullptr ||
         a->L == nullptr)
         return HPMC_ERR_INVALID_ARG;
@@ -380,9 +391,9 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     lay.clock = take(sizeof(Clock));
     lay.pos_total = (size_t)pos_off;
     lay.ori_total = (size_t)ori_off;
-    lay.backup_pos = take(8 * (size_t)pos_off);
-    lay.backup_ori = take(8 * (size_t)(ori_off > 0 ? ori_off : 1));
-    lay.backup_stats = take(sizeof(unsigned long long) * kStatsPerReplica * R);
+    lay.backup_pos = take(backups ? 8 * (size_t)pos_off : 0);
+    lay.backup_ori = take(backups ? 8 * (size_t)(ori_off > 0 ? ori_off : 1) : 0);
+    lay.backup_stats = take(backups ? sizeof(unsigned long long) * kStatsPerReplica * R : 0);
     const bool gq = queue == kQueueGlobal;
     lay.cell_total = cell_total;
     lay.gq_trial = take(gq ? 8 * 7 * (size_t)cell_total : 0);
@@ -415,9 +426,9 @@ int group_precision(const hpmc_state* st, const BatchGroup& g) {
     return (g.kind == kPolyhedron && st->walk64) ? HPMC_FP64 : st->precision;
 }
 
-// One sweep (grid path) or `chunk` sweeps (persistent path) of every replica
-// on stream s, ending with the device clock advanced accordingly.
-int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
+// One sweep (grid path) or the device clock's n sweeps (persistent path) of
+// every replica on stream s, ending with the device clock advanced by n.
+int enqueue_sweeps(hpmc_state* st, hipStream_t s) {
     int rc = HPMC_OK;
     if (st->path == HPMC_PATH_PERSISTENT) {
         // the groups (one per shape kind) share no replica, so with side
@@ -430,7 +441,7 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
         if (fork) rc = check_hip(st, hipEventRecord(st->fork, s));
         for (size_t k = 0; !rc && k < (fork ? 1 : ng); ++k) {
             const BatchGroup& g = st->groups[k];
-            rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), chunk,
+            rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g),
                                                  false, s));
         }
         for (size_t k = 1; fork && !rc && k < ng; ++k) {
@@ -439,7 +450,7 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
             forked = k;
             const BatchGroup& g = st->groups[k];
             rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g),
-                                                 chunk, false, st->side[k - 1]));
+                                                 false, st->side[k - 1]));
         }
         // every forked stream joins back, also after a failed launch
         for (size_t k = 1; k <= forked; ++k) {
@@ -448,7 +459,7 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
             if (!rc) rc = rj;
         }
         if (rc) return rc;
-        return check_hip(st, advance_clock(st->ws, chunk, s));
+        return check_hip(st, advance_clock(st->ws, s));
     }
     for (const BatchGroup& g : st->groups) {
         if (rc) break;
@@ -458,7 +469,7 @@ int enqueue_sweeps(hpmc_state* st, hipStream_t s, uint32_t chunk) {
             rc = check_hip(st, grid_passes(st->ws, g, st->pos, st->orient, group_precision(st, g),
                                            st->queue, s));
     }
-    if (!rc) rc = check_hip(st, advance_clock(st->ws, 1, s));
+    if (!rc) rc = check_hip(st, advance_clock(st->ws, s));
     return rc;
 }
 
@@ -519,7 +530,7 @@ void capture_graph(hpmc_state* st) {
         return;
     }
     const int last = st->last_hip;
-    const int rc = enqueue_sweeps(st, st->cap_stream, sweep_unit(st));
+    const int rc = enqueue_sweeps(st, st->cap_stream);
     const hipError_t ec = hipStreamEndCapture(st->cap_stream, &g);
     st->last_hip = last;
     if (rc == HPMC_OK && ec == hipSuccess && g != nullptr) {
@@ -570,7 +581,7 @@ int apply_config(hpmc_state* st, int cfg) {
             g.resident = std::min<int>(c, g.resident_max);
             g.lds_bytes = g.need[g.resident];
             const int rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient,
-                                                           group_precision(st, g), 0, true, st->stream));
+                                                           group_precision(st, g), true, st->stream));
             if (rc) return rc;
         }
     } else {
@@ -619,10 +630,16 @@ int set_replica_box(hpmc_state* st, int r, const SysDev& S, const ReplicaHost& r
 }
 
 int run_sweeps(hpmc_state* st, uint64_t n_sweeps, uint32_t k0, uint32_t k1) {
-    int rc = check_hip(st, set_clock(st->ws, (uint32_t)st->t, k0, k1, st->stream));
+    // a persistent launch runs the clock's n sweeps: whole chunks first, then
+    // the shorter remainder through the same captured launch
     const uint32_t unit = sweep_unit(st);
+    const uint32_t first = n_sweeps < unit ? (uint32_t)n_sweeps : unit;
+    int rc = check_hip(st, set_clock(st->ws, (uint32_t)st->t, k0, k1, first, st->stream));
     uint64_t done = 0;
-    while (!rc && done + unit <= n_sweeps) {
+    while (!rc && done < n_sweeps) {
+        const uint32_t len = n_sweeps - done < unit ? (uint32_t)(n_sweeps - done) : unit;
+        if (len != first) rc = check_hip(st, set_chunk(st->ws, len, st->stream));
+        if (rc) break;
         if (st->graph) {
             const hipError_t e = hipGraphLaunch(st->graph, st->stream);
             if (e != hipSuccess) {  // fall back to direct launches from here on
@@ -631,60 +648,35 @@ int run_sweeps(hpmc_state* st, uint64_t n_sweeps, uint32_t k0, uint32_t k1) {
                 st->flags |= HPMC_FLAG_NO_GRAPH;
                 continue;
             }
+            st->graph_sweeps += len;
         } else {
-            rc = enqueue_sweeps(st, st->stream, unit);
+            rc = enqueue_sweeps(st, st->stream);
         }
-        done += unit;
+        done += len;
     }
-    if (!rc && done < n_sweeps) rc = enqueue_sweeps(st, st->stream, (uint32_t)(n_sweeps - done));
     return rc;
 }
 
-}  // namespace
 
-extern "C" {
-
-int hpmc_workspace_bytes(const hpmc_init_args* args, size_t* out_bytes) {
-    if (out_bytes == nullptr) return HPMC_ERR_INVALID_ARG;
-    std::vector<ReplicaHost> rep;
-    std::vector<SysDev> sys;
-    std::vector<SpeciesDev> spc;
-    Layout lay{};
-    int path = 0;
-    std::vector<BatchGroup> groups;
-    std::vector<int32_t> list;
-    const int rc = plan(args, rep, sys, spc, lay, path, groups, list, device_lds_limit());
-    if (rc) return rc;
-    *out_bytes = lay.total;
+// The caller's particle buffers: positions always, orientations unless every
+// replica is a disk.
+int check_buffers(const hpmc_init_args* args, const std::vector<SpeciesDev>& spc) {
+    if (args->pos == nullptr) return HPMC_ERR_INVALID_ARG;
+    if (args->orient == nullptr)
+        for (const auto& sp : spc)
+            if (sp.kind != kDisk) return HPMC_ERR_INVALID_ARG;
     return HPMC_OK;
 }
 
-int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
-    if (out == nullptr) return HPMC_ERR_INVALID_ARG;
-    *out = nullptr;
-    hpmc_state* st = new (std::nothrow) hpmc_state();
-    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
-    Layout lay{};
-    std::vector<int32_t> list;
-    int rc = plan(args, st->rep, st->sys, st->spc, lay, st->path, st->groups, list,
-                  device_lds_limit());
-    if (rc == HPMC_OK && (args->pos == nullptr || args->workspace == nullptr)) rc = HPMC_ERR_INVALID_ARG;
-    if (rc == HPMC_OK && args->orient == nullptr) {
-        for (const auto& s : st->spc)
-            if (s.kind != kDisk) rc = HPMC_ERR_INVALID_ARG;
-    }
-    if (rc == HPMC_OK && ((uintptr_t)args->workspace % kAlign) != 0) rc = HPMC_ERR_INVALID_ARG;
-    if (rc == HPMC_OK && args->workspace_bytes < lay.total) rc = HPMC_ERR_WORKSPACE_TOO_SMALL;
-    if (rc) {
-        delete st;
-        return rc;
-    }
+// Point the state at the caller's arrays and carve its workspace (base) by
+// the layout.
+void bind_workspace(hpmc_state* st, const hpmc_init_args* args, const Layout& lay,
+                    const std::vector<int32_t>& list, char* base) {
     st->n_replicas = args->n_replicas;
     st->precision = args->precision;
     st->stream = (hipStream_t)args->stream;
     st->pos = args->pos;
     st->orient = args->orient ? args->orient : args->pos;  // never dereferenced for disks
-    char* base = (char*)args->workspace;
     st->ws.species = (SpeciesDev*)(base + lay.species);
     st->ws.sys = (SysDev*)(base + lay.sys);
     st->ws.stats = (unsigned long long*)(base + lay.stats);
@@ -723,16 +715,24 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
         q.count = (uint32_t*)(base + lay.gq_count);
         q.cell_total = lay.cell_total;
     }
+}
 
-    rc = check_hip(st, hipMemcpyAsync(st->ws.species, st->spc.data(),
-                                      sizeof(SpeciesDev) * st->n_replicas, hipMemcpyHostToDevice,
-                                      st->stream));
+// Copy the shape, grid and launch tables to the workspace, clear what the
+// kernels expect to start at zero (counters, cell histograms, queue
+// lengths), raise the persistent kernels' LDS limit, and check that every
+// position lies in [0, L) and every orientation is finite (before any cell
+// lookup).  Synchronises the stream.
+int upload_and_validate(hpmc_state* st, const Layout& lay) {
+    int rc = check_hip(st, hipMemcpyAsync(st->ws.species, st->spc.data(),
+                                          sizeof(SpeciesDev) * st->n_replicas, hipMemcpyHostToDevice,
+                                          st->stream));
     if (!rc)
         rc = check_hip(st, hipMemcpyAsync(st->ws.sys, st->sys.data(), sizeof(SysDev) * st->n_replicas,
                                           hipMemcpyHostToDevice, st->stream));
-    if (!rc && !list.empty())
-        rc = check_hip(st, hipMemcpyAsync(st->ws.batch_list, list.data(), sizeof(int32_t) * list.size(),
-                                          hipMemcpyHostToDevice, st->stream));
+    if (!rc && !st->list.empty())
+        rc = check_hip(st, hipMemcpyAsync(st->ws.batch_list, st->list.data(),
+                                          sizeof(int32_t) * st->list.size(), hipMemcpyHostToDevice,
+                                          st->stream));
     std::vector<int32_t> ident(st->n_replicas);
     for (int r = 0; r < st->n_replicas; ++r) ident[r] = r;
     if (!rc)
@@ -741,7 +741,7 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     if (!rc)
         rc = check_hip(st, fill_u64(st->ws.stats, 0ull, (size_t)kStatsPerReplica * st->n_replicas,
                                     st->stream));
-    if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, st->stream));
+    if (!rc) rc = check_hip(st, set_clock(st->ws, 0u, 0u, 0u, 1u, st->stream));
     if (!rc)  // cell histograms start at zero; every build leaves them so
         rc = check_hip(st, fill_u64((unsigned long long*)st->ws.count, 0ull,
                                     ((size_t)lay.cell_total + 1) / 2, st->stream));
@@ -750,23 +750,62 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
                                     st->stream));
     if (st->path == HPMC_PATH_PERSISTENT)
         for (const BatchGroup& g : st->groups)
-            if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g), 0,
+            if (!rc) rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient, group_precision(st, g),
                                                           true, st->stream));
     if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
-    if (!rc) {  // positions in [0, L) and finite orientations, before any cell lookup
-        std::vector<uint64_t> bad(st->n_replicas, 0);
-        rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
-        for (int r = 0; r < st->n_replicas && !rc; ++r)
-            rc = check_hip(st, validate_state(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
-        if (!rc)
-            rc = check_hip(st, hipMemcpyAsync(bad.data(), st->ws.overlap_out,
-                                              sizeof(uint64_t) * st->n_replicas,
-                                              hipMemcpyDeviceToHost, st->stream));
-        if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
-        if (!rc)
-            for (uint64_t b : bad)
-                if (b != 0) rc = HPMC_ERR_INVALID_ARG;
+    if (rc) return rc;
+    std::vector<uint64_t> bad(st->n_replicas, 0);
+    rc = check_hip(st, fill_u64(st->ws.overlap_out, 0ull, st->n_replicas, st->stream));
+    for (int r = 0; r < st->n_replicas && !rc; ++r)
+        rc = check_hip(st, validate_state(st->ws, st->rep[r], r, st->pos, st->orient, st->stream));
+    if (!rc)
+        rc = check_hip(st, hipMemcpyAsync(bad.data(), st->ws.overlap_out, sizeof(uint64_t) * st->n_replicas,
+                                          hipMemcpyDeviceToHost, st->stream));
+    if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+    if (!rc)
+        for (uint64_t b : bad)
+            if (b != 0) rc = HPMC_ERR_INVALID_ARG;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpmc_workspace_bytes(const hpmc_init_args* args, size_t* out_bytes) {
+    if (out_bytes == nullptr) return HPMC_ERR_INVALID_ARG;
+    std::vector<ReplicaHost> rep;
+    std::vector<SysDev> sys;
+    std::vector<SpeciesDev> spc;
+    Layout lay{};
+    int path = 0;
+    std::vector<BatchGroup> groups;
+    std::vector<int32_t> list;
+    const int rc = plan(args, rep, sys, spc, lay, path, groups, list, device_lds_limit());
+    if (rc) return rc;
+    *out_bytes = lay.total;
+    return HPMC_OK;
+}
+
+int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
+    if (out == nullptr) return HPMC_ERR_INVALID_ARG;
+    *out = nullptr;
+    hpmc_state* st = new (std::nothrow) hpmc_state();
+    if (st == nullptr) return HPMC_ERR_INVALID_ARG;
+    Layout lay{};
+    std::vector<int32_t> list;
+    int rc = plan(args, st->rep, st->sys, st->spc, lay, st->path, st->groups, list,
+                  device_lds_limit());
+    if (rc == HPMC_OK) rc = check_buffers(args, st->spc);
+    if (rc == HPMC_OK && args->workspace == nullptr) rc = HPMC_ERR_INVALID_ARG;
+    if (rc == HPMC_OK && ((uintptr_t)args->workspace % kAlign) != 0) rc = HPMC_ERR_INVALID_ARG;
+    if (rc == HPMC_OK && args->workspace_bytes < lay.total) rc = HPMC_ERR_WORKSPACE_TOO_SMALL;
+    if (rc) {
+        delete st;
+        return rc;
     }
+    bind_workspace(st, args, lay, list, (char*)args->workspace);
+    rc = upload_and_validate(st, lay);
     if (!rc) {
         std::vector<uint64_t> counts(st->n_replicas, 0);
         rc = count_all(st, counts.data());
@@ -777,6 +816,7 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     if (!rc) make_side_streams(st);
     if (!rc) capture_graph(st);
     if (rc) {
+        g_last_init_hip.store(st->last_hip);
         hpmc_destroy(st);
         return rc;
     }
@@ -983,7 +1023,7 @@ int hpmc_replica_info(hpmc_state* st, int32_t r, int32_t* cells_per_side, int32_
     return HPMC_OK;
 }
 
-int hpmc_last_hip_error(hpmc_state* st) { return st ? st->last_hip : 0; }
+int hpmc_last_hip_error(hpmc_state* st) { return st ? st->last_hip : g_last_init_hip.load(); }
 
 void hpmc_destroy(hpmc_state* st) {
     if (st == nullptr) return;
@@ -995,6 +1035,55 @@ void hpmc_destroy(hpmc_state* st) {
 }
 
 int hpmc_uses_graph(hpmc_state* st) { return (st && st->graph) ? 1 : 0; }
+
+int hpmc_phase_trace(uint64_t* out, int32_t n, int32_t reset) {
+    if (out == nullptr || n < kTraceWords) return HPMC_ERR_INVALID_ARG;
+    const hipError_t e = read_phase_trace((unsigned long long*)out, reset != 0);
+    if (e == hipErrorNotSupported) return HPMC_ERR_UNSUPPORTED;
+    return e == hipSuccess ? HPMC_OK : HPMC_ERR_HIP;
+}
+
+int hpmc_graph_sweeps(hpmc_state* st, uint64_t* out) {
+    if (st == nullptr || out == nullptr) return HPMC_ERR_INVALID_ARG;
+    *out = st->graph_sweeps;
+    return HPMC_OK;
+}
+
+int hpmc_volume_move(hpmc_state* st, int32_t replica, double u1, double u2, double beta_p,
+                     double delta_v, int32_t* accepted, double* L_after) {
+    if (st == nullptr || accepted == nullptr || replica < 0 || replica >= st->n_replicas)
+        return HPMC_ERR_INVALID_ARG;
+    if (!(u1 >= 0.0 && u1 < 1.0) || !(u2 >= 0.0 && u2 < 1.0) || !std::isfinite(beta_p) ||
+        !(delta_v >= 0.0) || !std::isfinite(delta_v))
+        return HPMC_ERR_INVALID_ARG;
+    const int r = replica;
+    const ReplicaHost& rh = st->rep[r];
+    *accepted = 0;
+    const double L = rh.L;
+    if (L_after) *L_after = L;
+    // trial volume V' = V + delta_v (2 u1 - 1) and side V'^(1/dim)
+    const double V = std::pow(L, (double)rh.dim);
+    const double dV = delta_v * (2.0 * u1 - 1.0);
+    const double V2 = V + dV;
+    if (!(V2 > 0.0)) return HPMC_OK;
+    const double L2 = std::pow(V2, 1.0 / (double)rh.dim);
+    if (L2 > rh.L_max) return HPMC_OK;
+    // scaled state; only a compression can create an overlap (the overlap
+    // region of two convex shapes is a convex set of separations containing
+    // 0, so r outside it keeps k r outside for k >= 1)
+    uint64_t ov = 0;
+    int rc = hpmc_scale_box(st, r, L2, dV < 0.0 ? &ov : nullptr);
+    if (rc == HPMC_ERR_BOX_TOO_SMALL) return HPMC_OK;
+    if (rc) return rc;
+    // Metropolis test of the isobaric volume move, min(1, exp(arg)); with
+    // u2 < 1 every arg >= 0 accepts, which also keeps exp from overflowing
+    const double arg = -beta_p * dV + (double)rh.N * std::log(V2 / V);
+    const bool ok = !(dV < 0.0 && ov > 0) && (arg >= 0.0 || u2 < std::exp(arg));
+    if (!ok) return hpmc_restore_box(st, r);
+    *accepted = 1;
+    if (L_after) *L_after = L2;
+    return HPMC_OK;
+}
 
 int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
     if (st == nullptr || trial_sweeps == 0) return HPMC_ERR_INVALID_ARG;

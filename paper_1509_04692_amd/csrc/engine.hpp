@@ -82,6 +82,42 @@ __device__ __forceinline__ void flush_block(const Counters& c, uint32_t* lds, un
     }
 }
 
+// Per-wave phase clock.  In a trace build (HPMC_TRACE) mark<PH>() adds the
+// shader cycles since the previous mark to phase PH (all lanes hold the same
+// wave-uniform values); flush() adds a wave's totals and 1 to the wave count
+// of its kernel's record.  In a normal build every call is empty.
+#ifdef HPMC_TRACE
+struct PhaseClock {
+    unsigned long long acc[kNumPhases];
+    unsigned long long last;
+    __device__ __forceinline__ void start() {
+#pragma unroll
+        for (int k = 0; k < kNumPhases; ++k) acc[k] = 0ull;
+        last = (unsigned long long)clock64();
+    }
+    template <int PH>
+    __device__ __forceinline__ void mark() {
+        const unsigned long long now = (unsigned long long)clock64();
+        acc[PH] += now - last;
+        last = now;
+    }
+    __device__ __forceinline__ void flush(unsigned long long* rec) const {
+        if (__lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < kNumPhases; ++k) atomicAdd(rec + k, acc[k]);
+            atomicAdd(rec + kNumPhases, 1ull);
+        }
+    }
+};
+#else
+struct PhaseClock {
+    __device__ __forceinline__ void start() {}
+    template <int PH>
+    __device__ __forceinline__ void mark() {}
+    __device__ __forceinline__ void flush(unsigned long long*) const {}
+};
+#endif
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -526,8 +562,9 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                                           const XsView<Traits<KIND>::dim>& xs, uint32_t colour,
                                           uint32_t select, uint32_t t, uint32_t k0, uint32_t k1,
                                           const double (&sh)[3], int a0, int n_act, WaveScratch ws,
-                                          Counters& ct) {
+                                          Counters& ct, PhaseClock& pc) {
     constexpr int D = Traits<KIND>::dim;
+    pc.mark<kPhOther>();
     const int lane = (int)__lane_id();
     const int grp = lane / G, sub = lane % G;
     const int leader = grp * G;
@@ -613,6 +650,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) yn[ax] = grid_coord(xn[ax], sh[ax], S.L);
     wave_sync();
+    pc.mark<kPhPropose>();
 
     if constexpr (Q == kWaveQueue) {
         // ---- 2 + 3. binary32 circumsphere pre-filter over the neighbour ranges
@@ -656,6 +694,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                 if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | slot;
                 queued += (uint32_t)__builtin_popcountll(hm);
                 if (queued >= 64u) {
+                    pc.mark<kPhScan>();
                     if constexpr (KIND == kPolygon && PREC == 0) {
                         queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, queued2, ct);
                     } else {
@@ -672,9 +711,11 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                     }
                     flagged = ws.flag[grp] != 0u;
                     e = flagged ? p : e;
+                    pc.mark<kPhDrain>();
                 }
             }
         }
+        pc.mark<kPhScan>();
         if constexpr (KIND == kPolygon && PREC == 0) {
             if (queued) queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, queued2, ct);
             while (queued2) {
@@ -686,6 +727,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         } else {
             if (queued) drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, queued, ws, ct);
         }
+        pc.mark<kPhDrain>();
     } else {
         // ---- 2 + 3, register queue (the paper's first variant): each lane
         // runs the pre-filter over its ranges and stops at its first hit; the
@@ -741,6 +783,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                 e = flagged ? p : e;
             }
         }
+        pc.mark<kPhScan>();
     }
 
     // ---- 4. write back (counters updated arithmetically, not per branch)
@@ -770,6 +813,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         }
     }
     wave_sync();
+    pc.mark<kPhWrite>();
 }
 
 }  // namespace hpmc

@@ -48,6 +48,35 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     return before + inc - v;
 }
 
+// Phase totals of a trace build: per traced kernel kNumPhases cycle sums and
+// a wave count (zero until read with reset).
+#ifdef HPMC_TRACE
+__device__ unsigned long long g_phase_trace[kTraceWords];
+#endif
+
+__device__ __forceinline__ void trace_flush(const PhaseClock& pc, int kernel) {
+#ifdef HPMC_TRACE
+    pc.flush(g_phase_trace + kernel * (kNumPhases + 1));
+#endif
+}
+
+hipError_t read_phase_trace(unsigned long long* out, bool reset) {
+#ifdef HPMC_TRACE
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_trace), sizeof(g_phase_trace));
+    if (e == hipSuccess && reset) {
+        const unsigned long long zero[kTraceWords] = {};
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_phase_trace), zero, sizeof(zero));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    return e;
+#else
+    (void)out;
+    (void)reset;
+    return hipErrorNotSupported;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Grid path: global cell list.
 // ---------------------------------------------------------------------------
@@ -56,12 +85,17 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, unsigned long lon
     if (i < n) p[i] = v;
 }
 
-__global__ void k_set_clock(Clock* __restrict__ clock, uint32_t t, uint32_t k0, uint32_t k1) {
-    if (threadIdx.x == 0) *clock = Clock{t, k0, k1, 0u};
+__global__ void k_set_clock(Clock* __restrict__ clock, uint32_t t, uint32_t k0, uint32_t k1,
+                            uint32_t n) {
+    if (threadIdx.x == 0) *clock = Clock{t, k0, k1, n};
 }
 
-__global__ void k_advance_clock(Clock* __restrict__ clock, uint32_t n) {
-    if (threadIdx.x == 0) clock->t += n;
+__global__ void k_set_chunk(Clock* __restrict__ clock, uint32_t n) {
+    if (threadIdx.x == 0) clock->n = n;
+}
+
+__global__ void k_advance_clock(Clock* __restrict__ clock) {
+    if (threadIdx.x == 0) clock->t += clock->n;
 }
 
 // Global cell lists of the grid path.  Every kernel below serves the
@@ -319,6 +353,8 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
     const SysDev S = sys[r];
     const SpeciesDev& P = spc[S.species];
     Counters ct = {};
+    PhaseClock pc;
+    pc.start();
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
     const int wave = threadIdx.x >> 6;
@@ -334,9 +370,11 @@ __global__ void __launch_bounds__(256) k_update(const SysDev* __restrict__ sys,
         pass_tile<KIND, PREC, G, NV, false, Q>(S, P, pos, ori_base + S.orient_off, cl,
                                             XsView<D>{xs + kXsStride * S.slot_off}, colour, select,
                                             t, k0, k1, sh, a0, n_act,
-                                            wave_scratch(scratch_words[wave]), ct);
+                                            wave_scratch(scratch_words[wave]), ct, pc);
     }
     flush_block(ct, &scratch_words[0][0], stat_stripe(stats, r));
+    pc.mark<kPhOther>();
+    trace_flush(pc, kTraceUpdate);
 }
 
 // ---------------------------------------------------------------------------
@@ -787,8 +825,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
                                                        double* __restrict__ pos_base,
                                                        double* __restrict__ ori_base,
                                                        unsigned long long* __restrict__ stats,
-                                                       const Clock* __restrict__ clock,
-                                                       uint32_t n_sweeps) {
+                                                       const Clock* __restrict__ clock) {
     constexpr int D = Traits<KIND>::dim;
     extern __shared__ __align__(16) unsigned char lds[];
     const int r = list[blockIdx.x];
@@ -815,8 +852,10 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     }
     __syncthreads();
     Counters ct = {};
+    PhaseClock pc;
+    pc.start();
     const Clock ck = *clock;
-    const uint32_t t0 = ck.t, k0 = ck.k0, k1 = ck.k1;
+    const uint32_t t0 = ck.t, k0 = ck.k0, k1 = ck.k1, n_sweeps = ck.n;
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
     const int chunk = (nc + B - 1) / B;
@@ -902,6 +941,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             }
         }
         __syncthreads();
+        pc.mark<kPhBuild>();
         const LdsCells cl{ends, mem};
         const uint32_t ncol = 1u << D;
         for (int rnd = 0; rnd < S.rounds; ++rnd) {
@@ -909,8 +949,10 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
                 for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64)
                     pass_tile<KIND, PREC, 1, NV, true>(S, P, pos, ori, cl, xs, colour, select, t, k0, k1,
-                                                 sh, a0, n_act, wscr, ct);
+                                                 sh, a0, n_act, wscr, ct, pc);
+                pc.mark<kPhOther>();
                 __syncthreads();
+                pc.mark<kPhBarrier>();
             }
         }
     }
@@ -922,6 +964,8 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         for (int k = tid; k < NC * N; k += B) gori[k] = ori[k];
     }
     flush(ct, stat_stripe(stats, r));
+    pc.mark<kPhOther>();
+    trace_flush(pc, kTraceBatch);
 }
 
 // ---------------------------------------------------------------------------
@@ -939,13 +983,19 @@ hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipSt
     return hipGetLastError();
 }
 
-hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, hipStream_t stream) {
-    k_set_clock<<<1, 64, 0, stream>>>(ws.clock, t, k0, k1);
+hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, uint32_t n,
+                     hipStream_t stream) {
+    k_set_clock<<<1, 64, 0, stream>>>(ws.clock, t, k0, k1, n);
     return hipGetLastError();
 }
 
-hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream) {
-    k_advance_clock<<<1, 64, 0, stream>>>(ws.clock, n);
+hipError_t set_chunk(const Workspace& ws, uint32_t n, hipStream_t stream) {
+    k_set_chunk<<<1, 64, 0, stream>>>(ws.clock, n);
+    return hipGetLastError();
+}
+
+hipError_t advance_clock(const Workspace& ws, hipStream_t stream) {
+    k_advance_clock<<<1, 64, 0, stream>>>(ws.clock);
     return hipGetLastError();
 }
 
@@ -1085,47 +1135,44 @@ hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, do
 
 template <int KIND, int PREC, int RES, int NV>
 static hipError_t launch_batch(const Workspace& ws, const int32_t* list, int n, int block, size_t lds,
-                               double* pos, double* orient, uint32_t n_sweeps, bool prepare,
-                               hipStream_t stream) {
+                               double* pos, double* orient, bool prepare, hipStream_t stream) {
     auto kern = k_batch<KIND, PREC, RES, NV>;
     if (prepare)  // raise the dynamic-LDS limit (not a stream operation; done before capture)
         return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds);
     if (block < 64 || block > kBatchBlock || block % 64 != 0) return hipErrorInvalidValue;
-    kern<<<n, block, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats, ws.clock, n_sweeps);
+    kern<<<n, block, lds, stream>>>(ws.sys, ws.species, list, pos, orient, ws.stats, ws.clock);
     return hipGetLastError();
 }
 
 template <int KIND, int PREC, int NV>
 static hipError_t launch_batch_res(const Workspace& ws, const BatchGroup& g, double* pos,
-                                   double* orient, uint32_t n_sweeps, bool prepare,
-                                   hipStream_t stream) {
+                                   double* orient, bool prepare, hipStream_t stream) {
     const int32_t* list = ws.batch_list + g.first;
     if (g.resident >= 2 && KIND != kDisk)
         return launch_batch<KIND, PREC, 2, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
-                                               n_sweeps, prepare, stream);
+                                               prepare, stream);
     if (g.resident >= 1)
         return launch_batch<KIND, PREC, 1, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
-                                               n_sweeps, prepare, stream);
+                                               prepare, stream);
     return launch_batch<KIND, PREC, 0, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
-                                           n_sweeps, prepare, stream);
+                                           prepare, stream);
 }
 
 hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* pos,
-                             double* orient, int precision, uint32_t n_sweeps, bool prepare,
-                             hipStream_t stream) {
+                             double* orient, int precision, bool prepare, hipStream_t stream) {
     if (g.kind == kDisk)
-        return launch_batch_res<kDisk, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+        return launch_batch_res<kDisk, 0, 0>(ws, g, pos, orient, prepare, stream);
     if (g.kind == kPolygon) {
         if (precision == 1)
-            return g.nv == 5 ? launch_batch_res<kPolygon, 1, 5>(ws, g, pos, orient, n_sweeps, prepare, stream)
-                             : launch_batch_res<kPolygon, 1, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
-        return g.nv == 5 ? launch_batch_res<kPolygon, 0, 5>(ws, g, pos, orient, n_sweeps, prepare, stream)
-                         : launch_batch_res<kPolygon, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+            return g.nv == 5 ? launch_batch_res<kPolygon, 1, 5>(ws, g, pos, orient, prepare, stream)
+                             : launch_batch_res<kPolygon, 1, 0>(ws, g, pos, orient, prepare, stream);
+        return g.nv == 5 ? launch_batch_res<kPolygon, 0, 5>(ws, g, pos, orient, prepare, stream)
+                         : launch_batch_res<kPolygon, 0, 0>(ws, g, pos, orient, prepare, stream);
     }
     if (precision == 1)
-        return launch_batch_res<kPolyhedron, 1, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
-    return launch_batch_res<kPolyhedron, 0, 0>(ws, g, pos, orient, n_sweeps, prepare, stream);
+        return launch_batch_res<kPolyhedron, 1, 0>(ws, g, pos, orient, prepare, stream);
+    return launch_batch_res<kPolyhedron, 0, 0>(ws, g, pos, orient, prepare, stream);
 }
 
 hipError_t pair_histogram(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,

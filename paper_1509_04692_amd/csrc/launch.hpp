@@ -104,22 +104,24 @@ hipError_t build_cells(const Workspace& ws, const int32_t* list, int count, int 
 hipError_t build_cells_one(const Workspace& ws, const ReplicaHost& rh, int r, const double* pos,
                            int shifted, hipStream_t stream);
 
-// Device clock: set {t, key}; advance t by n.
-hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, hipStream_t stream);
-hipError_t advance_clock(const Workspace& ws, uint32_t n, hipStream_t stream);
+// Device clock: set {t, key, sweeps per persistent launch n}; set n alone;
+// advance t by n.
+hipError_t set_clock(const Workspace& ws, uint32_t t, uint32_t k0, uint32_t k1, uint32_t n,
+                     hipStream_t stream);
+hipError_t set_chunk(const Workspace& ws, uint32_t n, hipStream_t stream);
+hipError_t advance_clock(const Workspace& ws, hipStream_t stream);
 
 // All colour passes of sweep t for the replicas of a grid-path group on
 // their global cell lists.
 hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
                        int precision, int queue, hipStream_t stream);
 
-// n_sweeps whole sweeps of the replicas of one batch group, one work-group
-// each.
+// Whole sweeps of the replicas of one batch group, one work-group each; the
+// number of sweeps is the device clock's n.
 // prepare = true only raises the kernel's dynamic-LDS limit (call before
 // launching or capturing).
 hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* pos,
-                             double* orient, int precision, uint32_t n_sweeps, bool prepare,
-                             hipStream_t stream);
+                             double* orient, int precision, bool prepare, hipStream_t stream);
 
 // Overlapping pairs of replica r (after build_cells with shifted = 0), added
 // to ws.overlap_out[r].
@@ -141,6 +143,11 @@ hipError_t scale_counts(const Workspace& ws, const ReplicaHost& rh, int r, const
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream);
 // n coordinates x -> x k wrapped into [0, L_new) (NPT box change).
 hipError_t scale_box(double* pos, int64_t n, double k, double L_new, hipStream_t stream);
+
+// Trace build (HPMC_TRACE): copy the kTraceWords phase totals to out (host)
+// after synchronising the device, and clear them when reset; otherwise
+// hipErrorNotSupported.
+hipError_t read_phase_trace(unsigned long long* out, bool reset);
 
 // Dynamic LDS of a persistent work-group (positions resident or not).
 size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res, int block);

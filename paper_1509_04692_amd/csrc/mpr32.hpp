@@ -44,6 +44,16 @@
 
 #include "types.hpp"
 
+// Observation hooks for a host build of the test harness (empty in the
+// library): every certified sign decision's value and error bound, the gap
+// test's value and bound, and the vertex pair of every support call.
+#ifndef HPMC_MPR32_OBSERVE
+#define HPMC_MPR32_OBSERVE(x, e)
+#endif
+#ifndef HPMC_MPR32_SUPPORT
+#define HPMC_MPR32_SUPPORT(ka, kb)
+#endif
+
 namespace hpmc {
 
 #define HPMC_HD __host__ __device__ inline
@@ -91,7 +101,10 @@ HPMC_HD float tv_dot_err(const TV& a, const TV& b) {
 }
 
 // Sign of a value with error bound e: +1, -1, or 0 when uncertain.
-HPMC_HD int certain_sign(float x, float e) { return x > e ? 1 : (x < -e ? -1 : 0); }
+HPMC_HD int certain_sign(float x, float e) {
+    HPMC_MPR32_OBSERVE(x, e);
+    return x > e ? 1 : (x < -e ? -1 : 0);
+}
 
 // Binary32 copies of the set-up values.
 struct Mink32 {
@@ -133,6 +146,7 @@ HPMC_HD Sup32 support32(const SpeciesDev& P, const Mink32& mk, const TV& n) {
             ka = k;
         }
     }
+    HPMC_MPR32_SUPPORT(ka, kb);
     const float bx = P.vx32[kb], by = P.vy32[kb], bz = P.vz32[kb];
     Sup32 s;
     s.p.v = F3{(fmaf(m[0][2], bz, fmaf(m[0][1], by, m[0][0] * bx)) + mk.t.v.x) - P.vx32[ka],
@@ -269,6 +283,7 @@ HPMC_HD int polyhedron_overlap32(const SpeciesDev& P, const double (&M)[3][3], c
             const float gap = dotf(d.v, n.v);
             const float egap = ehv + tv_dot_err(v3, n) + kSlack * 3.0f * kU32 * norm1(d.v) * norm1(n.v);
             const float n1 = norm1(n.v) + 3.0f * n.e;
+            HPMC_MPR32_OBSERVE(gap, egap);
             if (gap < -egap) return kMprNoOverlap;
             if (!(gap > egap + 2.0f * tol * n1)) return kMprUncertain;
         }

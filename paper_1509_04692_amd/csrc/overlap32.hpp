@@ -20,6 +20,13 @@
 #include "overlap64.hpp"
 #include "types.hpp"
 
+// Observation hook of the certified filters: a host build of the test
+// harness defines it to record every binary32 decision value beside its
+// error bound; the library's build leaves it empty.
+#ifndef HPMC_SAT32_OBSERVE
+#define HPMC_SAT32_OBSERVE(half, k, lo, hi)
+#endif
+
 namespace hpmc {
 
 enum : int { kNoOverlap = 0, kOverlap = 1, kUncertain = 2 };
@@ -75,6 +82,7 @@ __host__ __device__ inline int polygon_half32(const SpeciesDev& P, double rxd, d
                 }
             }
             const float smax = P.pmax32[k], smin = P.pmin32[k];
+            HPMC_SAT32_OBSERVE(HALF, k, lo, hi);
             if (lo >= smax + M || hi <= smin - M) return kHalfSeparated;
             unsure |= !(lo < smax - M && hi > smin + M);
         }
@@ -121,6 +129,7 @@ __host__ __device__ inline int polygon_overlap32_regular(const SpeciesDev& P, do
                 const float c = fmaf(P.nx32[k], tx, P.ny32[k] * ty);
                 const float l = lo + c, h = hi + c;
                 const float smax = P.pmax32[k], smin = P.pmin32[k];
+                HPMC_SAT32_OBSERVE(0, k, l, h);
                 if (l >= smax + M || h <= smin - M) return kNoOverlap;
                 unsure |= !(l < smax - M && h > smin + M);
             }
@@ -146,6 +155,7 @@ __host__ __device__ inline int polygon_overlap32_regular(const SpeciesDev& P, do
                 const float c = -fmaf(P.nx32[k], ux, P.ny32[k] * uy);
                 const float l = lo + c, h = hi + c;
                 const float smax = P.pmax32[k], smin = P.pmin32[k];
+                HPMC_SAT32_OBSERVE(1, k, l, h);
                 if (h <= smin - M || l >= smax + M) return kNoOverlap;
                 unsure |= !(h > smin + M && l < smax - M);
             }

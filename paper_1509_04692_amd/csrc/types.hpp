@@ -52,11 +52,14 @@ struct alignas(16) SpeciesDev {
     float pad2[2];
 };
 
-// Sweep counter and Philox key, read by the kernels from device memory so that
-// a captured sweep can be replayed: set once per hpmc_sweep call, advanced by
-// a kernel at the end of every sweep (or persistent chunk).
+// Sweep counter, Philox key and the length of a persistent launch, read by
+// the kernels from device memory so that one captured sweep (grid path) or
+// chunk (persistent path) can be replayed for any call: set once per
+// hpmc_sweep call (n changed again before a shorter last chunk), t advanced
+// by n by a kernel at the end of every sweep or chunk.
 struct alignas(16) Clock {
-    uint32_t t, k0, k1, pad;
+    uint32_t t, k0, k1;
+    uint32_t n;  // sweeps per persistent launch (1 on the grid path)
 };
 
 // One replica (independent system) and its grid.
@@ -75,6 +78,17 @@ struct alignas(16) SysDev {
     float scan_t2;
     uint32_t pad;
 };
+
+// Phases of the per-wave clock of a trace build (HPMC_TRACE): cell-list
+// build, trial move, pre-filter scan, queued full tests, write-back, waiting
+// at the work-group barrier after a pass, everything else (loads, loop
+// overhead).  Kernels traced: the persistent batch kernel and the grid
+// path's colour pass.
+enum Phase : int { kPhBuild = 0, kPhPropose, kPhScan, kPhDrain, kPhWrite, kPhBarrier, kPhOther,
+                   kNumPhases };
+enum TracedKernel : int { kTraceBatch = 0, kTraceUpdate = 1, kTraceKernels = 2 };
+// Per traced kernel: kNumPhases cycle totals, then the number of waves.
+constexpr int kTraceWords = kTraceKernels * (kNumPhases + 1);
 
 // Floats per particle reserved for the cell-sorted coordinates of any
 // replica in the global cell list (float2 in 2D, float4 in 3D).

@@ -35,6 +35,68 @@ def _as_list(x, n):
     return [x] * n
 
 
+def init_args(species, N, L, pos, orient, precision, path, stream, flags=0, L_max=None):
+    """hpmc_init_args for replicas with the given species / N / L lists and
+    device tensors pos / orient (replicas concatenated, hpmc.h layout).
+    Returns (args, objects that must outlive the call)."""
+    n_rep = len(species)
+    keep = []
+    sp_arr = (_lib.Species * n_rep)()
+    for r, sp in enumerate(species):
+        s = sp_arr[r]
+        s.dim = int(sp["dim"])
+        s.shape = _lib.SHAPES[sp["shape"]]
+        if sp["shape"] != "disk":
+            v = np.ascontiguousarray(np.asarray(sp["verts"], dtype=np.float64))
+            keep.append(v)
+            s.n_verts = v.shape[0]
+            s.verts = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.diameter = float(sp.get("diameter", 0.0))
+        s.d = float(sp.get("d", 0.0))
+        s.a = float(sp.get("a", 0.0))
+        s.p_rot = float(sp.get("p_rot", 0.0))
+        s.rounds = int(sp.get("rounds", 0))
+        s.sweep_radius = float(sp.get("sweep_radius", 0.0))
+    N_arr = (ctypes.c_int32 * n_rep)(*[int(x) for x in N])
+    L_arr = (ctypes.c_double * n_rep)(*[float(x) for x in L])
+    args = _lib.InitArgs()
+    args.n_replicas = n_rep
+    args.species = sp_arr
+    args.N = N_arr
+    args.L = L_arr
+    args.precision = _lib.PRECISIONS[precision]
+    args.path = _lib.PATHS[path]
+    args.pos = pos.data_ptr()
+    args.orient = orient.data_ptr() if orient is not None else None
+    args.stream = stream.cuda_stream
+    args.flags = flags
+    keep += [sp_arr, N_arr, L_arr]
+    if L_max is not None:
+        Lmax_arr = (ctypes.c_double * n_rep)(*[float(x) for x in L_max])
+        args.L_max = Lmax_arr
+        keep.append(Lmax_arr)
+    return args, keep
+
+
+def phase_trace(reset=False):
+    """Per-wave phase clock of the trace build (HPMC_LIBRARY pointing at
+    lib/libhpmc_trace.so): {kernel: {"waves": n, phase: cycles summed over
+    waves}} since the last reset; synchronises the device."""
+    lib = _lib.load()
+    n = len(_lib.TRACED_KERNELS) * (len(_lib.PHASES) + 1)
+    out = (ctypes.c_uint64 * n)()
+    rc = lib.hpmc_phase_trace(out, n, 1 if reset else 0)
+    if rc != _lib.HPMC_OK:
+        raise _lib.HpmcError(rc, "hpmc_phase_trace")
+    res, k = {}, 0
+    for name in _lib.TRACED_KERNELS:
+        d = {ph: int(out[k + j]) for j, ph in enumerate(_lib.PHASES)}
+        d["waves"] = int(out[k + len(_lib.PHASES)])
+        res[name] = d
+        k += len(_lib.PHASES) + 1
+    return res
+
+
 class System:
     def __init__(self, species, N, L, pos, orient=None, precision="fp64", path="auto",
                  device="cuda", stream=None, graphs=True, queue="wave", L_max=None):
@@ -81,47 +143,16 @@ class System:
         ori = np.concatenate(ori_parts) if ori_parts else np.zeros(1)
         self.orient = torch.from_numpy(ori).to(self.device)
 
-        self._keep = []
-        sp_arr = (_lib.Species * n_rep)()
-        for r, sp in enumerate(self.species):
-            s = sp_arr[r]
-            s.dim = int(sp["dim"])
-            s.shape = _lib.SHAPES[sp["shape"]]
-            if sp["shape"] != "disk":
-                v = np.ascontiguousarray(np.asarray(sp["verts"], dtype=np.float64))
-                self._keep.append(v)
-                s.n_verts = v.shape[0]
-                s.verts = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            s.diameter = float(sp.get("diameter", 0.0))
-            s.d = float(sp.get("d", 0.0))
-            s.a = float(sp.get("a", 0.0))
-            s.p_rot = float(sp.get("p_rot", 0.0))
-            s.rounds = int(sp.get("rounds", 0))
-            s.sweep_radius = float(sp.get("sweep_radius", 0.0))
-        self._sp_arr = sp_arr
-        self._N_arr = (ctypes.c_int32 * n_rep)(*self.N)
-        self._L_arr = (ctypes.c_double * n_rep)(*self.L)
         self.L_max = ([float(x) for x in _as_list(L_max, n_rep)] if L_max is not None
                       else list(self.L))
-        self._Lmax_arr = (ctypes.c_double * n_rep)(*self.L_max)
-
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
-        args = _lib.InitArgs()
-        args.n_replicas = n_rep
-        args.species = sp_arr
-        args.N = self._N_arr
-        args.L = self._L_arr
-        args.precision = _lib.PRECISIONS[precision]
-        args.path = _lib.PATHS[path]
-        args.pos = self.pos.data_ptr()
-        args.orient = self.orient.data_ptr()
-        args.stream = stream.cuda_stream
         if queue not in _lib.QUEUE_FLAGS:
             raise ValueError(f"queue must be one of {sorted(_lib.QUEUE_FLAGS)}")
-        args.flags = (0 if graphs else _lib.FLAG_NO_GRAPH) | _lib.QUEUE_FLAGS[queue]
-        args.L_max = self._Lmax_arr
+        flags = (0 if graphs else _lib.FLAG_NO_GRAPH) | _lib.QUEUE_FLAGS[queue]
+        args, self._keep = init_args(self.species, self.N, self.L, self.pos, self.orient, precision,
+                                     path, stream, flags, self.L_max)
         nbytes = ctypes.c_size_t()
         self._check(self._lib.hpmc_workspace_bytes(ctypes.byref(args), ctypes.byref(nbytes)),
                     "hpmc_workspace_bytes")
@@ -139,7 +170,8 @@ class System:
     # -- calls -------------------------------------------------------------
     def _check(self, rc, what):
         if rc != _lib.HPMC_OK:
-            hip = self._lib.hpmc_last_hip_error(self._handle) if getattr(self, "_handle", None) else 0
+            # a failed hpmc_init leaves no state: NULL asks for its HIP error
+            hip = self._lib.hpmc_last_hip_error(getattr(self, "_handle", None))
             raise _lib.HpmcError(rc, what, hip)
 
     def sweep(self, n_sweeps, seed):
@@ -162,6 +194,13 @@ class System:
     @property
     def uses_graph(self):
         return bool(self._lib.hpmc_uses_graph(self._handle))
+
+    @property
+    def graph_sweeps(self):
+        """Sweeps run by replaying the captured hipGraph since init."""
+        n = ctypes.c_uint64()
+        self._check(self._lib.hpmc_graph_sweeps(self._handle, ctypes.byref(n)), "hpmc_graph_sweeps")
+        return n.value
 
     def count_overlaps(self):
         out = (ctypes.c_uint64 * self.n_replicas)()
@@ -202,6 +241,19 @@ class System:
     def restore_box(self, r):
         self._check(self._lib.hpmc_restore_box(self._handle, int(r)), "hpmc_restore_box")
         self.L[r] = self._L_prev.pop(r)
+
+    def volume_move(self, r, u1, u2, beta_p, delta_v):
+        """One isobaric volume move of replica r with the uniforms (u1, u2);
+        returns True when accepted (the library decides and applies it)."""
+        acc, L_after = ctypes.c_int32(), ctypes.c_double()
+        self._check(self._lib.hpmc_volume_move(self._handle, int(r), float(u1), float(u2),
+                                               float(beta_p), float(delta_v), ctypes.byref(acc),
+                                               ctypes.byref(L_after)), "hpmc_volume_move")
+        if acc.value:
+            self._L_prev = getattr(self, "_L_prev", {})
+            self._L_prev[r] = self.L[r]
+        self.L[r] = L_after.value
+        return bool(acc.value)
 
     def stats(self):
         out = (_lib.Stats * self.n_replicas)()

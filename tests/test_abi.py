@@ -133,6 +133,20 @@ def test_queue_variant_flags(lib):
         assert ws_bytes(lib, *two, path=0, flags=_lib.QUEUE_FLAGS[q])[0] == 0   # auto: grid
 
 
+def test_polygon_rotation_bound(lib):
+    """Polygon rotation sizes above HPMC_MAX_POLYGON_ROTATION (0.75 rad) are
+    rejected: the unnormalised 2D move is exact to rounding only below it."""
+    with open(HEADER) as f:
+        bound = float(re.search(r"#define HPMC_MAX_POLYGON_ROTATION ([0-9.]+)", f.read()).group(1))
+    assert bound == 0.75
+    sp = inputs.pentagon_species()
+    assert ws_bytes(lib, [dict(sp, a=bound)], [1024], [32.0])[0] == 0
+    assert ws_bytes(lib, [dict(sp, a=float(np.nextafter(bound, 1.0)))], [1024], [32.0])[0] == -1
+    assert ws_bytes(lib, [dict(sp, a=float("nan"))], [1024], [32.0])[0] == -1
+    # polyhedra renormalise their quaternion: no bound
+    assert ws_bytes(lib, [dict(inputs.cube_species(), a=1.5)], [512], [12.0])[0] == 0
+
+
 def test_sweep_radius_rules(lib):
     sph = inputs.sphere_species(1.0)
     assert ws_bytes(lib, [sph], [512], [8.75])[0] == 0           # one vertex, swept

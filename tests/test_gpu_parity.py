@@ -434,8 +434,8 @@ def test_scale_counts_match_oracle(kind):
 @pytest.mark.parametrize("case", ["disks_grid", "disks_persistent", "pentagons_mixed",
                                   "cubes_mixed"])
 def test_npt_volume_moves_equal_the_oracle(case):
-    """Sweeps interleaved with volume moves (box scaling and the overlap count
-    in the kernels, acceptance on the host): final positions, orientations,
+    """Sweeps interleaved with volume moves (proposal, box scaling, overlap
+    count and acceptance in the library, hpmc_volume_move): final positions, orientations,
     box side, accepted moves and sweep counters equal the oracle's NPT chain
     bit for bit, with the grid rebuilt as the box changes."""
     shape, path = case.split("_")

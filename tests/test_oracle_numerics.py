@@ -149,3 +149,23 @@ def test_sincos_pin_detects_dropped_term(planted):
     mpmath.mp.dps = 50
     c, s = oracle.sincos(0.2, lib=lib)
     assert abs(mpmath.mpf(s) - mpmath.sin(mpmath.mpf(0.2))) > 2 * np.spacing(0.2)
+
+
+def test_polygon_rotation_keeps_unit_norm_up_to_the_angle_bound():
+    """The 2D move multiplies the unit complex orientation by (cos d, sin d)
+    from truncated series and never renormalises it (Sec. 2.1, q . dq).  Up to
+    the library's angle bound (0.75 rad) the first dropped term, d^17 / 17!,
+    is below 2^-53, so after 10^6 accepted rotations |z| may drift only by
+    rounding: at most 3 units of 2^-53 per product, 3.3e-10 in all.  At
+    a = 3 rad the truncation alone moves |z| by orders of magnitude more."""
+    from paper_1509_04692_amd import inputs
+    drift = {}
+    for a in (0.75, 3.0):
+        sp = inputs.pentagon_species(a=a, p_rot=1.0)
+        pos = np.array([[2.1], [2.1]])
+        ori = np.array([[1.0], [0.0]])
+        st = oracle.sweep(sp, 4.2, pos, ori, seed=3, n_sweeps=1_000_000)
+        assert st[1] == st[4] == 1_000_000  # every move a rotation, all accepted
+        drift[a] = abs(float(np.hypot(ori[0, 0], ori[1, 0])) - 1.0)
+    assert drift[0.75] <= 1e6 * 3 * 2.0 ** -53, drift
+    assert drift[3.0] > 1e-4, drift

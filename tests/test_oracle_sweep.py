@@ -288,3 +288,106 @@ def test_disk_pair_structure_matches_serial_metropolis():
     assert stats.chi2.sf(chi2, len(tstat)) > 1e-4, (tstat, cb.mean(0))
     # near-contact structure is real: the first bin is the most populated
     assert cb.mean(0)[0] > cb.mean(0)[-1]
+
+
+def _rotation_matrix(q):
+    """Textbook rotation matrix of the unit quaternion q = (w, x, y, z)."""
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _check_right_composition(lib=None):
+    sp = inputs.cube_species(a=0.3, p_rot=1.0)
+    L, seed = 7.5, 5
+    rng = np.random.Generator(np.random.PCG64(11))
+    for trial in range(8):
+        q0 = rng.normal(size=4)
+        q0 /= np.linalg.norm(q0)
+        pos = np.array([[1.3 + 0.7 * trial], [2.9], [4.1]])
+        ori = q0.reshape(4, 1).copy()
+        st = oracle.sweep(sp, L, pos, ori, seed=seed, n_sweeps=1, t0=trial, lib=lib)
+        assert st[0] == st[1] == st[4] == 1  # one rotation, accepted
+        got = _rotation_matrix(ori[:, 0])
+        right, left = [], []
+        for colour in range(8):  # one round: select = colour
+            w = oracle.philox4x32_10([trial, (3 << 28) | colour, 0, 0], [seed, 0])
+            dq = np.array([1.0] + [0.3 * (2.0 * oracle.u01(w[1 + a]) - 1.0) for a in range(3)])
+            right.append(np.abs(got - _rotation_matrix(q0) @ _rotation_matrix(dq)).max())
+            left.append(np.abs(got - _rotation_matrix(dq) @ _rotation_matrix(q0)).max())
+        assert min(right) < 1e-14, right
+        assert min(left) > 1e-3, left
+        assert sorted(right)[1] > 1e-3  # exactly one colour pass moved it
+
+
+def test_3d_rotation_composes_on_the_right():
+    """The 3D trial orientation is q . dq (Sec. 2.1): the particle turns by
+    dq about its own body axes, so R(q') = R(q) R(dq) -- not R(dq) R(q),
+    which would turn it about the box axes.  One cube alone in its box, one
+    sweep of rotation-only moves: dq = (1, v) with v from the particle's MOVE
+    words (v_a = a (2 u01(m_{1+a}) - 1)) for the colour pass that moved it."""
+    _check_right_composition()
+
+
+def test_3d_rotation_pin_detects_planted_left_product(planted):
+    lib = planted("ORACLE_PLANT_LEFT_ROTATION")
+    with pytest.raises(AssertionError):
+        _check_right_composition(lib)
+
+
+def _pentagon_pairs(pos, orient, L, r_max):
+    r = pos[:, :, None] - pos[:, None, :]
+    r -= L * np.round(r / L)
+    d = np.sqrt(np.sum(r * r, axis=0))
+    iu = np.triu_indices(pos.shape[1], 1)
+    theta = np.arctan2(orient[1], orient[0])
+    dth = (theta[:, None] - theta[None, :])[iu]
+    d = d[iu]
+    near = d < r_max
+    return d, np.cos(5.0 * dth[near])
+
+
+def test_pentagon_structure_matches_serial_metropolis():
+    """Pentagons at packing fraction 0.60 with translations and rotations:
+    the centre-centre g(r) near contact and the orientational correlation
+    <cos 5 (theta_i - theta_k)> of close pairs from 12 checkerboard chains
+    equal those of 12 serial one-move-at-a-time Metropolis chains (two-sample
+    t statistics).  Pins the rotation moves, the cell rule and the random
+    occupant choice together against the plain Metropolis chain of Sec. 2.1."""
+    sp, N, L, pos0, ori0 = inputs.workload_pentagons(144, 0.60)
+    edges = np.linspace(0.80, 1.40, 13)
+    n_eq, n_prod, every = 1000, 2000, 20
+
+    def run(kind, seed):
+        pos, ori = pos0.copy(), ori0.copy()
+        h = np.zeros(len(edges) - 1)
+        corr = []
+        if kind == "cb":
+            oracle.sweep(sp, L, pos, ori, seed=seed, n_sweeps=n_eq)
+        else:
+            oracle.serial_metropolis(sp, L, pos, ori, seed=seed, n_moves=n_eq * N)
+        for k in range(n_prod // every):
+            if kind == "cb":
+                oracle.sweep(sp, L, pos, ori, seed=seed, n_sweeps=every, t0=n_eq + k * every)
+            else:
+                oracle.serial_metropolis(sp, L, pos, ori, seed=seed, n_moves=every * N,
+                                         move0=(n_eq + k * every) * N)
+            d, c = _pentagon_pairs(pos, ori, L, 1.0)
+            h += np.histogram(d, bins=edges)[0]
+            corr.append(c.mean())
+        return h / (n_prod // every), float(np.mean(corr))
+
+    cb = [run("cb", 3000 + s) for s in range(12)]
+    se = [run("serial", 4000 + s) for s in range(12)]
+    from scipy import stats
+    hc, hs = np.array([x[0] for x in cb]), np.array([x[0] for x in se])
+    tstat = (hc.mean(0) - hs.mean(0)) / np.sqrt(hc.var(0, ddof=1) / 12 + hs.var(0, ddof=1) / 12)
+    assert stats.chi2.sf(float(np.sum(tstat ** 2)), len(tstat)) > 1e-4, (tstat, hc.mean(0))
+    cc, cs = np.array([x[1] for x in cb]), np.array([x[1] for x in se])
+    t_or = (cc.mean() - cs.mean()) / math.sqrt(cc.var(ddof=1) / 12 + cs.var(ddof=1) / 12)
+    assert abs(t_or) < 4.0, (cc.mean(), cs.mean(), t_or)
+    # the observables see real structure: close pairs prefer interlocked
+    # (anti-aligned) orientations, and contact-range bins are populated
+    assert hc.mean(0)[:4].sum() > 0
+    assert abs(cc.mean()) > 5 * cc.std(ddof=1) / math.sqrt(12), cc
