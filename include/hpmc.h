@@ -295,6 +295,33 @@ int hpmc_last_hip_error(hpmc_state *st);
 void hpmc_destroy(hpmc_state *st);
 const char *hpmc_strerror(int code);
 
+/* Bytes of the library's own device scratch, used by hpmc_sweep_static. */
+#define HPMC_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): hpmc_init +
+ * hpmc_set_sweep(t0) + hpmc_sweep(n_sweeps, seed) + hpmc_get_stats in one
+ * call that allocates nothing.  The tables, cell lists and counters live in
+ * a static device array of HPMC_STATIC_SCRATCH_BYTES (64 MiB) that each GPU
+ * the library runs on holds until the process ends; the caller still passes
+ * pos / orient (device, updated in place, the hpmc_init layout).
+ * args->workspace must be NULL and workspace_bytes 0 (else
+ * HPMC_ERR_INVALID_ARG); HPMC_FLAG_NO_GRAPH is implied (kernels launch
+ * directly on args->stream, the launches of several shape kinds one after
+ * another); the register and global queue flags give HPMC_ERR_UNSUPPORTED.
+ * A batch whose workspace (without the autotuning and box-move snapshots)
+ * exceeds the scratch gives HPMC_ERR_WORKSPACE_TOO_SMALL before any device
+ * work.  Positions must lie in [0, L) and orientations be finite
+ * (HPMC_ERR_INVALID_ARG otherwise); the initial state is not checked for
+ * overlaps.  The trajectory equals the hpmc_init / hpmc_sweep one bit for
+ * bit.  out_per_replica (host, may be NULL) receives the counters of these
+ * sweeps; *hip_error (may be NULL) the hipError_t of a failed HIP call, else
+ * 0.  Synchronising.  Every call on one GPU shares that GPU's scratch and
+ * overwrites it: calls that overlap in time on one GPU (other host threads
+ * or streams) race and must be serialised by the caller. */
+int hpmc_sweep_static(const hpmc_init_args *args, uint64_t t0, uint64_t n_sweeps, uint64_t seed,
+                      hpmc_stats *out_per_replica, int32_t *hip_error);
+
 #ifdef __cplusplus
 }
 #endif

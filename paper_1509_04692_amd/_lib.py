@@ -31,7 +31,7 @@ EXPORTS = ("hpmc_workspace_bytes", "hpmc_init", "hpmc_sweep", "hpmc_autotune", "
            "hpmc_restore_box", "hpmc_get_stats", "hpmc_reset_stats",
            "hpmc_sync_to_canonical", "hpmc_get_sweep", "hpmc_set_sweep", "hpmc_replica_info",
            "hpmc_uses_graph", "hpmc_graph_sweeps", "hpmc_volume_move", "hpmc_last_hip_error",
-           "hpmc_destroy", "hpmc_strerror", "hpmc_phase_trace")
+           "hpmc_destroy", "hpmc_strerror", "hpmc_phase_trace", "hpmc_sweep_static")
 FLAG_NO_GRAPH = 1
 QUEUE_FLAGS = {"wave": 0, "register": 2, "global": 4}  # HPMC_FLAG_*_QUEUE
 
@@ -120,6 +120,9 @@ def load(path=None):
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
     lib.hpmc_graph_sweeps.argtypes = [st, ctypes.POINTER(ctypes.c_uint64)]
     lib.hpmc_phase_trace.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.c_int32]
+    lib.hpmc_sweep_static.argtypes = [ctypes.POINTER(InitArgs), ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.POINTER(Stats),
+                                      ctypes.POINTER(ctypes.c_int32)]
     lib.hpmc_get_stats.argtypes = [st, ctypes.POINTER(Stats)]
     lib.hpmc_reset_stats.argtypes = [st]
     lib.hpmc_sync_to_canonical.argtypes = [st]

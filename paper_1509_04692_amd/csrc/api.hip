@@ -9,6 +9,7 @@
 #include <cmath>
 #include <atomic>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -18,6 +19,13 @@
 #include "types.hpp"
 
 using namespace hpmc;
+
+// Device memory of hpmc_sweep_static, the entry point that allocates
+// nothing: every workspace region of its call lives here.  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes this name to a kernel or a copy (on the host it is a stand-in, not a
+// device address): it uses the per-device address from hipGetSymbolAddress.
+__device__ __align__(256) unsigned char scratch[HPMC_STATIC_SCRATCH_BYTES];
 
 struct hpmc_state {
     int n_replicas = 0;
@@ -658,6 +666,34 @@ int run_sweeps(hpmc_state* st, uint64_t n_sweeps, uint32_t k0, uint32_t k1) {
 }
 
 
+// Device address of `scratch` on the current device: looked up once per
+// device, with that device current, and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out, int* hip_error) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *hip_error = (int)e;
+        return HPMC_ERR_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return HPMC_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            *hip_error = (int)e;
+            return HPMC_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HPMC_OK;
+}
+
 // The caller's particle buffers: positions always, orientations unless every
 // replica is a disk.
 int check_buffers(const hpmc_init_args* args, const std::vector<SpeciesDev>& spc) {
@@ -822,6 +858,41 @@ int hpmc_init(hpmc_state** out, const hpmc_init_args* args) {
     }
     *out = st;
     return HPMC_OK;
+}
+
+int hpmc_sweep_static(const hpmc_init_args* args, uint64_t t0, uint64_t n_sweeps, uint64_t seed,
+                      hpmc_stats* out_per_replica, int32_t* hip_error) {
+    if (hip_error) *hip_error = 0;
+    if (args == nullptr) return HPMC_ERR_INVALID_ARG;
+    if (t0 >= kSweepLimit || n_sweeps > kSweepLimit - t0) return HPMC_ERR_SWEEP_OVERFLOW;
+    hpmc_state st;
+    Layout lay{};
+    std::vector<int32_t> list;
+    int rc = plan(args, st.rep, st.sys, st.spc, lay, st.path, st.groups, list, device_lds_limit(),
+                  false);
+    if (rc) return rc;
+    rc = check_buffers(args, st.spc);
+    if (!rc && (args->workspace != nullptr || args->workspace_bytes != 0)) rc = HPMC_ERR_INVALID_ARG;
+    if (!rc && queue_mode(args->flags) != kQueueWave) rc = HPMC_ERR_UNSUPPORTED;
+    if (!rc && lay.total > (size_t)HPMC_STATIC_SCRATCH_BYTES) rc = HPMC_ERR_WORKSPACE_TOO_SMALL;
+    if (rc) return rc;
+    void* base = nullptr;
+    int hip = 0;
+    rc = static_scratch(&base, &hip);
+    if (rc) {
+        if (hip_error) *hip_error = hip;
+        return rc;
+    }
+    bind_workspace(&st, args, lay, list, (char*)base);
+    st.flags |= HPMC_FLAG_NO_GRAPH;  // direct launches: no graph, no side streams
+    rc = upload_and_validate(&st, lay);
+    st.t = t0;
+    if (!rc && n_sweeps) rc = run_sweeps(&st, n_sweeps, (uint32_t)seed, (uint32_t)(seed >> 32));
+    st.sweeps_done = n_sweeps;
+    if (!rc && out_per_replica) rc = hpmc_get_stats(&st, out_per_replica);
+    if (!rc) rc = check_hip(&st, hipStreamSynchronize(st.stream));
+    if (hip_error) *hip_error = st.last_hip;
+    return rc;
 }
 
 int hpmc_sweep(hpmc_state* st, uint64_t n_sweeps, uint64_t seed) {

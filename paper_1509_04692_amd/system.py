@@ -78,6 +78,28 @@ def init_args(species, N, L, pos, orient, precision, path, stream, flags=0, L_ma
     return args, keep
 
 
+def sweep_static(species, N, L, pos, orient, t0, n_sweeps, seed, precision="fp64", path="auto",
+                 stream=None):
+    """n_sweeps sweeps from sweep counter t0 through hpmc_sweep_static, the
+    entry point that allocates no device memory: pos / orient are the
+    caller's device tensors (float64, replicas concatenated, hpmc.h layout),
+    updated in place.  Returns the per-replica counters of these sweeps."""
+    import torch
+    lib = _lib.load()
+    n_rep = len(species)
+    if stream is None:
+        stream = torch.cuda.current_stream(pos.device)
+    args, keep = init_args(species, N, L, pos, orient, precision, path, stream)
+    out = (_lib.Stats * n_rep)()
+    hip = ctypes.c_int32()
+    rc = lib.hpmc_sweep_static(ctypes.byref(args), int(t0), int(n_sweeps), int(seed), out,
+                               ctypes.byref(hip))
+    del keep
+    if rc != _lib.HPMC_OK:
+        raise _lib.HpmcError(rc, "hpmc_sweep_static", hip.value)
+    return [{f: int(getattr(out[r], f)) for f in _lib.STAT_FIELDS} for r in range(n_rep)]
+
+
 def phase_trace(reset=False):
     """Per-wave phase clock of the trace build (HPMC_LIBRARY pointing at
     lib/libhpmc_trace.so): {kernel: {"waves": n, phase: cycles summed over

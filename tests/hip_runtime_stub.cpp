@@ -25,6 +25,8 @@ struct Region {
 };
 std::vector<Region> g_regions;
 std::map<const void*, std::string> g_names;
+std::map<const void*, size_t> g_var_size;
+std::map<const void*, void*> g_var_mem;
 dim3s g_grid{}, g_block{};
 size_t g_shm = 0;
 void* g_stream = nullptr;
@@ -52,6 +54,7 @@ std::string demangle(const std::string& m) {
 
 extern "C" {
 // -- test controls ---------------------------------------------------------
+void stub_add_region(uintptr_t base, uintptr_t size);
 void stub_add_region(uintptr_t base, uintptr_t size) { g_regions.push_back(Region{base, size}); }
 void stub_open_log(const char* path) { g_log = fopen(path, "w"); }
 long stub_launches() { return g_launches; }
@@ -67,7 +70,22 @@ void __hipRegisterFunction(void**, const void* host_fun, char*, const char* devi
                            void*, void*, void*, int*) {
     g_names[host_fun] = device_name;
 }
-void __hipRegisterVar(void**, char*, char*, const char*, int, size_t, int, int) {}
+// Device variables: a host buffer of the variable's size stands in for it
+// once its address is asked for, and becomes a valid region.
+void __hipRegisterVar(void**, char* host_var, char*, const char*, int, size_t size, int, int) {
+    g_var_size[host_var] = size & 0xffffffffu;
+}
+int hipGetSymbolAddress(void** dev, const void* symbol) {
+    const auto it = g_var_size.find(symbol);
+    if (it == g_var_size.end()) return 1;
+    void*& mem = g_var_mem[symbol];
+    if (mem == nullptr) {
+        mem = calloc(1, it->second);
+        stub_add_region((uintptr_t)mem, it->second);
+    }
+    *dev = mem;
+    return 0;
+}
 int __hipPushCallConfiguration(dim3s grid, dim3s block, size_t shm, void* stream) {
     g_grid = grid;
     g_block = block;
@@ -82,12 +100,15 @@ int __hipPopCallConfiguration(dim3s* grid, dim3s* block, size_t* shm, void** str
     *stream = g_stream;
     return 0;
 }
-int hipLaunchKernel(const void* f, dim3s grid, dim3s block, void** args, size_t, void*) {
+constexpr size_t kLdsLimit = 160 * 1024;  // gfx950 LDS per work-group
+
+int hipLaunchKernel(const void* f, dim3s grid, dim3s block, void** args, size_t shm, void*) {
     ++g_launches;
     const std::string name = demangle(g_names.count(f) ? g_names[f] : std::string("?"));
     if (g_log) fprintf(g_log, "launch %s grid(%u,%u,%u) block(%u,%u,%u)\n", name.c_str(), grid.x, grid.y,
                        grid.z, block.x, block.y, block.z);
     if (grid.x == 0 || grid.y == 0 || grid.z == 0 || block.x == 0 || block.x > 1024) violation("launch shape", name);
+    if (shm > kLdsLimit) violation("dynamic LDS", name);
     // the parameter list of the kernel's demangled signature: every pointer
     // argument must point into a registered region
     const size_t lp = name.find('('), rp = name.rfind(')');
@@ -131,10 +152,13 @@ int hipGetDevice(int* d) {
     return 0;
 }
 int hipDeviceGetAttribute(int* v, int, int) {
-    *v = 160 * 1024;
+    *v = (int)kLdsLimit;
     return 0;
 }
-int hipFuncSetAttribute(const void*, int, int) { return 0; }
+int hipFuncSetAttribute(const void* f, int, int value) {
+    if (value < 0 || (size_t)value > kLdsLimit) violation("LDS limit", demangle(g_names[f]));
+    return 0;
+}
 int hipGetLastError() { return 0; }
 int hipEventCreate(void** e) {
     *e = (void*)(g_fake++);

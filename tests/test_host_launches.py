@@ -77,6 +77,38 @@ DRIVER = textwrap.dedent(r"""
     run([inputs.workload_pentagons(1024, 0.6)], 0, 1, _lib.QUEUE_FLAGS["global"])
     run([inputs.workload_pentagons(1024, 0.6)], 0, 1, _lib.QUEUE_FLAGS["register"])
     run([inputs.workload_pentagons(20000, 0.6)], 1, 1)   # multi-kernel cell-list build
+    run([inputs.workload_pentagons(4096, 0.6)] * 2, 1, 2)  # the headline replica: LDS near the limit
+    run([inputs.workload_pentagons(4096, 0.6)] * 2, 0, 2)
+    run(inputs.screening_batch(6, seed=2026, n_lo=3000, n_hi=4096), 1, 2)
+    # the scratch-free entry point: its workspace is the library's static array
+    def run_static(items, precision, path):
+        n = len(items)
+        sp_arr = (_lib.Species * n)()
+        keep = []
+        for r, (sp, N, L, pos, ori) in enumerate(items):
+            s = sp_arr[r]
+            s.dim, s.shape = sp["dim"], _lib.SHAPES[sp["shape"]]
+            if sp["shape"] != "disk":
+                v = np.ascontiguousarray(sp["verts"], dtype=np.float64)
+                keep.append(v)
+                s.n_verts, s.verts = v.shape[0], v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            s.diameter = sp.get("diameter", 0.0)
+            s.d, s.a, s.p_rot = sp["d"], sp["a"], sp["p_rot"]
+        a = _lib.InitArgs()
+        a.n_replicas, a.species = n, sp_arr
+        a.N = (ctypes.c_int32 * n)(*[i[1] for i in items])
+        a.L = (ctypes.c_double * n)(*[i[2] for i in items])
+        a.precision, a.path = precision, path
+        pos = np.concatenate([i[3].ravel() for i in items])
+        ori = np.concatenate([i[4].ravel() for i in items if i[0]["shape"] != "disk"] or [np.zeros(1)])
+        for buf in (pos, ori):
+            stub.stub_add_region(ctypes.c_uint64(buf.ctypes.data), ctypes.c_uint64(buf.nbytes))
+        a.pos, a.orient = pos.ctypes.data, ori.ctypes.data
+        st = (_lib.Stats * n)()
+        hip = ctypes.c_int32()
+        assert lib.hpmc_sweep_static(ctypes.byref(a), 3, 70, 1, st, ctypes.byref(hip)) == 0
+    run_static([inputs.workload_pentagons(700, 0.6), inputs.workload_disks_256()], 1, 2)
+    run_static([inputs.workload_disks_256()], 0, 1)
     print("launches", stub.stub_launches(), "violations", stub.stub_violations())
 """)
 
