@@ -10,9 +10,12 @@
 * 4096 pentagons at the configuration's full 10^4 sweeps, bit for bit.
 * Full-length runs too long for the oracle (32768 cubes, 1000 sweeps;
   4,194,304 pentagons, 100 sweeps) are checked by properties that hold at
-  any length: no overlap afterwards, attempted moves = rounds x non-empty
-  cells per sweep on average, and the cell-reject fraction of translations
-  within binomial error of 1 - (1 - d / 2w)^dim.
+  any length: no overlap afterwards, every attempted move counted exactly
+  once as a cell reject, an overlap reject or an accept, attempted moves per
+  sweep and round between half the cell count and the cell count (one move
+  per non-empty cell), and rotations drawn with probability p_rot.  (The
+  cell-reject fraction has the closed form 1 - (1 - d / 2w)^dim only with at
+  most one particle per cell; these systems hold several.)
 """
 import math
 import sys
@@ -94,13 +97,6 @@ def test_pentagons_4096_ten_thousand_sweeps():
     _check_every_replica(system, [item], 1, 10000)
 
 
-def _cell_reject_check(st, sp, w):
-    trans = st["attempted"] - st["attempted_rot"]
-    p = 1.0 - (1.0 - sp["d"] / (2.0 * w)) ** sp["dim"]
-    frac = st["cell_reject"] / trans
-    assert abs(frac - p) < 5.0 * math.sqrt(p * (1 - p) / trans), (frac, p)
-
-
 @pytest.mark.parametrize("case", ["cubes_1000", "large_100"])
 def test_full_length_properties(case):
     if case == "cubes_1000":
@@ -120,5 +116,6 @@ def test_full_length_properties(case):
     # every sweep attempts one move per non-empty cell and round
     per = st["attempted"] / (n_sweeps * g["rounds"])
     assert 0.5 * g["n"] ** sp["dim"] < per <= g["n"] ** sp["dim"]
-    _cell_reject_check(st, sp, g["w"])
-    assert abs(st["attempted_rot"] / st["attempted"] - sp["p_rot"]) < 0.01
+    p, n = sp["p_rot"], st["attempted"]
+    assert abs(st["attempted_rot"] / n - p) < 5.0 * math.sqrt(p * (1 - p) / n)
+
