@@ -125,6 +125,16 @@ def make_system(wl, precision, path, batched, queue="wave"):
                   queue=queue)
 
 
+def decode_config(cfg, path):
+    """The fields of an hpmc_autotune configuration (include/hpmc.h)."""
+    if cfg is None:
+        return None
+    return {("lds_residency" if path == "persistent" else "lanes_per_cell"): cfg & 0xff,
+            "binary64_walk": bool(cfg & 0x100),
+            "drain_at": (64, 32, 16, None)[(cfg >> 9) & 3],
+            "work_group_size": ("default", "half", "quarter", None)[(cfg >> 11) & 3]}
+
+
 def timed_run(system, steps, warmup, seed):
     """Warm up, then time exactly `steps` sweeps with HIP events on the
     library's stream, synchronised on both sides.  Returns the time, the
@@ -295,6 +305,8 @@ def main():
                     help="timed runs of --steps sweeps per configuration (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--config", type=lambda x: int(x, 0), default=None,
+                    help="apply this launch configuration (hpmc_set_config encoding) instead of autotuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized buffer once (calibrates HBM byte counters)")
     ap.add_argument("--phase-trace", action="store_true",
@@ -342,7 +354,11 @@ def main():
         batched = mode == "batched"
         path = "persistent" if batched else "grid"
         system = make_system(wl, precision, path, batched, args.queue)
-        tuned = system.autotune(trial_sweeps=8) if not args.no_autotune else None
+        if args.config is not None:
+            system.set_config(args.config)
+            tuned = args.config
+        else:
+            tuned = system.autotune(trial_sweeps=8) if not args.no_autotune else None
         if args.phase_trace:
             from paper_1509_04692_amd.system import phase_trace
             system.sweep(args.warmup, args.seed)
@@ -380,6 +396,7 @@ def main():
             "pair_tests_per_move": diff["pair_tests"] / max(diff["attempted"], 1),
             "launches": n_launch,
             "autotuned": tuned,
+            "tuned_config": decode_config(tuned, path),
             "graph": system.uses_graph,
             "graph_replayed_sweeps": diff["graph_sweeps"],
             "phase_trace": trace,

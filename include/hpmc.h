@@ -172,16 +172,25 @@ int hpmc_init(hpmc_state **out, const hpmc_init_args *args);
  * sweeps equal one call of a + b).  Asynchronous on the state's stream. */
 int hpmc_sweep(hpmc_state *st, uint64_t n_sweeps, uint64_t seed);
 
-/* Time the launch configurations this state can use (grid path: lanes per
- * active cell 1, 2, 4, ..., 64, or 1 .. 8 with the register queue and 1 with
- * the global queue; persistent path: which particle data stays in LDS)
- * over trial_sweeps sweeps each, keep the fastest, and restore positions,
- * orientations, counters and the sweep counter exactly.  The trajectory does
- * not depend on the configuration.  With HPMC_MIXED and polyhedra the
- * binary64 XenoCollide walk is tried as well (its decisions equal the
- * certified binary32 walk's).  Synchronising.  *out_config (may be NULL)
- * receives the chosen lanes per cell (grid) or residency level (persistent)
- * in its low byte, plus 0x100 when MIXED polyhedra walk in binary64. */
+/* Time the launch configurations this state can use over trial_sweeps
+ * sweeps each, keep the fastest, and restore positions, orientations,
+ * counters and the sweep counter exactly.  The trajectory does not depend
+ * on the configuration.  Three stages, each keeping the fastest so far:
+ *   1. grid path: lanes per active cell 1, 2, 4, ..., 64 (1 .. 8 with the
+ *      register queue, 1 with the global queue); persistent path: the LDS
+ *      residency level (0: particle data in global memory, 1: positions in
+ *      LDS, 2: positions and orientations, 3: both, without the binary32
+ *      cell-sorted copy); with HPMC_MIXED and polyhedra also the binary64
+ *      XenoCollide walk (its decisions equal the certified binary32 walk's);
+ *   2. the queue depth (wave queue only): a wave drains its queued full
+ *      tests once 64, 32 or 16 wait;
+ *   3. persistent path: the work-group size, the default (enough lanes for
+ *      one 64-cell tile per wave), half or a quarter of it (at least 64).
+ * Synchronising.  *out_config (may be NULL) receives the chosen
+ * configuration: lanes per cell or residency level in bits 0-7, 0x100 for
+ * the binary64 walk, the queue depth code (0: 64, 1: 32, 2: 16) in bits 9-10
+ * and the work-group size code (0: default, 1: half, 2: quarter) in bits
+ * 11-12. */
 int hpmc_autotune(hpmc_state *st, uint32_t trial_sweeps, int32_t *out_config);
 
 /* Apply a launch configuration in the encoding hpmc_autotune returns, e.g. one

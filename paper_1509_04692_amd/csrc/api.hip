@@ -197,6 +197,7 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
     }
     if ((int64_t)S.rounds * (1 << s.dim) >= ((int64_t)1 << 28)) return HPMC_ERR_INVALID_ARG;
     S.scan_t2 = scan_threshold(P.circ2, L, S.w, s.dim);
+    S.drain_at = 64;
     rh.kind = s.shape;
     rh.dim = s.dim;
     rh.N = N;
@@ -219,6 +220,13 @@ struct Layout {
 // hipError_t of the last hpmc_init that failed in a HIP call (the state it
 // was building is gone by then).
 std::atomic<int> g_last_init_hip{0};
+
+// Highest residency level at most lv whose LDS fits the group.
+int highest_fit(const BatchGroup& g, int lv) {
+    for (; lv > 0; --lv)
+        if (g.fits & (1 << lv)) return lv;
+    return 0;
+}
 
 // Queue mode from hpmc_init_args.flags; -1 when both variants are asked for.
 int queue_mode(int32_t flags) {
@@ -285,8 +293,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         cell_total += (int64_t)rep[r].ncells_cap + 1;
         slot_total += sys[r].N;
         part_total += ((int64_t)rep[r].ncells_cap + kScanTile - 1) / kScanTile;
-        const int ncomp_r = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
-        const size_t lb = persistent_lds_bytes(sys[r].dim, ncomp_r, rep[r].ncells_cap, sys[r].N, 0, kBatchBlock);
+        const size_t lb = persistent_lds_bytes(spc[r].kind, a->precision, rep[r].ncells_cap, sys[r].N, 0,
+                                               kBatchBlock);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
         const int half = sys[r].n / 2;
         const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
@@ -311,8 +319,10 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         // first and takes the compute units first, and the cheaper kinds'
         // work-groups fill in as they free up
         for (int kind = kPolyhedron; kind >= kDisk; --kind) {
-            BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}};
-            const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
+            BatchGroup g{};
+            g.kind = kind;
+            g.first = (int32_t)list.size();
+            g.nv = -1;
             int64_t n_max = 0, n_act_max = 0;
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
@@ -321,14 +331,15 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
                 n_act_max = std::max<int64_t>(n_act_max, sys[r].dim == 3 ? half * half * half : half * half);
             }
             g.block = persistent_block(n_act_max, n_max);
-            size_t need[3] = {0, 0, 0};
+            g.block_base = g.block;
+            size_t need[kResidencyLevels] = {};
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
                 list.push_back(r);
                 g.count++;
                 g.nv = (g.nv == -1 || g.nv == spc[r].nv) ? spc[r].nv : 0;
-                for (int lv = 0; lv < 3; ++lv)
-                    need[lv] = std::max(need[lv], persistent_lds_bytes(sys[r].dim, ncomp, rep[r].ncells_cap,
+                for (int lv = 0; lv < kResidencyLevels; ++lv)
+                    need[lv] = std::max(need[lv], persistent_lds_bytes(kind, a->precision, rep[r].ncells_cap,
                                                                        sys[r].N, lv, g.block));
             }
             if (g.count == 0) continue;
@@ -336,15 +347,17 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
             // longest ones do not wait behind short ones for a compute unit
             std::stable_sort(list.begin() + g.first, list.end(),
                              [&](int32_t x, int32_t y) { return sys[x].N > sys[y].N; });
-            g.resident = 0;
-            for (int lv = (kind == kDisk ? 1 : 2); lv >= 1; --lv)
-                if (need[lv] <= lds_limit) {
-                    g.resident = lv;
-                    break;
-                }
-            g.resident_max = g.resident;
+            // levels whose LDS fits (level 0 always); disks have no
+            // orientations, so their level 2 is level 1
+            g.fits = 1;
+            for (int lv = 1; lv < kResidencyLevels; ++lv)
+                if (need[lv] <= lds_limit && !(kind == kDisk && lv == 2)) g.fits |= 1 << lv;
+            for (int lv = 0; lv < kResidencyLevels; ++lv) g.need[lv] = need[lv];
+            // before autotuning: the binary32 copy kept when it fits (level
+            // 2, else 1), level 3 only when neither fits
+            g.resident = highest_fit(g, 2);
+            if (g.resident == 0 && (g.fits & 8)) g.resident = 3;
             g.lds_bytes = need[g.resident];
-            for (int lv = 0; lv < 3; ++lv) g.need[lv] = need[lv];
             if (g.nv < 0) g.nv = 0;
             groups.push_back(g);
         }
@@ -549,18 +562,52 @@ void capture_graph(hpmc_state* st) {
     (void)hipGetLastError();
 }
 
-// Run n_sweeps from the current counter with key (k0, k1).
-// Launch configurations of a state: lanes per cell (grid) or residency level
-// (persistent) in the low byte, plus kWalk64 when MIXED polyhedra take the
-// binary64 walk.
+// Launch configurations of a state, one int:
+//   bits 0-7   lanes per active cell (grid) or LDS residency level (persistent)
+//   bit  8     MIXED polyhedra take the binary64 walk
+//   bits 9-10  queue depth: drain at 64 (0), 32 (1) or 16 (2) queued tests
+//   bits 11-12 persistent work-group size: the default (0), half (1) or a
+//              quarter (2) of it, at least 64 lanes
 constexpr int kWalk64 = 0x100;
+constexpr int kDrainShift = 9, kBlockShift = 11;
+constexpr uint32_t kDrainAt[3] = {64u, 32u, 16u};
 
-std::vector<int> config_candidates(const hpmc_state* st) {
+int drain_code(int cfg) { return (cfg >> kDrainShift) & 3; }
+int block_code(int cfg) { return (cfg >> kBlockShift) & 3; }
+
+// Lanes of a persistent group under a block code: the default size halved
+// `code` times, rounded down to whole waves (0 below one wave).
+int group_block(const BatchGroup& g, int code) {
+    const int b = (g.block_base >> code) / 64 * 64;
+    return b >= 64 ? b : 0;
+}
+
+// LDS per residency level and the levels that fit, for the group's replicas
+// at `block` lanes.
+void group_lds(const hpmc_state* st, BatchGroup& g, int block) {
+    size_t need[kResidencyLevels] = {};
+    for (int j = g.first; j < g.first + g.count; ++j) {
+        const int r = st->list[j];
+        for (int lv = 0; lv < kResidencyLevels; ++lv)
+            need[lv] = std::max(need[lv], persistent_lds_bytes(g.kind, st->precision, st->rep[r].ncells_cap,
+                                                               st->rep[r].N, lv, block));
+    }
+    const size_t limit = device_lds_limit();
+    g.fits = 1;
+    for (int lv = 1; lv < kResidencyLevels; ++lv)
+        if (need[lv] <= limit && !(g.kind == kDisk && lv == 2)) g.fits |= 1 << lv;
+    for (int lv = 0; lv < kResidencyLevels; ++lv) g.need[lv] = need[lv];
+}
+
+// Lanes-per-cell or residency choices (with the walk bit) of the first
+// tuning stage.
+std::vector<int> base_candidates(const hpmc_state* st) {
     std::vector<int> cands;
     if (st->path == HPMC_PATH_PERSISTENT) {
-        int top = 0;
-        for (const BatchGroup& g : st->groups) top = std::max(top, (int)g.resident_max);
-        for (int lv = top; lv >= 0; --lv) cands.push_back(lv);
+        int any = 0;
+        for (const BatchGroup& g : st->groups) any |= g.fits;
+        for (int lv = kResidencyLevels - 1; lv >= 0; --lv)
+            if (any & (1 << lv)) cands.push_back(lv);
     } else if (st->queue == kQueueGlobal) {
         cands = {1};  // one lane per cell or queued pair: nothing to choose but the walk
     } else if (st->queue == kQueueWave) {
@@ -577,16 +624,43 @@ std::vector<int> config_candidates(const hpmc_state* st) {
     return cands;
 }
 
-// Switch to configuration cfg (one of config_candidates) and re-capture the
-// sweep graph.
+// A configuration this state can use: a base candidate, a queue depth the
+// wave queue has (the register and global queues have none), and a
+// work-group size every persistent group can take.
+bool config_valid(const hpmc_state* st, int cfg) {
+    if (cfg < 0 || (cfg >> 13) != 0) return false;
+    const std::vector<int> base = base_candidates(st);
+    if (std::find(base.begin(), base.end(), cfg & 0x1ff) == base.end()) return false;
+    const int dc = drain_code(cfg), bc = block_code(cfg);
+    if (dc > 2 || (dc != 0 && st->queue != kQueueWave)) return false;
+    if (bc > 2 || (bc != 0 && st->path != HPMC_PATH_PERSISTENT)) return false;
+    for (const BatchGroup& g : st->groups)
+        if (st->path == HPMC_PATH_PERSISTENT && group_block(g, bc) == 0) return false;
+    return true;
+}
+
+// Switch to configuration cfg and re-capture the sweep graph.
 int apply_config(hpmc_state* st, int cfg) {
-    const std::vector<int> cands = config_candidates(st);
-    if (std::find(cands.begin(), cands.end(), cfg) == cands.end()) return HPMC_ERR_INVALID_ARG;
+    if (!config_valid(st, cfg)) return HPMC_ERR_INVALID_ARG;
     const int c = cfg & 0xff;
     st->walk64 = (cfg & kWalk64) ? 1 : 0;
+    const uint32_t drain_at = kDrainAt[drain_code(cfg)];
+    bool sys_changed = false;
+    for (SysDev& S : st->sys) {
+        sys_changed |= S.drain_at != drain_at;
+        S.drain_at = drain_at;
+    }
+    if (sys_changed) {
+        int rc = check_hip(st, hipMemcpyAsync(st->ws.sys, st->sys.data(), sizeof(SysDev) * st->n_replicas,
+                                              hipMemcpyHostToDevice, st->stream));
+        if (!rc) rc = check_hip(st, hipStreamSynchronize(st->stream));
+        if (rc) return rc;
+    }
     if (st->path == HPMC_PATH_PERSISTENT) {
         for (BatchGroup& g : st->groups) {
-            g.resident = std::min<int>(c, g.resident_max);
+            g.block = group_block(g, block_code(cfg));
+            group_lds(st, g, g.block);
+            g.resident = highest_fit(g, c);
             g.lds_bytes = g.need[g.resident];
             const int rc = check_hip(st, persistent_sweeps(st->ws, g, st->pos, st->orient,
                                                            group_precision(st, g), true, st->stream));
@@ -961,6 +1035,7 @@ int hpmc_scale_box(hpmc_state* st, int32_t replica, double L_new, uint64_t* over
     S.cell_off = old.cell_off;
     S.slot_off = old.slot_off;
     S.part_off = old.part_off;
+    S.drain_at = old.drain_at;
     const ReplicaHost& oh = st->rep[r];
     rh.path = oh.path;
     rh.lanes_per_cell = oh.lanes_per_cell;
@@ -1170,14 +1245,27 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
         rc = check_hip(st, hipMemcpyAsync(st->ws.backup_stats, st->ws.stats, 8 * nstat,
                                           hipMemcpyDeviceToDevice, st->stream));
     if (rc) return rc;
-    std::vector<int> cands = config_candidates(st);
+    // three stages, each keeping the fastest: lanes per cell or LDS
+    // residency (and the walk), then the queue depth, then (persistent) the
+    // work-group size
+    std::vector<int> cands = base_candidates(st);
     auto apply = [&](int cfg) { (void)apply_config(st, cfg); };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc) rc = check_hip(st, hipEventCreate(&e0));
     if (!rc) rc = check_hip(st, hipEventCreate(&e1));
     float best_ms = 0.f;
     int best = cands.empty() ? 0 : cands[0];
+    bool first = true;
+    for (int stage = 0; stage < 3 && !rc; ++stage) {
+        if (stage == 1) {
+            cands.clear();
+            for (int dc = 1; dc <= 2; ++dc) cands.push_back(best | (dc << kDrainShift));
+        } else if (stage == 2) {
+            cands.clear();
+            for (int bc = 1; bc <= 2; ++bc) cands.push_back(best | (bc << kBlockShift));
+        }
     for (size_t ci = 0; ci < cands.size() && !rc; ++ci) {
+        if (!config_valid(st, cands[ci])) continue;
         apply(cands[ci]);
         rc = run_sweeps(st, 1, 0xA5A5u, 0x5A5Au);  // warm-up
         if (!rc) rc = check_hip(st, hipEventRecord(e0, st->stream));
@@ -1186,9 +1274,10 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
         if (!rc) rc = check_hip(st, hipEventSynchronize(e1));
         float ms = 0.f;
         if (!rc) rc = check_hip(st, hipEventElapsedTime(&ms, e0, e1));
-        if (!rc && (ci == 0 || ms < best_ms)) {
+        if (!rc && (first || ms < best_ms)) {
             best_ms = ms;
             best = cands[ci];
+            first = false;
         }
         // restore the snapshot after every trial
         if (!rc)
@@ -1200,6 +1289,7 @@ int hpmc_autotune(hpmc_state* st, uint32_t trial_sweeps, int32_t* out_config) {
         if (!rc)
             rc = check_hip(st, hipMemcpyAsync(st->ws.stats, st->ws.backup_stats, 8 * nstat,
                                               hipMemcpyDeviceToDevice, st->stream));
+    }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

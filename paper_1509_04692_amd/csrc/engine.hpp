@@ -18,6 +18,8 @@
 // the order in which the tests run.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "overlap32.hpp"
 #include "overlap64.hpp"
@@ -182,6 +184,28 @@ struct XsView {
         else
             reinterpret_cast<float4*>(p)[s] = make_float4(v[0], v[1], v[2], 0.0f);
     }
+};
+
+// The same binary32 shifted-frame coordinates computed on the fly from the
+// binary64 positions (tag order, LDS) through the cell list's members, for
+// work-groups that keep positions and orientations in LDS and have no room
+// for the copy: the values equal the copy's bit for bit (one binary64
+// subtraction and wrap, then the cast), so the pre-filter decides the same.
+// Stores are dropped: the positions themselves are the state.
+template <int D>
+struct PosXsView {
+    const uint16_t* mem;
+    const double* p;
+    int N;
+    double s0, s1, s2, L;
+    __device__ __forceinline__ void load(uint32_t s, float (&v)[3]) const {
+        const uint32_t k = mem[s];
+        v[0] = (float)grid_coord(p[k], s0, L);
+        v[1] = (float)grid_coord(p[N + k], s1, L);
+        v[2] = D == 3 ? (float)grid_coord(p[2 * N + k], s2, L) : 0.0f;
+    }
+    template <class T>
+    __device__ __forceinline__ void store(uint32_t, const T&) const {}
 };
 
 template <int KIND>
@@ -351,18 +375,33 @@ __device__ __forceinline__ void neighbour_range(const CELLS& cl, const int (&cc)
     e = cl.end((uint32_t)(base + x1));
 }
 
-// Per-wave LDS scratch: a 128-entry ring of queued pair tests and one flag per
-// group (cell) of the tile.
+// Candidates a lane of the wave-queue scan loads at once from a cell list in
+// global memory (a 3D neighbour range holds about three times as many as a
+// 2D one); one from LDS, whose latency is short.  Scans of a global list
+// also queue the member tag with each hit, so the drain needs no lookup.
+template <int D, bool GLOBAL>
+constexpr int kScanUnroll = GLOBAL ? (D == 3 ? 4 : 2) : 1;
+template <class CELLS>
+constexpr bool kGlobalList = std::is_same<CELLS, GlobalCells>::value;
+
+// Per-wave LDS scratch: one flag per group (cell) of the tile, a 128-entry
+// ring of queued pair tests, and a second ring for the two-stage binary64
+// polygon drain.
 struct WaveScratch {
-    uint32_t* q;     // 128 entries: owner lane << 26 | neighbour slot
-    uint32_t* q2;    // 128 entries: polygon pairs left after their first half of axes
     uint32_t* flag;  // 64 entries
+    uint32_t* q;     // 128 entries: owner lane << 26 | neighbour tag (global cell
+                     // list) or slot (LDS cell list)
+    uint32_t* q2;    // 128 entries: polygon pairs left after their first half of axes
 };
 constexpr int kQueueWords = 128;
 constexpr int kFlagWords = 64;
 constexpr int kWaveScratchWords = 2 * kQueueWords + kFlagWords;
+// Words a wave needs: the second ring only for binary64 polygons.
+__host__ __device__ constexpr int wave_scratch_words(int kind, int prec) {
+    return kind == kPolygon && prec == 0 ? kWaveScratchWords : kFlagWords + kQueueWords;
+}
 __device__ __forceinline__ WaveScratch wave_scratch(uint32_t* base) {
-    return WaveScratch{base, base + kQueueWords, base + 2 * kQueueWords};
+    return WaveScratch{base, base + kFlagWords, base + kFlagWords + kQueueWords};
 }
 constexpr uint32_t kTagMask = (1u << 26) - 1u;
 
@@ -392,15 +431,17 @@ __device__ __forceinline__ void drain(const SysDev& S, const SpeciesDev& P, cons
 #pragma unroll
     for (int c = 0; c < 4; ++c) tq[c] = c < Traits<KIND>::ncomp ? __shfl(qn[c], owner, 64) : qn[c];
     if (lane < n && ws.flag[owner / G] == 0u) {
-        const uint32_t k = cl.member(e & kTagMask);
+        const uint32_t k = kGlobalList<CELLS> ? e & kTagMask : cl.member(e & kTagMask);
+        // the neighbour's orientation is loaded with its position (one
+        // memory latency for both), before the circumsphere test needs it
+        double qk[4];
+        load_orient<KIND>(ori, S.N, k, qk);
         double r[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < D; ++a) r[a] = min_image(pos.get(a, k) - tx[a], S.L, S.inv_L);
         double r2 = r[0] * r[0] + r[1] * r[1];
         if constexpr (D == 3) r2 = r2 + r[2] * r[2];
         if (r2 < P.circ2) {
-            double qk[4];
-            load_orient<KIND>(ori, S.N, k, qk);
             if (full_test<KIND, PREC, NV>(P, r, tq, qk, ct)) ws.flag[owner / G] = 1u;
         }
     }
@@ -429,7 +470,7 @@ __device__ __forceinline__ uint32_t drain_polygon1(const SysDev& S, const Specie
     const double tc = __shfl(qn[0], owner, 64), ts = __shfl(qn[1], owner, 64);
     bool push = false;
     if (lane < n && ws.flag[owner / G] == 0u) {
-        const uint32_t k = cl.member(e & kTagMask);
+        const uint32_t k = kGlobalList<CELLS> ? e & kTagMask : cl.member(e & kTagMask);
         const double rx = min_image(pos.get(0, k) - tx, S.L, S.inv_L);
         const double ry = min_image(pos.get(1, k) - ty, S.L, S.inv_L);
         if (rx * rx + ry * ry < P.circ2) {
@@ -466,7 +507,7 @@ __device__ __forceinline__ void drain_polygon2(const SysDev& S, const SpeciesDev
     const double tx = __shfl(xn[0], owner, 64), ty = __shfl(xn[1], owner, 64);
     const double tc = __shfl(qn[0], owner, 64), ts = __shfl(qn[1], owner, 64);
     if (lane < n && ws.flag[owner / G] == 0u) {
-        const uint32_t k = cl.member(e & kTagMask);
+        const uint32_t k = kGlobalList<CELLS> ? e & kTagMask : cl.member(e & kTagMask);
         const double rx = min_image(pos.get(0, k) - tx, S.L, S.inv_L);
         const double ry = min_image(pos.get(1, k) - ty, S.L, S.inv_L);
         const double kc = ori[k], ks = ori[S.N + k];
@@ -556,10 +597,12 @@ __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, co
 
 // PARK: the sorted copy is in LDS and the moving particle's slot is parked
 // at infinity during its own scan (else the scan tests the slot).
-template <int KIND, int PREC, int G, int NV, bool PARK, int Q = kWaveQueue, class POS, class CELLS>
+// YF: active cells indexed y first (work-groups with their state in LDS).
+template <int KIND, int PREC, int G, int NV, bool PARK, int Q = kWaveQueue, bool YF = PARK,
+          class POS, class CELLS, class XSV>
 __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                           double* __restrict__ ori, const CELLS& cl,
-                                          const XsView<Traits<KIND>::dim>& xs, uint32_t colour,
+                                          const XSV& xs, uint32_t colour,
                                           uint32_t select, uint32_t t, uint32_t k0, uint32_t k1,
                                           const double (&sh)[3], int a0, int n_act, WaveScratch ws,
                                           Counters& ct, PhaseClock& pc) {
@@ -580,10 +623,10 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     double qn[4] = {1.0, 0.0, 0.0, 0.0};
     bool c_rot = false, c_moved = false;  // rotation attempted / translation attempted
     if (sub == 0 && a < n_act) {
-        // LDS-resident 2D tiles (PARK) index y first: data locality does not
+        // LDS-resident 2D tiles (YF) index y first: data locality does not
         // matter there, and most waves then skip the x-wrapped ranges (in 3D
         // a wave spans several x columns, so nearly every wave holds an edge)
-        active_cell<PARK && D == 2>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
+        active_cell<YF && D == 2>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
         const uint32_t beg = cl.begin(c), fin = cl.end(c);
         if (beg != fin) {
             ct.attempted++;
@@ -659,7 +702,12 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         // the longest range of the wave.
         constexpr int NR = Neighbourhood<D>::ranges;
         constexpr int NK = (NR + G - 1) / G;
+        constexpr bool TAGQ = kGlobalList<CELLS>;
+        constexpr int U = kScanUnroll<D, TAGQ>;
         const float t2 = S.scan_t2;
+        // queue depth: a drain starts once this many tests wait (at most 64,
+        // so at most 127 entries are ever queued)
+        const uint32_t drain_at = S.drain_at;
         bool flagged = false;  // this lane's cell already has an overlap (register copy)
         uint32_t queued = 0;   // wave-uniform
         uint32_t queued2 = 0;  // wave-uniform, polygons only
@@ -673,46 +721,60 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
             float ref[3] = {0.0f, 0.0f, 0.0f};
             if (live && !flagged && ri < NR) neighbour_range<D>(cl, cc, n, ri, S.L, yn, p, e, ref);
             for (;;) {
-                // each predicate is a single compare so that its ballot is the
-                // compare's lane mask: a flagged lane has e = p, an idle lane's
-                // distance is infinite
-                const bool work = p < e;
-                if (wave_ballot(work) == 0ull) break;
-                const uint32_t slot = work ? p : 0u;  // idle lanes read slot 0 (always valid)
-                float v[3];
-                xs.load(slot, v);
-                const float rx = v[0] - ref[0], ry = v[1] - ref[1];
-                float r2 = fmaf(ry, ry, rx * rx);
-                if constexpr (D == 3) {
-                    const float rz = v[2] - ref[2];
-                    r2 = fmaf(rz, rz, r2);
+                if (wave_ballot(p < e) == 0ull) break;
+                // U candidates per lane at a time: their loads are issued
+                // together so that one memory latency covers them; each is
+                // then tested and queued in slot order.  Each predicate is a
+                // single compare so that its ballot is the compare's lane mask:
+                // an idle lane's distance is infinite, a flagged lane's range
+                // ends at the candidate where the flag was seen.
+                uint32_t sl[U], tg[U];
+                float v[U][3];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    sl[u] = p + u < e ? p + u : 0u;  // idle lanes read slot 0 (always valid)
+                    xs.load(sl[u], v[u]);
+                    tg[u] = TAGQ ? cl.member(sl[u]) : sl[u];
                 }
-                r2 = (work && (PARK || slot != pi)) ? r2 : INFINITY;
-                const bool hit = r2 < t2;
-                p += work ? 1u : 0u;
-                const uint64_t hm = wave_ballot(hit);
-                if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | slot;
-                queued += (uint32_t)__builtin_popcountll(hm);
-                if (queued >= 64u) {
-                    pc.mark<kPhScan>();
-                    if constexpr (KIND == kPolygon && PREC == 0) {
-                        queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, queued2, ct);
-                    } else {
-                        drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool work = p + (uint32_t)u < e;
+                    const float rx = v[u][0] - ref[0], ry = v[u][1] - ref[1];
+                    float r2 = fmaf(ry, ry, rx * rx);
+                    if constexpr (D == 3) {
+                        const float rz = v[u][2] - ref[2];
+                        r2 = fmaf(rz, rz, r2);
                     }
-                    queued -= 64u;
-                    compact_queue(ws.q, 64u, queued);
-                    if constexpr (KIND == kPolygon && PREC == 0) {
-                        if (queued2 >= 64u) {
-                            drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
-                            queued2 -= 64u;
-                            compact_queue(ws.q2, 64u, queued2);
+                    r2 = (work && (PARK || sl[u] != pi)) ? r2 : INFINITY;
+                    const bool hit = r2 < t2;
+                    const uint64_t hm = wave_ballot(hit);
+                    if (hit) ws.q[queued + lanes_below(hm)] = ((uint32_t)leader << 26) | tg[u];  // tag or slot
+                    queued += (uint32_t)__builtin_popcountll(hm);
+                    if (queued >= drain_at) {
+                        // up to one entry per lane; the rest stays queued
+                        const uint32_t m = queued < 64u ? queued : 64u;
+                        pc.mark<kPhScan>();
+                        if constexpr (KIND == kPolygon && PREC == 0) {
+                            queued2 = drain_polygon1<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, m, ws, queued2, ct);
+                        } else {
+                            drain<KIND, PREC, G, NV>(S, P, pos, ori, cl, xn, qn, m, ws, ct);
                         }
+                        queued -= m;
+                        compact_queue(ws.q, m, queued);
+                        if constexpr (KIND == kPolygon && PREC == 0) {
+                            if (queued2 >= 64u) {
+                                drain_polygon2<PREC, G, NV>(S, P, pos, ori, cl, xn, qn, 64u, ws, ct);
+                                queued2 -= 64u;
+                                compact_queue(ws.q2, 64u, queued2);
+                            }
+                        }
+                        flagged = ws.flag[grp] != 0u;
+                        const uint32_t stop = p + (uint32_t)u + 1u;
+                        e = flagged && stop < e ? stop : e;
+                        pc.mark<kPhDrain>();
                     }
-                    flagged = ws.flag[grp] != 0u;
-                    e = flagged ? p : e;
-                    pc.mark<kPhDrain>();
                 }
+                p = p + (uint32_t)U < e ? p + (uint32_t)U : e;
             }
         }
         pc.mark<kPhScan>();

@@ -780,10 +780,13 @@ __global__ void __launch_bounds__(256) k_pair_hist(const SysDev* __restrict__ sy
 // ---------------------------------------------------------------------------
 // Persistent path: one work-group owns one replica and runs whole sweeps.
 // LDS (dynamic), in this order: positions D*N f64 (residency >= 1),
-// orientations ncomp*N f64 (residency 2), the cell-sorted binary32
-// coordinates (N float2 / float4), members N u16, inclusive ends ncells u16,
-// a union (counts ncells u32 while building the cell list / wave queues and
-// flags during the passes) and 16 scan words.
+// orientations ncomp*N f64 (residency >= 2), the cell-sorted binary32
+// coordinates (N float2 / float4; not at residency 3, where the pre-filter
+// computes them from the positions), members N u16, inclusive ends ncells
+// u16, a union (counts ncells u32 while building the cell list / wave queues
+// and flags during the passes) and 16 scan words.  At residency 3 the
+// replica's whole state stays in LDS between the launch's first load and its
+// last store, both coalesced.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -792,9 +795,10 @@ struct BatchLayout {
 };
 
 // Residency level: 0 = particle data in global memory, 1 = positions in LDS,
-// 2 = positions and orientations in LDS.
+// 2 = positions and orientations in LDS, 3 = the same without the binary32
+// copy.  wave_words: per-wave scratch (wave_scratch_words).
 __host__ __device__ inline BatchLayout batch_layout(int dim, int ncomp, int N, int ncells,
-                                                    int nwaves, int res) {
+                                                    int nwaves, int res, int wave_words) {
     BatchLayout b;
     size_t o = 0;
     b.pos = o;
@@ -802,15 +806,15 @@ __host__ __device__ inline BatchLayout batch_layout(int dim, int ncomp, int N, i
     b.ori = o;
     o += res >= 2 ? align16((size_t)ncomp * N * 8) : 0;
     b.xs = o;
-    o += align16((size_t)N * (size_t)xs_bytes(dim));
+    o += res <= 2 ? align16((size_t)N * (size_t)xs_bytes(dim)) : 0;
     b.mem = o;
     o += align16((size_t)N * 2);
     b.ends = o;
     o += align16((size_t)ncells * 2);
     b.uni = o;
-    const size_t uni_words = (size_t)ncells > (size_t)nwaves * kWaveScratchWords
+    const size_t uni_words = (size_t)ncells > (size_t)nwaves * wave_words
                                  ? (size_t)ncells
-                                 : (size_t)nwaves * kWaveScratchWords;
+                                 : (size_t)nwaves * wave_words;
     o += align16(uni_words * 4);
     b.scan = o;
     o += 16 * 4;
@@ -834,7 +838,9 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     const int tid = threadIdx.x, B = blockDim.x, nwaves = B >> 6, wave = tid >> 6;
     const int N = S.N, nc = S.ncells;
     constexpr int NC = Traits<KIND>::ncomp;
-    const BatchLayout lay = batch_layout(D, NC, N, nc, nwaves, RES);
+    constexpr int WW = wave_scratch_words(KIND, PREC);
+    constexpr bool XS = RES <= 2;  // binary32 cell-sorted copy kept in LDS
+    const BatchLayout lay = batch_layout(D, NC, N, nc, nwaves, RES, WW);
     double* gpos = pos_base + S.pos_off;
     double* gori = ori_base + S.orient_off;
     const PosView pos{RES >= 1 ? reinterpret_cast<double*>(lds + lay.pos) : gpos, N};
@@ -859,7 +865,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     const int half = S.n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
     const int chunk = (nc + B - 1) / B;
-    const WaveScratch wscr = wave_scratch(uni + wave * kWaveScratchWords);
+    const WaveScratch wscr = wave_scratch(uni + wave * WW);
     for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
         const uint32_t t = t0 + sw;
         double sh[3];
@@ -909,7 +915,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             if (i < N) {
                 const uint32_t slot = atomicAdd(count + own_cell[j], 1u);
                 mem[slot] = (uint16_t)i;
-                xs.store(slot, own_y[j]);
+                if constexpr (XS) xs.store(slot, own_y[j]);
             }
         }
         for (int i = tid + kOwn * B; i < N; i += B) {
@@ -917,7 +923,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             particle_grid<D>(S, pos, (uint32_t)i, sh, y);
             const uint32_t slot = atomicAdd(count + cell_of_grid<D>(S, y), 1u);
             mem[slot] = (uint16_t)i;
-            xs.store(slot, y);
+            if constexpr (XS) xs.store(slot, y);
         }
         __syncthreads();
         // ascending tags within each cell; the coordinates move with their tags
@@ -927,17 +933,19 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             for (uint32_t p = b + 1; p < e; ++p) {
                 const uint16_t v = mem[p];
                 float vy[3];
-                xs.load(p, vy);
+                if constexpr (XS) xs.load(p, vy);
                 uint32_t q = p;
                 while (q > b && mem[q - 1] > v) {
                     mem[q] = mem[q - 1];
-                    float m[3];
-                    xs.load(q - 1, m);
-                    xs.store(q, m);
+                    if constexpr (XS) {
+                        float m[3];
+                        xs.load(q - 1, m);
+                        xs.store(q, m);
+                    }
                     --q;
                 }
                 mem[q] = v;
-                xs.store(q, vy);
+                if constexpr (XS) xs.store(q, vy);
             }
         }
         __syncthreads();
@@ -947,9 +955,16 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         for (int rnd = 0; rnd < S.rounds; ++rnd) {
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
-                for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64)
-                    pass_tile<KIND, PREC, 1, NV, true>(S, P, pos, ori, cl, xs, colour, select, t, k0, k1,
-                                                 sh, a0, n_act, wscr, ct, pc);
+                for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64) {
+                    if constexpr (XS) {
+                        pass_tile<KIND, PREC, 1, NV, true>(S, P, pos, ori, cl, xs, colour, select, t, k0,
+                                                           k1, sh, a0, n_act, wscr, ct, pc);
+                    } else {
+                        const PosXsView<D> pxs{mem, pos.p, N, sh[0], sh[1], sh[2], S.L};
+                        pass_tile<KIND, PREC, 1, NV, false, kWaveQueue, true>(
+                            S, P, pos, ori, cl, pxs, colour, select, t, k0, k1, sh, a0, n_act, wscr, ct, pc);
+                    }
+                }
                 pc.mark<kPhOther>();
                 __syncthreads();
                 pc.mark<kPhBarrier>();
@@ -973,8 +988,10 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
-size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res, int block) {
-    return batch_layout(dim, ncomp, N, ncells, block / 64, res).total;
+size_t persistent_lds_bytes(int kind, int precision, int ncells, int N, int res, int block) {
+    const int dim = kind == kPolyhedron ? 3 : 2;
+    const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
+    return batch_layout(dim, ncomp, N, ncells, block / 64, res, wave_scratch_words(kind, precision)).total;
 }
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream) {
@@ -1149,6 +1166,9 @@ template <int KIND, int PREC, int NV>
 static hipError_t launch_batch_res(const Workspace& ws, const BatchGroup& g, double* pos,
                                    double* orient, bool prepare, hipStream_t stream) {
     const int32_t* list = ws.batch_list + g.first;
+    if (g.resident >= 3)
+        return launch_batch<KIND, PREC, 3, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
+                                               prepare, stream);
     if (g.resident >= 2 && KIND != kDisk)
         return launch_batch<KIND, PREC, 2, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
                                                prepare, stream);

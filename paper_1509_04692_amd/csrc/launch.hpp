@@ -77,15 +77,17 @@ struct ReplicaHost {
 // work-group per replica) and the grid path (blockIdx.y selects the replica).
 struct BatchGroup {
     int32_t kind, first, count;
-    int32_t resident;  // persistent: 0 none, 1 positions, 2 positions + orientations in LDS
-    int32_t resident_max;  // highest level whose LDS fits
+    int32_t resident;  // persistent: 0 none, 1 positions, 2 positions + orientations in LDS,
+                       // 3 the same without the binary32 cell-sorted copy
+    int32_t fits;      // bit lv set when residency level lv fits in LDS
     int32_t nv;        // common polygon vertex count, 0 when mixed or not a polygon
     size_t lds_bytes;
-    size_t need[3];    // dynamic LDS per residency level
+    size_t need[4];    // dynamic LDS per residency level
     // grid path: largest replica of the group and the lanes per active cell
     int32_t dim, lanes, rounds_max;
     int64_t n_max, nc_max, n_act_max;
-    int32_t block = kBatchBlock;  // persistent: lanes per work-group
+    int32_t block = kBatchBlock;       // persistent: lanes per work-group
+    int32_t block_base = kBatchBlock;  // the size persistent_block chose
 };
 
 constexpr int kScanTile = 2048;  // cells per scan work-group (256 lanes x 8)
@@ -149,7 +151,10 @@ hipError_t scale_box(double* pos, int64_t n, double k, double L_new, hipStream_t
 // hipErrorNotSupported.
 hipError_t read_phase_trace(unsigned long long* out, bool reset);
 
-// Dynamic LDS of a persistent work-group (positions resident or not).
-size_t persistent_lds_bytes(int dim, int ncomp, int ncells, int N, int res, int block);
+constexpr int kResidencyLevels = 4;
+
+// Dynamic LDS of a persistent work-group of `block` lanes for a replica of
+// this kind, precision, cell count and N at residency level res.
+size_t persistent_lds_bytes(int kind, int precision, int ncells, int N, int res, int block);
 
 }  // namespace hpmc

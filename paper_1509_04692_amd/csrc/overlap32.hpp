@@ -225,7 +225,7 @@ inline bool fill_polygon_tables(SpeciesDev& P) {
 // Mixed-precision polyhedron test: the binary64 set-up, the certified
 // binary32 walk, and the binary64 walk when the former is uncertain.
 // Returns the overlap bit | (binary64 used) << 1.
-__device__ __noinline__ int polyhedron_overlap_mixed(const SpeciesDev& P, const V3& r, const Quat& qa,
+__device__ __forceinline__ int polyhedron_overlap_mixed(const SpeciesDev& P, const V3& r, const Quat& qa,
                                                      const Quat& qb) {
     const Minkowski64 mk = polyhedron_setup64(r, qa, qb);
     if (P.mpr32_ok) {

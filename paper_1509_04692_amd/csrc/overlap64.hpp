@@ -208,7 +208,7 @@ __device__ __forceinline__ bool polyhedron_mpr64(const SpeciesDev& P, const Mink
     }
 }
 
-__device__ __noinline__ bool polyhedron_overlap64(const SpeciesDev& P, const V3& r, const Quat& qa,
+__device__ __forceinline__ bool polyhedron_overlap64(const SpeciesDev& P, const V3& r, const Quat& qa,
                                                   const Quat& qb) {
     return polyhedron_mpr64(P, polyhedron_setup64(r, qa, qb));
 }

@@ -76,7 +76,9 @@ struct alignas(16) SysDev {
     // coordinate copy: every pair whose binary64 |r|^2 is below circ2 has a
     // binary32 |r|^2 below scan_t2 (bound derived on the host).
     float scan_t2;
-    uint32_t pad;
+    // queued full tests at which a wave drains its queue (16, 32 or 64; the
+    // autotuner's queue depth)
+    uint32_t drain_at;
 };
 
 // Phases of the per-wave clock of a trace build (HPMC_TRACE): cell-list

@@ -119,3 +119,57 @@ def test_full_length_properties(case):
     p, n = sp["p_rot"], st["attempted"]
     assert abs(st["attempted_rot"] / n - p) < 5.0 * math.sqrt(p * (1 - p) / n)
 
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_every_residency_level_equals_the_oracle(level):
+    """The persistent kernel at each LDS residency level (0: state in global
+    memory, 1: positions in LDS, 2: positions and orientations, 3: both and
+    no binary32 copy, the pre-filter computing it from the positions) on a
+    batch where every level fits, FP64 and MIXED."""
+    items = inputs.screening_batch(8, seed=2027, n_lo=64, n_hi=900)
+    for precision in ("fp64", "mixed"):
+        announce(f"residency {level}, {precision}, N={[c[1] for c in items]}")
+        system = _system(items, precision=precision, path="persistent")
+        system.set_config(level)
+        system.sweep(5, seed=13)
+        _check_every_replica(system, items, 13, 5)
+        del system
+
+
+def test_headline_batch_at_residency_three():
+    """512 x 4096 pentagons with positions and orientations in LDS and no
+    binary32 copy (the level whose LDS fits 4096 pentagons with their
+    orientations)."""
+    items = [inputs.workload_pentagons(4096, 0.60)] * 512
+    announce("512 x 4096 pentagons, mixed, persistent, residency 3")
+    system = _system(items, precision="mixed", path="persistent")
+    system.set_config(3)
+    system.sweep(3, seed=1)
+    _check_every_replica(system, items, 1, 3)
+
+
+@pytest.mark.parametrize("case", ["grid_pentagons_drain32", "grid_pentagons_drain16",
+                                  "grid_cubes_drain16", "persistent_drain32_half",
+                                  "persistent_drain16_quarter"])
+def test_queue_depth_and_work_group_size_equal_the_oracle(case):
+    """The autotuner's queue depths (drain at 32 or 16 queued tests instead of
+    64) and persistent work-group sizes (half and a quarter of the default):
+    the oracle's trajectory with every one."""
+    kind, what = case.split("_", 1)
+    drain = {"drain32": 1, "drain16": 2}[what.split("_")[-2 if kind == "persistent" else -1]]
+    if kind == "grid":
+        if "cubes" in what:
+            items, precision, lanes, n = [inputs.workload_cubes(1000, 0.45)], "mixed", 8, 4
+        else:
+            items, precision, lanes, n = [inputs.workload_pentagons(1024, 0.60)], "fp64", 16, 10
+        cfg = lanes | (drain << 9)
+    else:
+        items = inputs.screening_batch(6, seed=2029, n_lo=200, n_hi=1500)
+        precision, n = "mixed", 6
+        block = {"half": 1, "quarter": 2}[what.split("_")[-1]]
+        cfg = 3 | (drain << 9) | (block << 11)
+    announce(f"{case}: config {cfg:#x}, N={[c[1] for c in items]}")
+    system = _system(items, precision=precision, path=kind)
+    system.set_config(cfg)
+    system.sweep(n, seed=21)
+    _check_every_replica(system, items, 21, n)

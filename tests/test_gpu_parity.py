@@ -140,7 +140,9 @@ def test_autotuned_mixed_polyhedra_equal_the_oracle():
     announce("autotune mixed cubes")
     system = _system(sp, N, L, pos, orient, precision="mixed", path="grid")
     cfg = system.autotune(trial_sweeps=2)
-    assert (cfg & 0xff) in (1, 2, 4, 8, 16, 32, 64) and cfg & ~0x1ff == 0
+    # lanes per cell, the walk bit, a queue depth code; no work-group code on the grid path
+    assert (cfg & 0xff) in (1, 2, 4, 8, 16, 32, 64) and (cfg >> 9) & 3 in (0, 1, 2)
+    assert cfg >> 11 == 0
     system.sweep(8, seed=3)
     ref_pos, ref_ori = pos.copy(), orient.copy()
     ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=3, n_sweeps=8)
@@ -236,10 +238,19 @@ def test_set_config_rejects_what_the_state_cannot_use():
     with pytest.raises(HpmcError):
         reg.set_config(16)
     reg.set_config(8)
+    with pytest.raises(HpmcError):
+        reg.set_config(8 | (1 << 9))     # the register queue has no queue depth
+    grid.set_config(8 | (2 << 9))        # drain at 16 queued tests
+    for bad in (1 | (3 << 9), 1 | (1 << 11), 1 << 13):  # no drain code 3; block size persistent only
+        with pytest.raises(HpmcError):
+            grid.set_config(bad)
     pers = _system([sp, sp], [N, N], [L, L], [pos, pos], [orient, orient], path="persistent")
     pers.set_config(0)
-    with pytest.raises(HpmcError):
-        pers.set_config(3)
+    pers.set_config(3)
+    pers.set_config(3 | (1 << 9) | (2 << 11))  # drain at 32, a quarter of the lanes
+    for bad in (4, 3 | (3 << 11)):
+        with pytest.raises(HpmcError):
+            pers.set_config(bad)
 
 
 @pytest.mark.parametrize("queue", ["register", "global"])
@@ -327,7 +338,10 @@ def test_graph_replay_direct_launch_and_autotune_agree(path):
     assert np.array_equal(g.orientations(), d.orientations())
     before = (g.positions().copy(), g.orientations().copy(), g.stats(), g.sweep_counter)
     cfg = g.autotune(trial_sweeps=4)
-    assert cfg in ((0, 1, 2) if path == "persistent" else (1, 2, 4, 8, 16, 32, 64))
+    # lanes per cell or residency level, queue depth code, work-group size code
+    assert cfg & 0xff in ((0, 1, 2, 3) if path == "persistent" else (1, 2, 4, 8, 16, 32, 64))
+    assert not cfg & 0x100 and (cfg >> 9) & 3 in (0, 1, 2) and cfg >> 13 == 0
+    assert (cfg >> 11) & 3 in ((0, 1, 2) if path == "persistent" else (0,))
     assert np.array_equal(g.positions(), before[0]) and np.array_equal(g.orientations(), before[1])
     assert g.stats() == before[2] and g.sweep_counter == before[3]
     g.sweep(30, seed=9)
