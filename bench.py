@@ -56,6 +56,8 @@ def op_costs(nv):
         "mpr_setup": 169,           # relative rotation, two matrices, offset, first portal
         "mpr_support": 34 + 12 * nv,
         "mpr_iter": 55,
+        "seg_setup": 15 + 8 * nv,   # relative rotation 6 + offset 6 + (s + s)^2 3 + nv vertex maps
+        "seg_test": 16,             # one point-segment distance test (largest branch)
     }
 
 

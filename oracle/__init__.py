@@ -8,7 +8,8 @@ with the GPU library; the C source is ``hpmc_oracle.c`` next to this file.
 
 A species is a plain dict: ``dim``, ``shape`` ("disk" | "polygon" |
 "polyhedron"), ``verts`` (n x dim, particle frame; polygons CCW),
-``diameter`` (disks), ``d``, ``a``, ``p_rot`` and ``rounds`` (0 = auto).
+``diameter`` (disks), ``d``, ``a``, ``p_rot``, ``rounds`` (0 = auto) and
+``sweep_radius`` (polygons and polyhedra swept by a disk / ball; 0 = none).
 Positions are (dim, N) float64 arrays (structure of arrays, canonical order),
 orientations (2, N) for polygons (c, s) and (4, N) for polyhedra (w, x, y, z).
 """

@@ -36,12 +36,14 @@
 /*
  * ORACLE_COUNT_OPS builds a variant that counts algorithmic events of the
  * sweep (moves by kind, candidate pairs, separating-axis set-ups and axes
- * evaluated, XenoCollide set-ups, support evaluations and iterations), all
+ * evaluated, XenoCollide set-ups, support evaluations and iterations,
+ * swept-polygon distance set-ups and point-segment tests), all
  * with early exit, for the benchmark's work-per-move figure.  The normal
  * build compiles EVENT() to nothing.
  */
 enum { EV_TRANSLATE, EV_ROTATE2, EV_ROTATE3, EV_CAND2, EV_CAND3, EV_SAT_SETUP, EV_SAT_AXIS,
-       EV_SAT_FRAME_B, EV_MPR_SETUP, EV_MPR_SUPPORT, EV_MPR_ITER, EV_COUNT };
+       EV_SAT_FRAME_B, EV_MPR_SETUP, EV_MPR_SUPPORT, EV_MPR_ITER, EV_SEG_SETUP, EV_SEG_TEST,
+       EV_COUNT };
 #ifdef ORACLE_COUNT_OPS
 static int64_t or_events[EV_COUNT];
 int64_t *or_event_counts(void) { return or_events; }
@@ -166,7 +168,7 @@ typedef struct {
     double nrm[OR_MAXV][2];               /* polygon outward edge normals */
     double pmin[OR_MAXV], pmax[OR_MAXV];  /* own projections onto them */
     double R, dmax, circ2, tol2;
-    double sweep;  /* sweep radius of a spheropolyhedron, 0 otherwise */
+    double sweep;  /* sweep radius of a spheropolygon / -polyhedron, 0 otherwise */
 } shape_t;
 
 static int setup_shape(const or_species *sp, shape_t *sh)
@@ -186,8 +188,6 @@ static int setup_shape(const or_species *sp, shape_t *sh)
             return OR_ERR_INVALID_ARG;
         if (!(sp->sweep_radius >= 0.0) || !isfinite(sp->sweep_radius))
             return OR_ERR_INVALID_ARG;
-        if (sp->sweep_radius > 0.0 && sp->shape != OR_POLYHEDRON)
-            return OR_ERR_INVALID_ARG; /* rounded shapes: polyhedra only */
         sh->sweep = sp->sweep_radius;
         int min_verts = sh->sweep > 0.0 ? 1 : want_dim + 1;
         if (sp->n_verts < min_verts || sp->n_verts > OR_MAXV)
@@ -208,13 +208,16 @@ static int setup_shape(const or_species *sp, shape_t *sh)
          * every point within the sweep radius of one) lies inside */
         sh->R = nextafter(rmax + sh->sweep, INFINITY);
         if (sp->shape == OR_POLYGON) {
+            /* a swept core of one or two vertices (a point, a segment) has
+             * no turn to check; its edge k -> k+1 normals still serve the
+             * separating-axis test of the cores */
             for (int k = 0; k < sh->nv; ++k) {
                 int k1 = (k + 1) % sh->nv, k2 = (k + 2) % sh->nv;
                 double ex = sh->v[k1][0] - sh->v[k][0];
                 double ey = sh->v[k1][1] - sh->v[k][1];
                 double fx = sh->v[k2][0] - sh->v[k1][0];
                 double fy = sh->v[k2][1] - sh->v[k1][1];
-                if (!(ex * fy - ey * fx > 0.0))
+                if (sh->nv >= 3 && !(ex * fy - ey * fx > 0.0))
                     return OR_ERR_INVALID_ARG; /* not strictly convex CCW */
                 sh->nrm[k][0] = ey;
                 sh->nrm[k][1] = -ex;
@@ -320,6 +323,74 @@ static int overlap_polygon(const shape_t *sh, const double r[2], const double qa
             return 0;
     }
     return 1;
+}
+
+/* Spheropolygons (swept convex polygons, Sec. 2.3): the particle is every
+ * point within the sweep radius s of its core polygon, so two overlap when
+ * their cores overlap or pass closer than s + s.  Two convex cores that do
+ * not meet are closest at a vertex of one and an edge of the other; a core of
+ * one or two vertices is a point or a segment, covered by its "edges"
+ * k -> k+1 all the same.  Point p is closer than r (r2 = r^2) to the
+ * segment a-b exactly when the nearest point of the segment is: the end a
+ * (projection parameter c1 <= 0), the end b (c1 >= |b - a|^2 = c2), or the
+ * foot of the perpendicular, at squared distance cross^2 / c2. */
+static int point_segment_close(double px, double py, double ax, double ay, double bx, double by,
+                               double r2)
+{
+    EVENT(EV_SEG_TEST);
+    double ex = bx - ax, ey = by - ay;
+    double wx = px - ax, wy = py - ay;
+    double c1 = wx * ex + wy * ey;
+    if (c1 <= 0.0)
+        return wx * wx + wy * wy < r2;
+    double c2 = ex * ex + ey * ey;
+    if (c1 >= c2) {
+        double dx = px - bx, dy = py - by;
+        return dx * dx + dy * dy < r2;
+    }
+    double cr = ex * wy - ey * wx;
+    return cr * cr < r2 * c2;
+}
+
+/* Cores closer than s + s, measured in A's frame: A's vertices against B's
+ * edges, then B's vertices against A's edges. */
+static int polygon_cores_close(const shape_t *sh, const double r[2], const double qa[2],
+                               const double qb[2])
+{
+    double cA = qa[0], sA = qa[1], cB = qb[0], sB = qb[1];
+    EVENT(EV_SEG_SETUP);
+    double zc = cA * cB + sA * sB;
+    double zs = cA * sB - sA * cB;
+    double tx = cA * r[0] + sA * r[1];
+    double ty = cA * r[1] - sA * r[0];
+#ifdef ORACLE_PLANT_SWEEP_ONE_SIDED
+    double reach = sh->sweep;
+#else
+    double reach = sh->sweep + sh->sweep;
+#endif
+    double r2 = reach * reach;
+    double bx[OR_MAXV], by[OR_MAXV];
+    for (int j = 0; j < sh->nv; ++j) {
+        bx[j] = (zc * sh->v[j][0] - zs * sh->v[j][1]) + tx;
+        by[j] = (zs * sh->v[j][0] + zc * sh->v[j][1]) + ty;
+    }
+    for (int j = 0; j < sh->nv; ++j)
+        for (int k = 0; k < sh->nv; ++k) {
+            int k1 = (k + 1) % sh->nv;
+            if (point_segment_close(sh->v[j][0], sh->v[j][1], bx[k], by[k], bx[k1], by[k1], r2))
+                return 1;
+        }
+#ifdef ORACLE_PLANT_SWEPT_ONE_WAY
+    return 0;
+#endif
+    for (int j = 0; j < sh->nv; ++j)
+        for (int k = 0; k < sh->nv; ++k) {
+            int k1 = (k + 1) % sh->nv;
+            if (point_segment_close(bx[j], by[j], sh->v[k][0], sh->v[k][1], sh->v[k1][0],
+                                    sh->v[k1][1], r2))
+                return 1;
+        }
+    return 0;
 }
 
 /* Hamilton product p (x) q, each component summed left to right. */
@@ -555,8 +626,11 @@ static int full_test(const shape_t *sh, const double *r, const double *qa, const
 {
     if (sh->kind == OR_DISK)
         return norm2(r, 2) < sh->circ2;
-    if (sh->kind == OR_POLYGON)
-        return overlap_polygon(sh, r, qa, qb);
+    if (sh->kind == OR_POLYGON) {
+        if (overlap_polygon(sh, r, qa, qb))
+            return 1;
+        return sh->sweep > 0.0 && polygon_cores_close(sh, r, qa, qb);
+    }
     return overlap_polyhedron(sh, r, qa, qb);
 }
 

@@ -51,11 +51,12 @@ typedef struct {
     double a;             /* rotation size */
     double p_rot;         /* probability that a move is a rotation */
     int32_t rounds;       /* colour rounds per sweep, 0 = automatic */
-    double sweep_radius;  /* polyhedra: the shape is every point within this
-                             distance of the convex hull of verts (a
-                             spheropolyhedron, Sec. 2.3); 0 = the hull itself.
-                             With sweep_radius > 0, 1..OR_MAXV vertices (one
-                             vertex: a sphere, two: a spherocylinder). */
+    double sweep_radius;  /* polygons and polyhedra: the shape is every point
+                             within this distance of the convex hull of verts
+                             (a spheropolygon / spheropolyhedron, Sec. 2.3);
+                             0 = the hull itself.  With sweep_radius > 0,
+                             1..OR_MAXV vertices (one vertex: a disk or
+                             sphere, two: a stadium or spherocylinder). */
 } or_species;
 
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

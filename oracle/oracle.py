@@ -27,7 +27,7 @@ _LIB_OPS_PATH = os.path.join(_HERE, "liboracle_ops.so")
 
 # Event counters of the ORACLE_COUNT_OPS build, in the order of hpmc_oracle.c.
 EVENT_NAMES = ("translate", "rotate2", "rotate3", "cand2", "cand3", "sat_setup", "sat_axis",
-               "sat_frame_b", "mpr_setup", "mpr_support", "mpr_iter")
+               "sat_frame_b", "mpr_setup", "mpr_support", "mpr_iter", "seg_setup", "seg_test")
 
 
 def build(extra_flags=(), out_path=None):

@@ -156,6 +156,30 @@ def rounded_cube_species(edge=1.0, radius=0.1, d=0.08, a=0.1, p_rot=0.5):
             + 4.0 / 3.0 * math.pi * radius ** 3}
 
 
+# -- spheropolygons: a convex polygon swept by a disk (sweep_radius > 0) ---------
+
+def rounded_polygon_species(verts, radius, d=0.1, a=0.2, p_rot=0.5):
+    """Core polygon `verts` (counter-clockwise; one vertex: a disk, two: a
+    stadium) swept by a disk of `radius`.  Area by the Steiner formula
+    A + P r + pi r^2, P the core's perimeter (twice the length of a segment)."""
+    v = np.asarray(verts, dtype=np.float64).reshape(-1, 2)
+    perim = float(np.sum(np.linalg.norm(np.roll(v, -1, axis=0) - v, axis=1)))
+    core = polygon_area(v) if len(v) >= 3 else 0.0
+    return {"dim": 2, "shape": "polygon", "verts": v, "sweep_radius": float(radius),
+            "d": float(d), "a": float(a), "p_rot": float(p_rot), "rounds": 0,
+            "volume": core + perim * radius + math.pi * radius ** 2}
+
+
+def stadium_species(length=1.0, radius=0.25, d=0.1, a=0.2, p_rot=0.5):
+    """Segment of `length` along x swept by a disk of `radius`."""
+    return rounded_polygon_species([[-0.5 * length, 0.0], [0.5 * length, 0.0]], radius, d, a, p_rot)
+
+
+def rounded_pentagon_species(circumradius=0.4, radius=0.1, d=0.1, a=0.2, p_rot=0.5):
+    """Regular pentagon of `circumradius` swept by a disk of `radius`."""
+    return rounded_polygon_species(regular_polygon_vertices(5, circumradius), radius, d, a, p_rot)
+
+
 def box_length(N, particle_volume, phi, dim):
     """Side of the square / cubic periodic box holding N particles at phi."""
     return (N * particle_volume / phi) ** (1.0 / dim)
@@ -337,7 +361,7 @@ def initial_state(sp, N, phi, seed=INIT_SEED):
     except ValueError:
         if sp["shape"] == "disk":
             pos, orient = disk_triangular_lattice(sp, N, L, seed)
-        elif sp["shape"] == "polygon" and len(sp["verts"]) == 5:
+        elif sp["shape"] == "polygon" and len(sp["verts"]) == 5 and not sp.get("sweep_radius"):
             pos, orient = pentagon_interlocked_lattice(sp, N, L, seed)
         elif sp["shape"] == "polyhedron":
             try:
@@ -417,6 +441,23 @@ def workload_spherocylinders(N=4096, phi=0.15):
 
 def workload_rounded_cubes(N=4096, phi=0.45):
     sp = rounded_cube_species(1.0, 0.1, d=0.08, a=0.1, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_rounded_pentagons(N=4096, phi=0.50):
+    """Regular pentagons of core circumradius 0.4 swept by a disk of radius
+    0.1 (outer circumradius 0.5, like the plain pentagons)."""
+    sp = rounded_pentagon_species(0.4, 0.1, d=0.1, a=0.2, p_rot=0.5)
+    L, pos, orient = initial_state(sp, N, phi)
+    return sp, N, L, pos, orient
+
+
+def workload_stadiums(N=4096, phi=0.30):
+    """Stadiums: a unit segment swept by a disk of radius 0.25 (aspect
+    (1 + 0.5) / 0.5 = 3), on a square lattice (whose pitch the long axis
+    sets, hence the low packing fraction)."""
+    sp = stadium_species(1.0, 0.25, d=0.1, a=0.2, p_rot=0.5)
     L, pos, orient = initial_state(sp, N, phi)
     return sp, N, L, pos, orient
 

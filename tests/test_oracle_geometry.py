@@ -10,6 +10,14 @@
 * Convex polyhedra (XenoCollide in the oracle) against full 3D separating
   axes (all face normals plus all edge-edge cross products), against the
   closed form for axis-aligned unit cubes, and against point sampling.
+* Spheropolyhedra: spheres and spherocylinders in closed form, rounded
+  cubes against core separations and point sampling.
+* Spheropolygons (cores overlapping or closer than twice the sweep radius in
+  the oracle): one-vertex cores against the disk closed form, two-vertex
+  cores against the segment distance, rounded polygons against the sampled
+  signed separation of the cores (max over directions of the smallest
+  projected vertex difference); monotone in the sweep radius, the plain
+  polygon in its small limit, and the hard-disk chain bit for bit.
 * Invariants: exchange symmetry and global rotation invariance.
 
 Configurations whose separation or penetration is below 1e-9 are skipped:
@@ -426,10 +434,15 @@ def test_sweep_radius_shape_rules():
     assert oracle.shape_info(sph)["R"] == math.nextafter(0.5, math.inf)
     rc = inputs.rounded_cube_species(1.0, 0.1)
     assert oracle.shape_info(rc)["R"] == math.nextafter(math.sqrt(0.75) + 0.1, math.inf)
-    with pytest.raises(ValueError):  # a swept polygon is not supported
-        oracle.shape_info(dict(inputs.pentagon_species(), sweep_radius=0.1))
+    rp = inputs.rounded_pentagon_species(0.4, 0.1)
+    assert oracle.shape_info(rp)["R"] == math.nextafter(0.4 + 0.1, math.inf)
+    assert oracle.shape_info(inputs.stadium_species(1.0, 0.25))["R"] == math.nextafter(0.75, math.inf)
     with pytest.raises(ValueError):  # fewer than 4 vertices need a sweep radius
         oracle.shape_info(dict(inputs.spherocylinder_species(), sweep_radius=0.0))
+    with pytest.raises(ValueError):  # fewer than 3 polygon vertices need one too
+        oracle.shape_info(dict(inputs.stadium_species(), sweep_radius=0.0))
+    with pytest.raises(ValueError):  # a swept core must still be convex
+        oracle.shape_info(dict(rp, verts=rp["verts"][::-1].copy()))
     with pytest.raises(ValueError):
         oracle.shape_info(dict(inputs.cube_species(), sweep_radius=-0.1))
 
@@ -443,6 +456,198 @@ def test_sweep_pins_detect_a_one_sided_sweep(planted):
         dist = rng.uniform(0.0, 1.3)
         r = _rand_unit(rng) * dist
         mismatches += oracle.overlap_full(sp, r, random_quat(rng), random_quat(rng), lib=lib) != (dist < 1.0)
+    assert mismatches > 0
+
+
+# -- spheropolygons (core polygon swept by a disk of radius s) -----------------
+#
+# Independent reference: the signed separation of two convex cores,
+# D = max over unit directions u of min over vertex pairs u . (b_j - a_k),
+# the distance between the cores when they are apart and minus the
+# penetration depth when they overlap; the swept shapes overlap exactly when
+# D < 2 s.  Sampling u at NDIR angles gives a lower bound within
+# (max vertex-pair distance) x (pi / NDIR) of D.
+
+NDIR = 20000
+_U = np.stack([np.cos(np.arange(NDIR) * (2 * math.pi / NDIR)),
+               np.sin(np.arange(NDIR) * (2 * math.pi / NDIR))], axis=1)
+
+
+def signed_separation(PA, PB):
+    diff = (PB[:, None, :] - PA[None, :, :]).reshape(-1, 2)
+    proj = diff @ _U.T
+    err = float(np.linalg.norm(diff, axis=1).max()) * (math.pi / NDIR)
+    return float(proj.min(axis=0).max()), err
+
+
+def _random_z(rng):
+    t = rng.uniform(0.0, 2.0 * math.pi)
+    return np.array([math.cos(t), math.sin(t)])
+
+
+def test_spheropolygon_one_vertex_is_a_disk():
+    """One-vertex core swept by s = 1/2: the unit disk, overlapping exactly
+    when the centres are closer than 1, whatever the orientations."""
+    sp = inputs.rounded_polygon_species([[0.0, 0.0]], 0.5)
+    rng = np.random.Generator(np.random.PCG64(51))
+    hits = 0
+    for _ in range(3000):
+        dist = rng.uniform(0.0, 1.3)
+        if abs(dist - 1.0) < 1e-9:
+            continue
+        want = dist < 1.0
+        r = _random_z(rng) * dist
+        assert oracle.overlap_full(sp, r, _random_z(rng), _random_z(rng)) == want
+        hits += want
+    assert 0.6 < hits / 3000 < 0.9
+
+
+def test_stadium_closed_form():
+    """Two-vertex core (a segment) swept by s: overlap exactly when the core
+    segments are closer than 2 s (segment distance by the clamped quadratic
+    above, crossing segments at distance 0)."""
+    s = 0.25
+    sp = inputs.stadium_species(1.0, s)
+    rng = np.random.Generator(np.random.PCG64(52))
+    h = np.array([0.5, 0.0])
+    checked = hits = crossing = 0
+    for _ in range(3000):
+        r = _random_z(rng) * rng.uniform(0.0, 1.6)
+        za, zb = _random_z(rng), _random_z(rng)
+        ra, rb = rot2(za), rot2(zb)
+        dist = segment_distance(-ra @ h, ra @ h, r - rb @ h, r + rb @ h)
+        if abs(dist - 2 * s) < 1e-8:
+            continue
+        want = dist < 2 * s
+        assert oracle.overlap_full(sp, r, za, zb) == want, (r, za, zb, dist)
+        checked += 1
+        hits += want
+        crossing += dist < 1e-12
+    assert checked > 2900 and 0.2 < hits / checked < 0.8 and crossing > 50
+
+
+@pytest.mark.parametrize("verts, s", [
+    (inputs.regular_polygon_vertices(5, 0.4), 0.1),
+    (inputs.regular_polygon_vertices(3, 0.5), 0.05),
+    (np.array([[-0.6, -0.2], [0.5, -0.3], [0.4, 0.25], [-0.3, 0.35]]), 0.15),
+])
+def test_rounded_polygons_against_signed_separation(verts, s):
+    """Swept convex polygons against the sampled signed separation of their
+    cores, over centre distances from deep overlap to well apart."""
+    sp = inputs.rounded_polygon_species(verts, s)
+    R = float(np.linalg.norm(verts, axis=1).max()) + s
+    rng = np.random.Generator(np.random.PCG64(53))
+    apart = overlap = near = 0
+    for _ in range(600):
+        r = _random_z(rng) * rng.uniform(0.0, 2.3 * R)
+        za, zb = _random_z(rng), _random_z(rng)
+        D, err = signed_separation(world_polygon(verts, za, [0.0, 0.0]), world_polygon(verts, zb, r))
+        got = oracle.overlap_full(sp, r, za, zb)
+        if D > 2 * s + 1e-12:  # the sampled D is a lower bound
+            assert not got, (r, za, zb, D)
+            apart += 1
+        elif D < 2 * s - err - 1e-12:
+            assert got, (r, za, zb, D)
+            overlap += 1
+            near += D > 0.0  # cores apart, swept disks meet
+    assert apart > 80 and overlap > 150 and near > 30, (apart, overlap, near)
+
+
+def test_spheropolygon_monotone_in_the_sweep_radius_and_its_limit():
+    """A larger sweep radius never removes an overlap; a tiny one decides as
+    the plain polygon wherever the cores are not within it of contact."""
+    v = inputs.regular_polygon_vertices(5, 0.5)
+    plain = inputs.pentagon_species(0.5)
+    tiny = inputs.rounded_polygon_species(v, 1e-12)
+    small = inputs.rounded_polygon_species(v, 0.05)
+    large = inputs.rounded_polygon_species(v, 0.1)
+    rng = np.random.Generator(np.random.PCG64(54))
+    grew = same = 0
+    for _ in range(2000):
+        r = _random_z(rng) * rng.uniform(0.5, 1.3)
+        za, zb = _random_z(rng), _random_z(rng)
+        a, b = oracle.overlap_full(small, r, za, zb), oracle.overlap_full(large, r, za, zb)
+        assert b or not a
+        grew += b and not a
+        gap = sat_gap_2d(world_polygon(v, za, [0.0, 0.0]), world_polygon(v, zb, r))
+        if abs(gap) > 1e-9:
+            assert oracle.overlap_full(tiny, r, za, zb) == oracle.overlap_full(plain, r, za, zb)
+            same += 1
+    assert grew > 50 and same > 1900
+
+
+def test_spheropolygon_exchange_and_rotation_invariance():
+    """Swapping the particles (r -> -r) and turning the whole pair by a
+    common angle leave the decision unchanged away from contact."""
+    v = inputs.regular_polygon_vertices(5, 0.4)
+    s = 0.1
+    sp = inputs.rounded_polygon_species(v, s)
+    rng = np.random.Generator(np.random.PCG64(55))
+    checked = 0
+    for _ in range(800):
+        r = _random_z(rng) * rng.uniform(0.3, 1.2)
+        za, zb = _random_z(rng), _random_z(rng)
+        D, err = signed_separation(world_polygon(v, za, [0.0, 0.0]), world_polygon(v, zb, r))
+        if abs(D - 2 * s) < err + 1e-6:
+            continue
+        base = oracle.overlap_full(sp, r, za, zb)
+        assert oracle.overlap_full(sp, -r, zb, za) == base
+        g = _random_z(rng)
+        rg = rot2(g)
+        zag = np.array([g[0] * za[0] - g[1] * za[1], g[1] * za[0] + g[0] * za[1]])
+        zbg = np.array([g[0] * zb[0] - g[1] * zb[1], g[1] * zb[0] + g[0] * zb[1]])
+        assert oracle.overlap_full(sp, rg @ r, zag, zbg) == base
+        checked += 1
+    assert checked > 700
+
+
+def test_one_vertex_spheropolygons_reproduce_hard_disks():
+    """Without rotations, cores of one vertex swept by s are disks of
+    diameter 2 s: the checkerboard chain of such a system equals the hard-disk
+    chain bit for bit (same draws, same decisions |r|^2 < (2 s)^2)."""
+    disk = inputs.disk_species(1.0, d=0.1)
+    swept = inputs.rounded_polygon_species([[0.0, 0.0]], 0.5, d=0.1, a=0.0, p_rot=0.0)
+    N, phi = 400, 0.55
+    L, pos, _ = inputs.initial_state(disk, N, phi)
+    assert oracle.grid(disk, N, L) == oracle.grid(swept, N, L)
+    p1, p2 = pos.copy(), pos.copy()
+    o1 = np.zeros((1, N))
+    o2 = inputs.identity_orientations(swept, N)
+    st1 = oracle.sweep(disk, L, p1, o1, seed=7, n_sweeps=20)
+    st2 = oracle.sweep(swept, L, p2, o2, seed=7, n_sweeps=20)
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(st1, st2)
+    stat = dict(zip(oracle.STAT_NAMES, st1))
+    assert stat["accept"] > 0 and stat["overlap_reject"] > 0
+
+
+def test_spheropolygon_pins_detect_a_one_sided_sweep(planted):
+    lib = planted("ORACLE_PLANT_SWEEP_ONE_SIDED")
+    sp = inputs.rounded_polygon_species([[0.0, 0.0]], 0.5)
+    rng = np.random.Generator(np.random.PCG64(56))
+    mismatches = 0
+    for _ in range(300):
+        dist = rng.uniform(0.0, 1.3)
+        r = _random_z(rng) * dist
+        mismatches += oracle.overlap_full(sp, r, _random_z(rng), _random_z(rng), lib=lib) != (dist < 1.0)
+    assert mismatches > 0
+
+
+def test_spheropolygon_pins_detect_one_way_distances(planted):
+    """Measuring only A's vertices against B's edges misses contacts where a
+    vertex of B is nearest to an edge of A."""
+    lib = planted("ORACLE_PLANT_SWEPT_ONE_WAY")
+    v = inputs.regular_polygon_vertices(5, 0.4)
+    s = 0.1
+    sp = inputs.rounded_polygon_species(v, s)
+    rng = np.random.Generator(np.random.PCG64(57))
+    mismatches = 0
+    for _ in range(400):
+        r = _random_z(rng) * rng.uniform(0.6, 1.2)
+        za, zb = _random_z(rng), _random_z(rng)
+        D, err = signed_separation(world_polygon(v, za, [0.0, 0.0]), world_polygon(v, zb, r))
+        if 0.0 < D < 2 * s - err - 1e-12:
+            mismatches += not oracle.overlap_full(sp, r, za, zb, lib=lib)
     assert mismatches > 0
 
 
