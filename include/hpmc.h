@@ -104,8 +104,9 @@ typedef enum { HPMC_PATH_AUTO = 0, HPMC_PATH_GRID = 1, HPMC_PATH_PERSISTENT = 2 
 typedef struct {
     int32_t dim;          /* 2 (disk, polygon) or 3 (polyhedron) */
     int32_t shape;        /* hpmc_shape */
-    int32_t n_verts;      /* polygon: 3..8 (CCW, strictly convex); polyhedron: 4..64,
-                             or 1..64 with sweep_radius > 0 */
+    int32_t n_verts;      /* polygon: 3..8 (CCW, strictly convex), or 1..8 with
+                             sweep_radius > 0; polyhedron: 4..64, or 1..64 with
+                             sweep_radius > 0 */
     const double *verts;  /* host, n_verts x dim row-major; NULL for disks */
     double diameter;      /* disks */
     double d;             /* translation: each component uniform in [-d, d] */
@@ -114,12 +115,15 @@ typedef struct {
                              v uniform in [-a, a]^3, renormalised */
     double p_rot;         /* probability that a move is a rotation (0 for disks) */
     int32_t rounds;       /* colour rounds per sweep; 0 = max(1, round(N / cells)) */
-    double sweep_radius;  /* polyhedra: the particle is every point within this
-                             distance of the vertices' convex hull (a
-                             spheropolyhedron, Sec. 2.3; one vertex gives a
-                             sphere, two a spherocylinder); 0 for the hull
-                             itself and for disks and polygons.  Swept shapes
-                             always walk XenoCollide in binary64. */
+    double sweep_radius;  /* polygons and polyhedra: the particle is every point
+                             within this distance of the vertices' convex hull
+                             (a spheropolygon or spheropolyhedron, Sec. 2.3;
+                             one vertex gives a disk / sphere, two a stadium /
+                             spherocylinder); 0 for the hull itself and for
+                             disks.  Swept shapes are always tested in binary64
+                             (spheropolygons: the cores overlap or pass closer
+                             than twice the radius; spheropolyhedra:
+                             XenoCollide); spheropolygons need the wave queue. */
 } hpmc_species;
 
 typedef struct {

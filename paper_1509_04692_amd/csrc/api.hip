@@ -101,8 +101,9 @@ int build_species(const hpmc_species& s, SpeciesDev& P) {
     if (s.shape == HPMC_POLYGON && !(s.a <= HPMC_MAX_POLYGON_ROTATION)) return HPMC_ERR_INVALID_ARG;
     if (s.rounds < 0) return HPMC_ERR_INVALID_ARG;
     if (!(s.sweep_radius >= 0.0) || !std::isfinite(s.sweep_radius)) return HPMC_ERR_INVALID_ARG;
-    if (s.sweep_radius > 0.0 && s.shape != HPMC_POLYHEDRON) return HPMC_ERR_INVALID_ARG;
+    if (s.sweep_radius > 0.0 && s.shape == HPMC_DISK) return HPMC_ERR_INVALID_ARG;
     P.sweep = s.sweep_radius;
+    if (s.shape == HPMC_POLYGON && P.sweep > 0.0) P.kind = kSpheropolygon;
     if (s.shape == HPMC_DISK) {
         if (s.dim != 2 || !(s.diameter > 0.0) || s.p_rot != 0.0) return HPMC_ERR_INVALID_ARG;
         P.R = s.diameter * 0.5;
@@ -198,7 +199,7 @@ int build_grid(const hpmc_species& s, const SpeciesDev& P, int32_t N, double L, 
     if ((int64_t)S.rounds * (1 << s.dim) >= ((int64_t)1 << 28)) return HPMC_ERR_INVALID_ARG;
     S.scan_t2 = scan_threshold(P.circ2, L, S.w, s.dim);
     S.drain_at = 64;
-    rh.kind = s.shape;
+    rh.kind = P.kind;
     rh.dim = s.dim;
     rh.N = N;
     rh.n = n;
@@ -266,6 +267,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     for (int r = 0; r < R; ++r) {
         int rc = build_species(a->species[r], spc[r]);
         if (rc) return rc;
+        // swept polygons run the wave queue only
+        if (spc[r].kind == kSpheropolygon && queue != kQueueWave) return HPMC_ERR_UNSUPPORTED;
         rc = build_grid(a->species[r], spc[r], a->N[r], a->L[r], sys[r], rep[r]);
         if (rc) return rc;
         // cell lists are sized for the largest box a volume move may reach
@@ -283,7 +286,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         sys[r].orient_off = ori_off;
         rep[r].pos_off = pos_off;
         rep[r].orient_off = ori_off;
-        const int ncomp = spc[r].kind == kDisk ? 0 : (spc[r].kind == kPolygon ? 2 : 4);
+        const int ncomp = orient_comps(spc[r].kind);
         pos_off += (int64_t)sys[r].dim * sys[r].N;
         ori_off += (int64_t)ncomp * sys[r].N;
         // this replica's slice of the global cell lists
@@ -318,7 +321,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         // kinds with the costlier overlap test first: their launch is captured
         // first and takes the compute units first, and the cheaper kinds'
         // work-groups fill in as they free up
-        for (int kind = kPolyhedron; kind >= kDisk; --kind) {
+        constexpr int kCostOrder[kNumKinds] = {kPolyhedron, kSpheropolygon, kPolygon, kDisk};
+        for (const int kind : kCostOrder) {
             BatchGroup g{};
             g.kind = kind;
             g.first = (int32_t)list.size();
@@ -363,7 +367,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         }
     } else {
         // grid path: one launch per step for all replicas of a kind
-        for (int kind = kDisk; kind <= kPolyhedron; ++kind) {
+        for (int kind = 0; kind < kNumKinds; ++kind) {
             BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}, 0, 1, 0, 0, 0, 0};
             int64_t n_act_total = 0;
             for (int r = 0; r < R; ++r) {
@@ -442,8 +446,10 @@ int count_all(hpmc_state* st, uint64_t* out) {
 }
 
 // Precision of a group's kernels: MIXED polyhedra may take the binary64
-// walk when the autotuner found it faster (the decisions are the same).
+// walk when the autotuner found it faster (the decisions are the same);
+// swept polygons have binary64 tests only.
 int group_precision(const hpmc_state* st, const BatchGroup& g) {
+    if (g.kind == kSpheropolygon) return HPMC_FP64;
     return (g.kind == kPolyhedron && st->walk64) ? HPMC_FP64 : st->precision;
 }
 

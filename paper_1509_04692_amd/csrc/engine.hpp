@@ -30,9 +30,13 @@ namespace hpmc {
 template <int KIND>
 struct Traits {
     static constexpr int dim = KIND == kPolyhedron ? 3 : 2;
-    static constexpr int ncomp = KIND == kDisk ? 0 : (KIND == kPolygon ? 2 : 4);
+    static constexpr int ncomp = orient_comps(KIND);
     static constexpr int nbrs = KIND == kPolyhedron ? 27 : 9;
 };
+
+// Shapes turned by a unit complex number (Sec. 2.1's 2D rotation move).
+template <int KIND>
+constexpr bool kPlanarTurn = KIND == kPolygon || KIND == kSpheropolygon;
 
 // Per-lane counters, named fields (an array indexed on two branches gets its
 // increments merged through a selected address and lands in scratch).
@@ -213,7 +217,7 @@ __device__ __forceinline__ void load_orient(const double* __restrict__ ori, int 
                                             double (&q)[4]) {
     q[0] = 1.0;
     q[1] = q[2] = q[3] = 0.0;
-    if constexpr (KIND == kPolygon) {
+    if constexpr (kPlanarTurn<KIND>) {
         q[0] = ori[i];
         q[1] = ori[N + i];
     } else if constexpr (KIND == kPolyhedron) {
@@ -231,6 +235,10 @@ __device__ __forceinline__ bool full_test(const SpeciesDev& P, const double (&r)
                                           Counters& ct) {
     if constexpr (KIND == kDisk) {
         return true;
+    } else if constexpr (KIND == kSpheropolygon) {
+        ct.pair_tests++;
+        ct.pair_fp64++;
+        return spheropolygon_overlap64(P, r[0], r[1], qi[0], qi[1], qk[0], qk[1]);
     } else if constexpr (KIND == kPolygon) {
         ct.pair_tests++;
         if constexpr (PREC == 1) {
@@ -574,7 +582,7 @@ __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, co
                 live &= cell_coord(xn[ax], sh[ax], S.L, S.inv_w, n) == cc[ax];
             }
         } else {
-            if constexpr (KIND == kPolygon) {
+            if constexpr (kPlanarTurn<KIND>) {
                 const double delta = P.a * (2.0 * u01(m.y) - 1.0);
                 double cd, sd;
                 small_angle_sincos(delta, cd, sd);
@@ -649,7 +657,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                     live &= cell_coord(xn[ax], sh[ax], S.L, S.inv_w, n) == cc[ax];
                 }
             } else {
-                if constexpr (KIND == kPolygon) {
+                if constexpr (kPlanarTurn<KIND>) {
                     const double delta = P.a * (2.0 * u01(m.y) - 1.0);
                     double cd, sd;
                     small_angle_sincos(delta, cd, sd);
@@ -863,7 +871,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
             for (int ax = 0; ax < D; ++ax) pos.set(ax, i, xn[ax]);
         }
         if (!rejected && c_rot) {
-            if constexpr (KIND == kPolygon) {
+            if constexpr (kPlanarTurn<KIND>) {
                 ori[i] = qn[0];
                 ori[N + i] = qn[1];
             } else if constexpr (KIND == kPolyhedron) {

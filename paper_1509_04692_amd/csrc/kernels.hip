@@ -990,7 +990,7 @@ static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
 size_t persistent_lds_bytes(int kind, int precision, int ncells, int N, int res, int block) {
     const int dim = kind == kPolyhedron ? 3 : 2;
-    const int ncomp = kind == kDisk ? 0 : (kind == kPolygon ? 2 : 4);
+    const int ncomp = orient_comps(kind);
     return batch_layout(dim, ncomp, N, ncells, block / 64, res, wave_scratch_words(kind, precision)).total;
 }
 
@@ -1118,6 +1118,10 @@ static void launch_global_queue(const Workspace& ws, const BatchGroup& g, double
 template <int KIND, int PREC, int NV>
 static void launch_passes_q(const Workspace& ws, const BatchGroup& g, double* pos, double* orient,
                             int queue, hipStream_t stream) {
+    if constexpr (KIND == kSpheropolygon) {  // the wave queue only (checked at init)
+        launch_passes_nv<KIND, PREC, NV, kWaveQueue>(ws, g, pos, orient, stream);
+        return;
+    }
     if (queue == kQueueGlobal)
         launch_global_queue<KIND, PREC, NV>(ws, g, pos, orient, stream);
     else if (queue == kQueueRegister)
@@ -1143,6 +1147,8 @@ hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, do
         launch_passes<kPolygon, 1>(ws, g, pos, orient, queue, stream);
     else if (g.kind == kPolygon)
         launch_passes<kPolygon, 0>(ws, g, pos, orient, queue, stream);
+    else if (g.kind == kSpheropolygon)
+        launch_passes<kSpheropolygon, 0>(ws, g, pos, orient, queue, stream);
     else if (precision == 1)
         launch_passes<kPolyhedron, 1>(ws, g, pos, orient, queue, stream);
     else
@@ -1190,6 +1196,8 @@ hipError_t persistent_sweeps(const Workspace& ws, const BatchGroup& g, double* p
         return g.nv == 5 ? launch_batch_res<kPolygon, 0, 5>(ws, g, pos, orient, prepare, stream)
                          : launch_batch_res<kPolygon, 0, 0>(ws, g, pos, orient, prepare, stream);
     }
+    if (g.kind == kSpheropolygon)
+        return launch_batch_res<kSpheropolygon, 0, 0>(ws, g, pos, orient, prepare, stream);
     if (precision == 1)
         return launch_batch_res<kPolyhedron, 1, 0>(ws, g, pos, orient, prepare, stream);
     return launch_batch_res<kPolyhedron, 0, 0>(ws, g, pos, orient, prepare, stream);
@@ -1225,6 +1233,10 @@ hipError_t scale_counts(const Workspace& ws, const ReplicaHost& rh, int r, const
         k_scale_count<kPolygon><<<grid, 256, 0, stream>>>(ws.sys, ws.species, r, pos, orient,
                                                           ws.start, ws.members, ws.cell_of,
                                                           ws.hist_edges, n_s, reach, ws.hist_out);
+    else if (rh.kind == kSpheropolygon)
+        k_scale_count<kSpheropolygon><<<grid, 256, 0, stream>>>(ws.sys, ws.species, r, pos, orient,
+                                                                ws.start, ws.members, ws.cell_of,
+                                                                ws.hist_edges, n_s, reach, ws.hist_out);
     else
         k_scale_count<kPolyhedron><<<grid, 256, 0, stream>>>(ws.sys, ws.species, r, pos, orient,
                                                              ws.start, ws.members, ws.cell_of,
@@ -1258,7 +1270,7 @@ hipError_t validate_state(const Workspace& ws, const ReplicaHost& rh, int r, con
     const int N = rh.N;
     if (rh.kind == kDisk)
         k_validate<0><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, orient, ws.overlap_out);
-    else if (rh.kind == kPolygon)
+    else if (rh.kind == kPolygon || rh.kind == kSpheropolygon)
         k_validate<2><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, orient, ws.overlap_out);
     else
         k_validate<4><<<blocks_for(N, 256), 256, 0, stream>>>(ws.sys, r, pos, orient, ws.overlap_out);
@@ -1274,6 +1286,9 @@ hipError_t count_pairs(const Workspace& ws, const ReplicaHost& rh, int r, const 
                                                                 ws.overlap_out);
     else if (rh.kind == kPolygon)
         k_count<kPolygon><<<blocks_for(N, 256), 256, 0, stream>>>(
+            ws.sys, ws.species, r, pos, orient, ws.start, ws.members, ws.cell_of, ws.overlap_out);
+    else if (rh.kind == kSpheropolygon)
+        k_count<kSpheropolygon><<<blocks_for(N, 256), 256, 0, stream>>>(
             ws.sys, ws.species, r, pos, orient, ws.start, ws.members, ws.cell_of, ws.overlap_out);
     else
         k_count<kPolyhedron><<<blocks_for(N, 256), 256, 0, stream>>>(

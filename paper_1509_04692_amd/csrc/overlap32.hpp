@@ -176,14 +176,15 @@ __host__ __device__ inline int polygon_overlap32(const SpeciesDev& P, double rxd
 
 // Host side: edge normals, own projections and binary32 copies of a polygon
 // type (vertices and R already set).  False unless the vertices are
-// counter-clockwise and strictly convex.
+// counter-clockwise and strictly convex (a swept core of one or two
+// vertices, a point or a segment, has no turn to check).
 inline bool fill_polygon_tables(SpeciesDev& P) {
     double nmax = 0.0;
     for (int k = 0; k < P.nv; ++k) {
         const int k1 = (k + 1) % P.nv, k2 = (k + 2) % P.nv;
         const double ex = P.vx[k1] - P.vx[k], ey = P.vy[k1] - P.vy[k];
         const double fx = P.vx[k2] - P.vx[k1], fy = P.vy[k2] - P.vy[k1];
-        if (!(ex * fy - ey * fx > 0.0)) return false;
+        if (P.nv >= 3 && !(ex * fy - ey * fx > 0.0)) return false;
         P.nx[k] = ey;
         P.ny[k] = -ex;
         nmax = std::fmax(nmax, std::sqrt(ey * ey + ex * ex));

@@ -77,6 +77,79 @@ __device__ __forceinline__ bool polygon_overlap64(const SpeciesDev& P, double rx
 }
 
 // ---------------------------------------------------------------------------
+// Spheropolygons: a core polygon swept by a disk of radius s (Sec. 2.3's
+// swept shapes).  Two overlap when the cores overlap (the separating axes
+// above) or pass closer than s + s; cores that do not meet are closest at a
+// vertex of one and an edge of the other, and a core of one or two vertices
+// (a point, a segment) is covered by its edges k -> k+1 all the same.
+// Distances are taken in A's frame with B's vertices mapped as in HALF 0.
+// ---------------------------------------------------------------------------
+// Point p closer than r (r2 = r^2) to segment a-b: nearest point a when the
+// projection parameter c1 <= 0, b when c1 >= c2 = |b - a|^2, else the foot of
+// the perpendicular at squared distance cross^2 / c2.
+__device__ __forceinline__ bool point_segment_close64(double px, double py, double ax, double ay,
+                                                      double bx, double by, double r2) {
+    const double ex = bx - ax, ey = by - ay;
+    const double wx = px - ax, wy = py - ay;
+    const double c1 = wx * ex + wy * ey;
+    if (c1 <= 0.0) return wx * wx + wy * wy < r2;
+    const double c2 = ex * ex + ey * ey;
+    if (c1 >= c2) {
+        const double dx = px - bx, dy = py - by;
+        return dx * dx + dy * dy < r2;
+    }
+    const double cr = ex * wy - ey * wx;
+    return cr * cr < r2 * c2;
+}
+
+__device__ __forceinline__ bool polygon_cores_close64(const SpeciesDev& P, double rx, double ry,
+                                                      double cA, double sA, double cB, double sB) {
+    constexpr int MV = kMaxPolyVerts;
+    const int nv = P.nv;
+    const double zc = cA * cB + sA * sB;
+    const double zs = cA * sB - sA * cB;
+    const double tx = cA * rx + sA * ry;
+    const double ty = cA * ry - sA * rx;
+    const double reach = P.sweep + P.sweep;
+    const double r2 = reach * reach;
+    // B's vertices in A's frame, in registers (compile-time indices only)
+    double bx[MV], by[MV];
+#pragma unroll
+    for (int j = 0; j < MV; ++j) {
+        bx[j] = 0.0;
+        by[j] = 0.0;
+        if (j < nv) {
+            bx[j] = (zc * P.vx[j] - zs * P.vy[j]) + tx;
+            by[j] = (zs * P.vx[j] + zc * P.vy[j]) + ty;
+        }
+    }
+    // the uniform loop runs over A's vertex / edge k (scalar reads), the
+    // unrolled one over B's
+    for (int k = 0; k < nv; ++k) {
+        const int k1 = k + 1 < nv ? k + 1 : 0;
+        const double ax = P.vx[k], ay = P.vy[k], ax1 = P.vx[k1], ay1 = P.vy[k1];
+#pragma unroll
+        for (int j = 0; j < MV; ++j) {
+            if (j < nv) {
+                // A's vertex k against B's edge j -> j+1
+                const double bx1 = j + 1 < nv ? bx[j + 1 < MV ? j + 1 : 0] : bx[0];
+                const double by1 = j + 1 < nv ? by[j + 1 < MV ? j + 1 : 0] : by[0];
+                if (point_segment_close64(ax, ay, bx[j], by[j], bx1, by1, r2)) return true;
+                // B's vertex j against A's edge k -> k+1
+                if (point_segment_close64(bx[j], by[j], ax, ay, ax1, ay1, r2)) return true;
+            }
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool spheropolygon_overlap64(const SpeciesDev& P, double rx, double ry,
+                                                        double cA, double sA, double cB, double sB) {
+    return polygon_overlap64<0>(P, rx, ry, cA, sA, cB, sB) ||
+           polygon_cores_close64(P, rx, ry, cA, sA, cB, sB);
+}
+
+// ---------------------------------------------------------------------------
 // Convex polyhedra, XenoCollide (minkowski portal refinement; Jacobs 2008,
 // Snethen).  D = B - A in A's frame, support S_D(n) = M S_B(M^T n) + t -
 // S_A(-n) (Eq. 2, with the centre offset rotated into A's frame), where S_X

@@ -9,7 +9,15 @@ constexpr int kMaxPolyVerts = 8;     // polygons: 3..8 vertices
 constexpr int kMaxPolyhedronVerts = 64;
 constexpr int kMaxHistBins = 64;     // pair-separation histogram
 
-enum Kind : int32_t { kDisk = 0, kPolygon = 1, kPolyhedron = 2 };
+// kSpheropolygon: a polygon species with a sweep radius (its own kernels:
+// binary64 tests only); the public API names it a polygon with
+// sweep_radius > 0.
+enum Kind : int32_t { kDisk = 0, kPolygon = 1, kPolyhedron = 2, kSpheropolygon = 3 };
+constexpr int kNumKinds = 4;
+
+// Orientation components per particle: none (disks), a unit complex number
+// (2D shapes), a unit quaternion (polyhedra).
+constexpr int orient_comps(int kind) { return kind == kDisk ? 0 : (kind == kPolyhedron ? 4 : 2); }
 
 // Bytes per particle of the cell-sorted binary32 coordinate copy.
 constexpr int xs_bytes(int dim) { return dim == 3 ? 16 : 8; }
@@ -35,7 +43,7 @@ struct alignas(16) SpeciesDev {
     double circ2;    // circumsphere threshold (R + R)^2
     double tol2;     // squared XenoCollide tolerance
     double d, a, p_rot;
-    double sweep;    // sweep radius of a spheropolyhedron, 0 otherwise
+    double sweep;    // sweep radius of a spheropolygon / -polyhedron, 0 otherwise
     double vx[kMaxPolyhedronVerts], vy[kMaxPolyhedronVerts], vz[kMaxPolyhedronVerts];
     double nx[kMaxPolyVerts], ny[kMaxPolyVerts];      // polygon outward edge normals
     double pmin[kMaxPolyVerts], pmax[kMaxPolyVerts];  // own projections onto them

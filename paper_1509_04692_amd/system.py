@@ -15,7 +15,7 @@ comparison variants "register" and "global" (grid path only).
 
 ``species`` is a dict (or one per replica) with keys dim, shape ("disk",
 "polygon", "polyhedron"), verts (n x dim), diameter, d, a, p_rot, rounds and
-(polyhedra) sweep_radius,
+(polygons and polyhedra) sweep_radius,
 as produced by ``paper_1509_04692_amd.inputs``.
 """
 import ctypes

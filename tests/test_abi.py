@@ -153,8 +153,20 @@ def test_sweep_radius_rules(lib):
     assert ws_bytes(lib, [dict(sph, sweep_radius=0.0)], [512], [8.75])[0] == -1
     assert ws_bytes(lib, [dict(sph, sweep_radius=-0.5)], [512], [8.75])[0] == -1
     pent = dict(inputs.pentagon_species(), sweep_radius=0.1)
-    assert ws_bytes(lib, [pent], [1024], [32.0])[0] == -1          # polyhedra only
+    assert ws_bytes(lib, [pent], [1024], [32.0])[0] == 0           # a spheropolygon
     assert ws_bytes(lib, [inputs.spherocylinder_species()], [512], [16.5])[0] == 0
+    stadium = inputs.stadium_species(1.0, 0.25)
+    assert ws_bytes(lib, [stadium], [512], [40.0])[0] == 0         # two-vertex core
+    assert ws_bytes(lib, [dict(stadium, sweep_radius=0.0)], [512], [40.0])[0] == -1
+    dot = inputs.rounded_polygon_species([[0.0, 0.0]], 0.5)
+    assert ws_bytes(lib, [dot], [512], [40.0])[0] == 0             # one-vertex core: a disk
+    assert ws_bytes(lib, [dict(disk := inputs.disk_species(), sweep_radius=0.1)], [512], [40.0])[0] == -1
+    assert disk["shape"] == "disk"
+    # swept polygons run the wave queue only
+    for q in ("register", "global"):
+        assert ws_bytes(lib, [pent], [1024], [32.0], path=1, flags=_lib.QUEUE_FLAGS[q])[0] == -7
+        assert ws_bytes(lib, [inputs.pentagon_species()], [1024], [32.0], path=1,
+                        flags=_lib.QUEUE_FLAGS[q])[0] == 0
 
 
 def test_box_growth_limit(lib):

@@ -133,6 +133,59 @@ def test_spheropolyhedra(shape, path, precision):
     assert st["pair_fp64"] == st["pair_tests"] > 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["rounded_pentagons", "stadiums", "dots"])
+@pytest.mark.parametrize("path", ["grid", "persistent"])
+def test_spheropolygons(shape, path, precision):
+    """Swept polygons (cores overlapping or closer than twice the sweep
+    radius, binary64 in both precisions) against the oracle: rounded
+    pentagons, stadiums (two-vertex cores) and one-vertex cores (disks)."""
+    if shape == "rounded_pentagons":
+        sp, N, L, pos, orient = inputs.workload_rounded_pentagons(1024, 0.55)
+    elif shape == "stadiums":
+        sp, N, L, pos, orient = inputs.workload_stadiums(1024, 0.25)
+    else:
+        sp = inputs.rounded_polygon_species([[0.0, 0.0]], 0.5, d=0.1, a=0.2, p_rot=0.5)
+        L, pos, orient = inputs.initial_state(sp, 1024, 0.55)
+    system, gpu, ref = run_pair(sp, L, pos, orient, 20, seed=29, precision=precision, path=path)
+    assert_parity(gpu, ref, sp)
+    assert system.count_overlaps()[0] == 0
+    st = system.stats()[0]
+    assert st["pair_fp64"] == st["pair_tests"] > 0
+    assert 0 < st["overlap_reject"] and 0 < st["accept"]
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 16, 64])
+def test_spheropolygon_lane_counts_and_a_mixed_batch(lanes):
+    """Every lanes-per-cell width of the grid path, then a persistent batch
+    holding spheropolygons beside plain polygons and disks (one group per
+    kind), each replica against the oracle."""
+    sp, N, L, pos, orient = inputs.workload_rounded_pentagons(900, 0.6)
+    announce(f"rounded pentagons lanes={lanes}")
+    system = _system(sp, N, L, pos, orient, path="grid")
+    system.set_config(lanes)
+    system.sweep(12, 31)
+    ref_pos, ref_ori = pos.copy(), orient.copy()
+    ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=31, n_sweeps=12)
+    assert_parity((system.positions(), system.orientations(), system.stats()[0]),
+                  (ref_pos, ref_ori, ref_stats), sp)
+    if lanes != 64:
+        return
+    items = [inputs.workload_rounded_pentagons(700, 0.5), inputs.workload_pentagons(600, 0.6),
+             inputs.workload_stadiums(500, 0.25), inputs.workload_disks_256()]
+    announce("batch of spheropolygons, pentagons, stadiums, disks")
+    system = _system([i[0] for i in items], [i[1] for i in items], [i[2] for i in items],
+                     [i[3] for i in items], [i[4] for i in items], precision="mixed",
+                     path="persistent")
+    system.sweep(70, 33)
+    for r, (sp, N, L, pos, orient) in enumerate(items):
+        ref_pos, ref_ori = pos.copy(), orient.copy()
+        ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=33, n_sweeps=70, replica=r)
+        assert_parity((system.positions(r), system.orientations(r), system.stats()[r]),
+                      (ref_pos, ref_ori, ref_stats), sp)
+    assert list(system.count_overlaps()) == [0, 0, 0, 0]
+
+
 def test_autotuned_mixed_polyhedra_equal_the_oracle():
     """The autotuner may move mixed-precision polyhedra to the binary64 walk;
     either way the trajectory is the oracle's."""
@@ -352,7 +405,7 @@ def test_graph_replay_direct_launch_and_autotune_agree(path):
     assert np.array_equal(g.positions(), ref_pos) and np.array_equal(g.orientations(), ref_ori)
 
 
-@pytest.mark.parametrize("kind", ["disk", "pentagon", "cube"])
+@pytest.mark.parametrize("kind", ["disk", "pentagon", "cube", "rounded_pentagon"])
 def test_count_overlaps_matches_oracle_on_overlapping_states(kind):
     """Random (overlapping) states cannot be initialised, so the count is
     checked after placing particles by a sweep-free route: a valid state is
@@ -363,13 +416,15 @@ def test_count_overlaps_matches_oracle_on_overlapping_states(kind):
         sp, N, L, pos, orient = inputs.workload_disks_256()
     elif kind == "pentagon":
         sp, N, L, pos, orient = inputs.workload_pentagons(1024, 0.5)
+    elif kind == "rounded_pentagon":
+        sp, N, L, pos, orient = inputs.workload_rounded_pentagons(1024, 0.5)
     else:
         sp, N, L, pos, orient = inputs.workload_cubes(512, 0.3)
     announce(f"count {kind}")
     system = _system(sp, N, L, pos, orient)
     rnd_pos = np.ascontiguousarray(rng.uniform(0, L, size=pos.shape))
     rnd_ori = orient.copy()
-    if kind == "pentagon":
+    if kind in ("pentagon", "rounded_pentagon"):
         t = rng.uniform(-np.pi, np.pi, size=N)
         rnd_ori = np.ascontiguousarray(np.stack([np.cos(t), np.sin(t)]))
     elif kind == "cube":
@@ -415,7 +470,8 @@ def test_pair_histogram_matches_oracle(kind):
     assert err.value.code == -7
 
 
-@pytest.mark.parametrize("kind", ["disk", "pentagon", "sphere", "trunc_oct", "cube_mixed"])
+@pytest.mark.parametrize("kind", ["disk", "pentagon", "sphere", "trunc_oct", "cube_mixed",
+                                  "stadium"])
 def test_scale_counts_match_oracle(kind):
     """Volume-perturbation counts of an equilibrated state (oracle sweeps from
     the lattice): every scale factor's count equals the oracle's all-pairs
@@ -428,6 +484,8 @@ def test_scale_counts_match_oracle(kind):
         sp, N, L, pos, orient = inputs.workload_spheres(500, 0.45)
     elif kind == "trunc_oct":
         sp, N, L, pos, orient = inputs.workload_truncated_octahedra_solid(250, 0.70)
+    elif kind == "stadium":
+        sp, N, L, pos, orient = inputs.workload_stadiums(500, 0.25)
     else:
         sp, N, L, pos, orient = inputs.workload_cubes(512, 0.45)
     oracle.sweep(sp, L, pos, orient, seed=23, n_sweeps=15)

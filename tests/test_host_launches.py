@@ -80,6 +80,11 @@ DRIVER = textwrap.dedent(r"""
     run([inputs.workload_pentagons(4096, 0.6)] * 2, 1, 2)  # the headline replica: LDS near the limit
     run([inputs.workload_pentagons(4096, 0.6)] * 2, 0, 2)
     run(inputs.screening_batch(6, seed=2026, n_lo=3000, n_hi=4096), 1, 2)
+    # spheropolygons: grid path (every lanes-per-cell candidate) and a batch
+    # mixing them with plain polygons, stadiums and disks
+    run([inputs.workload_rounded_pentagons(1500, 0.5)], 1, 1)
+    run([inputs.workload_rounded_pentagons(900, 0.5), inputs.workload_stadiums(500, 0.25),
+         inputs.workload_pentagons(600, 0.6), inputs.workload_disks_256()], 1, 2)
     # the scratch-free entry point: its workspace is the library's static array
     def run_static(items, precision, path):
         n = len(items)
