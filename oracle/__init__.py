@@ -30,6 +30,7 @@ from .oracle import (  # noqa: F401
     scale_positions,
     pair_overlaps,
     philox4x32_10,
+    philox4x32_10_many,
     reset_events,
     serial_metropolis,
     shape_info,

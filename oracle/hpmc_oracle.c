@@ -94,6 +94,12 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 }
 
 /* Uniform in (0,1): (w + 1/2) / 2^32, exact in binary64. */
+void or_philox4x32_10_many(const uint32_t *ctr, int64_t n, const uint32_t key[2], uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        or_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 double or_u01(uint32_t w)
 {
 #ifdef ORACLE_PLANT_U01_NO_HALF

@@ -60,6 +60,8 @@ typedef struct {
 } or_species;
 
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* n counters (4 words each, consecutive) under one key, for bulk checks. */
+void or_philox4x32_10_many(const uint32_t *ctr, int64_t n, const uint32_t key[2], uint32_t *out);
 double or_u01(uint32_t w);
 uint32_t or_index(uint32_t w, uint32_t n);
 void or_sincos(double delta, double *c, double *s);

@@ -63,6 +63,8 @@ def _declare(lib):
     sp = ctypes.POINTER(_Species)
     lib.or_philox4x32_10.argtypes = [_P_U32, _P_U32, _P_U32]
     lib.or_philox4x32_10.restype = None
+    lib.or_philox4x32_10_many.argtypes = [_P_U32, ctypes.c_int64, _P_U32, _P_U32]
+    lib.or_philox4x32_10_many.restype = None
     lib.or_u01.argtypes = [ctypes.c_uint32]
     lib.or_u01.restype = ctypes.c_double
     lib.or_index.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
@@ -100,6 +102,14 @@ def _declare(lib):
     lib.or_serial_metropolis.restype = ctypes.c_int
 
 
+def _stale(lib_path):
+    """True when the library is missing or older than the C source or header."""
+    if not os.path.exists(lib_path):
+        return True
+    t = os.path.getmtime(lib_path)
+    return any(os.path.getmtime(os.path.join(_HERE, f)) > t for f in ("hpmc_oracle.c", "hpmc_oracle.h"))
+
+
 def load(path=None):
     """Load (building first if absent) the oracle library."""
     global _lib
@@ -108,7 +118,7 @@ def load(path=None):
         _declare(lib)
         return lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        if _stale(_LIB_PATH):
             build()
         _lib = ctypes.CDLL(_LIB_PATH)
         _declare(_lib)
@@ -119,7 +129,7 @@ def load_counting():
     """The event-counting build (ORACLE_COUNT_OPS), built on first use."""
     global _lib_ops
     if _lib_ops is None:
-        if not os.path.exists(_LIB_OPS_PATH):
+        if _stale(_LIB_OPS_PATH):
             build(extra_flags=["-DORACLE_COUNT_OPS"], out_path=_LIB_OPS_PATH)
         lib = ctypes.CDLL(_LIB_OPS_PATH)
         _declare(lib)
@@ -177,6 +187,16 @@ def philox4x32_10(ctr, key, lib=None):
     o = (ctypes.c_uint32 * 4)()
     lib.or_philox4x32_10(c, k, o)
     return tuple(int(x) for x in o)
+
+
+def philox4x32_10_many(ctr, key, lib=None):
+    """Philox4x32-10 of every row of an (n, 4) uint32 counter array."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    out = np.zeros_like(ctr)
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    (lib or load()).or_philox4x32_10_many(ctr.ctypes.data_as(_P_U32), int(ctr.shape[0]), k,
+                                          out.ctypes.data_as(_P_U32))
+    return out
 
 
 def u01(w, lib=None):

@@ -36,6 +36,17 @@ def test_philox_known_answers():
         assert oracle.philox4x32_10(ctr, key) == want
 
 
+def test_philox_bulk_equals_single_calls():
+    """The bulk entry point used by the device probe is the single-counter
+    generator row by row (known-answer vectors included)."""
+    rng = np.random.Generator(np.random.PCG64(94))
+    ctr = rng.integers(0, 2 ** 32, size=(500, 4), dtype=np.uint64).astype(np.uint32)
+    key = (0x9E3779B9, 0x01234567)
+    out = oracle.philox4x32_10_many(ctr, key)
+    for i in range(len(ctr)):
+        assert tuple(int(x) for x in out[i]) == oracle.philox4x32_10(ctr[i], key)
+
+
 def test_philox_known_answers_detect_planted_round_count(planted):
     lib = planted("ORACLE_PLANT_PHILOX_9_ROUNDS")
     ctr, key, want = _kat()[0]
