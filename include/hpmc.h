@@ -53,6 +53,10 @@ extern "C" {
 #define HPMC_ERR_HIP (-5)                 /* a HIP runtime call failed */
 #define HPMC_ERR_SWEEP_OVERFLOW (-6)      /* sweep counter would reach 2^32 */
 #define HPMC_ERR_UNSUPPORTED (-7)         /* valid request the library does not support */
+#define HPMC_ERR_CELL_OVERFLOW (-8)       /* a persistent 2D cell list outgrew its ghost-column
+                                             slots: only a state with overlaps written into
+                                             the caller's arrays can do that; the sweeps
+                                             stopped without moving a particle */
 
 /* The persistent path launches one kernel per this many sweeps (a call of
  * n sweeps: n / 64 such launches, then one launch of the n % 64 left). */
@@ -268,7 +272,8 @@ int hpmc_pair_histogram(hpmc_state *st, int32_t replica, const double *edges2, i
 int hpmc_count_overlaps(hpmc_state *st, uint64_t *out_per_replica);
 
 /* Counters per replica.  out_per_replica: host, n_replicas entries.
- * Synchronising. */
+ * Synchronising.  HPMC_ERR_CELL_OVERFLOW (counters still filled in) when a
+ * persistent sweep since the last reset stopped on a cell-list overflow. */
 int hpmc_get_stats(hpmc_state *st, hpmc_stats *out_per_replica);
 int hpmc_reset_stats(hpmc_state *st);
 

@@ -18,6 +18,7 @@ ERRORS = {
     -5: "HIP runtime error",
     -6: "sweep counter would exceed 2^32",
     -7: "unsupported configuration",
+    -8: "cell list overflow (overlapping state)",
 }
 SHAPES = {"disk": 0, "polygon": 1, "polyhedron": 2}
 PRECISIONS = {"fp64": 0, "mixed": 1}

@@ -229,6 +229,68 @@ int highest_fit(const BatchGroup& g, int lv) {
     return 0;
 }
 
+// Ghost-column slots a persistent 2D replica needs at most: the particles of
+// two columns of cells.  Particles that do not overlap have disjoint
+// inscribed disks of radius r_in, and the disks of the particles centred in
+// one cell (width w < 1.5 d_max, as n >= 4 is the largest even count with
+// w >= d_max) lie in a square of side w + 2 r_in, so a cell holds at most
+// (w + 2 r_in)^2 / (pi r_in^2) of them.  0 (no ghost columns) for 3D kinds,
+// for shapes whose centre is not inside them, and where the slots would
+// exceed the 16-bit cell list.
+int ghost_capacity(const SpeciesDev& P, int N, int n_cap) {
+    if (P.kind == kPolyhedron) return 0;
+    double r_in = 0.0;
+    if (P.kind == kDisk) {
+        r_in = P.R;
+    } else {
+        if (P.nv >= 3) {
+            r_in = INFINITY;
+            for (int k = 0; k < P.nv; ++k)
+                r_in = std::fmin(r_in, P.pmax[k] / std::sqrt(P.nx[k] * P.nx[k] + P.ny[k] * P.ny[k]));
+            if (!(r_in > 0.0)) r_in = 0.0;
+        }
+        r_in += P.sweep;
+    }
+    if (!(r_in > 0.0)) return 0;
+    const double w = 1.5 * (P.R + P.R) * (1.0 + 1e-9);
+    const double per_cell = std::floor((w + 2.0 * r_in) * (w + 2.0 * r_in) / (3.141592653589793 * r_in * r_in)) + 1.0;
+    const double cap = std::fmin((double)N, 2.0 * (double)n_cap * per_cell);
+    if ((double)N + cap > 65535.0) return 0;
+    return (int)cap;
+}
+
+// Dynamic LDS per residency level for the replicas of group g at `block`
+// lanes, the levels that fit, and those that keep ghost edge columns (2D
+// kinds at levels 0-2, wherever every replica has a ghost capacity and the
+// larger layout fits).
+void group_lds_levels(BatchGroup& g, const std::vector<int32_t>& list, const std::vector<ReplicaHost>& rep,
+                      int precision, int block, size_t limit) {
+    size_t plain[kResidencyLevels] = {}, ghost[kResidencyLevels] = {};
+    bool all_ghost = true;
+    for (int j = g.first; j < g.first + g.count; ++j) {
+        const ReplicaHost& h = rep[list[j]];
+        all_ghost &= h.ghost_cap > 0;
+        for (int lv = 0; lv < kResidencyLevels; ++lv) {
+            plain[lv] = std::max(plain[lv], persistent_lds_bytes(g.kind, precision, h.ncells_cap, h.n_cap, h.N,
+                                                                 lv, block, 0));
+            if (lv <= 2 && h.ghost_cap > 0)
+                ghost[lv] = std::max(ghost[lv], persistent_lds_bytes(g.kind, precision, h.ncells_cap, h.n_cap,
+                                                                     h.N, lv, block, h.ghost_cap));
+        }
+    }
+    g.fits = 1;
+    g.ghost = 0;
+    for (int lv = 0; lv < kResidencyLevels; ++lv) {
+        g.need[lv] = plain[lv];
+        if (lv <= 2 && all_ghost && g.kind != kPolyhedron && ghost[lv] <= limit) {
+            g.need[lv] = ghost[lv];
+            g.ghost |= 1 << lv;
+        }
+        // disks have no orientations, so their level 2 is level 1
+        if (lv >= 1 && g.need[lv] <= limit && !(g.kind == kDisk && lv == 2)) g.fits |= 1 << lv;
+    }
+}
+
 // Queue mode from hpmc_init_args.flags; -1 when both variants are asked for.
 int queue_mode(int32_t flags) {
     const bool reg = (flags & HPMC_FLAG_REGISTER_QUEUE) != 0, glob = (flags & HPMC_FLAG_GLOBAL_QUEUE) != 0;
@@ -279,6 +341,7 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         rc = build_grid(a->species[r], spc[r], a->N[r], L_max, smax, hmax);
         if (rc) return rc;
         rep[r].ncells_cap = std::max(smax.ncells, sys[r].ncells);
+        rep[r].n_cap = std::max(hmax.n, rep[r].n);
         rep[r].L_max = L_max;
         sys[r].species = r;
         sys[r].replica = r;
@@ -296,8 +359,8 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
         cell_total += (int64_t)rep[r].ncells_cap + 1;
         slot_total += sys[r].N;
         part_total += ((int64_t)rep[r].ncells_cap + kScanTile - 1) / kScanTile;
-        const size_t lb = persistent_lds_bytes(spc[r].kind, a->precision, rep[r].ncells_cap, sys[r].N, 0,
-                                               kBatchBlock);
+        const size_t lb = persistent_lds_bytes(spc[r].kind, a->precision, rep[r].ncells_cap, rep[r].n_cap,
+                                               sys[r].N, 0, kBatchBlock, 0);
         if (sys[r].N > 65535 || lb > lds_limit) fits_lds = false;
         const int half = sys[r].n / 2;
         const int64_t n_act = sys[r].dim == 3 ? (int64_t)half * half * half : (int64_t)half * half;
@@ -312,6 +375,9 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
     for (int r = 0; r < R; ++r) {
         sys[r].path = path;
         rep[r].path = path;
+        const int cap = path == HPMC_PATH_PERSISTENT ? ghost_capacity(spc[r], sys[r].N, rep[r].n_cap) : 0;
+        sys[r].ghost_cap = cap;
+        rep[r].ghost_cap = cap;
     }
     // persistent path: one launch per shape kind; positions held in LDS when
     // every replica of the kind fits
@@ -336,39 +402,35 @@ int plan(const hpmc_init_args* a, std::vector<ReplicaHost>& rep, std::vector<Sys
             }
             g.block = persistent_block(n_act_max, n_max);
             g.block_base = g.block;
-            size_t need[kResidencyLevels] = {};
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
                 list.push_back(r);
                 g.count++;
                 g.nv = (g.nv == -1 || g.nv == spc[r].nv) ? spc[r].nv : 0;
-                for (int lv = 0; lv < kResidencyLevels; ++lv)
-                    need[lv] = std::max(need[lv], persistent_lds_bytes(kind, a->precision, rep[r].ncells_cap,
-                                                                       sys[r].N, lv, g.block));
             }
             if (g.count == 0) continue;
             // largest replicas first: work-groups start in list order, so the
             // longest ones do not wait behind short ones for a compute unit
             std::stable_sort(list.begin() + g.first, list.end(),
                              [&](int32_t x, int32_t y) { return sys[x].N > sys[y].N; });
-            // levels whose LDS fits (level 0 always); disks have no
-            // orientations, so their level 2 is level 1
-            g.fits = 1;
-            for (int lv = 1; lv < kResidencyLevels; ++lv)
-                if (need[lv] <= lds_limit && !(kind == kDisk && lv == 2)) g.fits |= 1 << lv;
-            for (int lv = 0; lv < kResidencyLevels; ++lv) g.need[lv] = need[lv];
+            // levels whose LDS fits (level 0 always)
+            group_lds_levels(g, list, rep, a->precision, g.block, lds_limit);
             // before autotuning: the binary32 copy kept when it fits (level
             // 2, else 1), level 3 only when neither fits
             g.resident = highest_fit(g, 2);
             if (g.resident == 0 && (g.fits & 8)) g.resident = 3;
-            g.lds_bytes = need[g.resident];
+            g.lds_bytes = g.need[g.resident];
             if (g.nv < 0) g.nv = 0;
             groups.push_back(g);
         }
     } else {
         // grid path: one launch per step for all replicas of a kind
         for (int kind = 0; kind < kNumKinds; ++kind) {
-            BatchGroup g{kind, (int32_t)list.size(), 0, 0, 0, -1, 0, {0, 0, 0}, 0, 1, 0, 0, 0, 0};
+            BatchGroup g{};
+            g.kind = kind;
+            g.first = (int32_t)list.size();
+            g.nv = -1;
+            g.lanes = 1;
             int64_t n_act_total = 0;
             for (int r = 0; r < R; ++r) {
                 if (spc[r].kind != kind) continue;
@@ -591,18 +653,7 @@ int group_block(const BatchGroup& g, int code) {
 // LDS per residency level and the levels that fit, for the group's replicas
 // at `block` lanes.
 void group_lds(const hpmc_state* st, BatchGroup& g, int block) {
-    size_t need[kResidencyLevels] = {};
-    for (int j = g.first; j < g.first + g.count; ++j) {
-        const int r = st->list[j];
-        for (int lv = 0; lv < kResidencyLevels; ++lv)
-            need[lv] = std::max(need[lv], persistent_lds_bytes(g.kind, st->precision, st->rep[r].ncells_cap,
-                                                               st->rep[r].N, lv, block));
-    }
-    const size_t limit = device_lds_limit();
-    g.fits = 1;
-    for (int lv = 1; lv < kResidencyLevels; ++lv)
-        if (need[lv] <= limit && !(g.kind == kDisk && lv == 2)) g.fits |= 1 << lv;
-    for (int lv = 0; lv < kResidencyLevels; ++lv) g.need[lv] = need[lv];
+    group_lds_levels(g, st->list, st->rep, st->precision, block, device_lds_limit());
 }
 
 // Lanes-per-cell or residency choices (with the walk bit) of the first
@@ -1042,9 +1093,12 @@ int hpmc_scale_box(hpmc_state* st, int32_t replica, double L_new, uint64_t* over
     S.slot_off = old.slot_off;
     S.part_off = old.part_off;
     S.drain_at = old.drain_at;
+    S.ghost_cap = old.ghost_cap;
     const ReplicaHost& oh = st->rep[r];
     rh.path = oh.path;
     rh.lanes_per_cell = oh.lanes_per_cell;
+    rh.ghost_cap = oh.ghost_cap;
+    rh.n_cap = oh.n_cap;
     rh.nv = oh.nv;
     rh.pos_off = oh.pos_off;
     rh.orient_off = oh.orient_off;
@@ -1137,8 +1191,9 @@ int hpmc_get_stats(hpmc_state* st, hpmc_stats* out) {
         out[r].pair_tests = v[kPairTests];
         out[r].pair_fp64 = v[kPairFp64];
         out[r].sweeps = st->sweeps_done;
+        if (v[kCellOverflow]) rc = HPMC_ERR_CELL_OVERFLOW;
     }
-    return HPMC_OK;
+    return rc;
 }
 
 int hpmc_reset_stats(hpmc_state* st) {
@@ -1322,6 +1377,7 @@ const char* hpmc_strerror(int code) {
         case HPMC_ERR_HIP: return "HIP runtime error";
         case HPMC_ERR_SWEEP_OVERFLOW: return "sweep counter would exceed 2^32";
         case HPMC_ERR_UNSUPPORTED: return "unsupported configuration";
+        case HPMC_ERR_CELL_OVERFLOW: return "cell list overflow (overlapping state)";
         default: return "unknown error";
     }
 }

@@ -141,8 +141,11 @@ struct PosView {
 };
 
 struct GlobalCells {
+    static constexpr bool ghost = false;
     const uint32_t* __restrict__ start;
     const uint32_t* __restrict__ members;
+    // storage index of cell cc (linear index c)
+    __device__ __forceinline__ uint32_t index(const int (&)[3], uint32_t c, int) const { return c; }
     __device__ __forceinline__ uint32_t begin(uint32_t c) const { return start[c]; }
     __device__ __forceinline__ uint32_t end(uint32_t c) const { return start[c + 1]; }
     __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
@@ -150,8 +153,27 @@ struct GlobalCells {
 
 // LDS cell list: inclusive ends[ncells] and members (16-bit tags).
 struct LdsCells {
+    static constexpr bool ghost = false;
     const uint16_t* ends;
     const uint16_t* members;
+    __device__ __forceinline__ uint32_t index(const int (&)[3], uint32_t c, int) const { return c; }
+    __device__ __forceinline__ uint32_t begin(uint32_t c) const { return c ? ends[c - 1] : 0u; }
+    __device__ __forceinline__ uint32_t end(uint32_t c) const { return ends[c]; }
+    __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
+};
+
+// LDS cell list of a 2D grid with ghost edge columns: every row of n cells
+// is stored as n + 2, the first a copy of the row's last cell and the last a
+// copy of its first, their binary32 coordinates shifted by -L and +L.  The
+// cells x - 1 .. x + 1 of any row are then one contiguous slot range, with
+// no periodic wrap along x.  Storage index of cell (x, y): x + 1 + (n + 2) y.
+struct LdsGhostCells {
+    static constexpr bool ghost = true;
+    const uint16_t* ends;
+    const uint16_t* members;
+    __device__ __forceinline__ uint32_t index(const int (&cc)[3], uint32_t, int n) const {
+        return (uint32_t)(cc[0] + 1 + (n + 2) * cc[1]);
+    }
     __device__ __forceinline__ uint32_t begin(uint32_t c) const { return c ? ends[c - 1] : 0u; }
     __device__ __forceinline__ uint32_t end(uint32_t c) const { return ends[c]; }
     __device__ __forceinline__ uint32_t member(uint32_t p) const { return members[p]; }
@@ -351,10 +373,26 @@ struct Neighbourhood {
     static constexpr int ranges = D == 3 ? 18 : 6;
 };
 
+// Neighbour slot range ri of cell cc for the pre-filter, with the reference
+// point (the trial position, shifted by +-L where the range wraps).  Plain
+// lists: per row an in-row range (ri even) and the x-wrapped cell (ri odd,
+// empty unless cc sits at an x edge).  Ghost lists (2D): one range per row.
 template <int D, class CELLS>
 __device__ __forceinline__ void neighbour_range(const CELLS& cl, const int (&cc)[3], int n, int ri,
                                                 double L, const double (&yn)[3], uint32_t& b,
                                                 uint32_t& e, float (&ref)[3]) {
+    if constexpr (CELLS::ghost) {
+        static_assert(D == 2, "ghost edge columns are a 2D layout");
+        const int yy = cc[1] + ri - 1;
+        const int y = wrap_cell(yy, n);
+        ref[0] = (float)yn[0];
+        ref[1] = (float)(yy < 0 ? yn[1] + L : (yy >= n ? yn[1] - L : yn[1]));
+        ref[2] = 0.0f;
+        const uint32_t base = (uint32_t)((n + 2) * y + cc[0]);  // storage index of x - 1
+        b = cl.begin(base);
+        e = cl.end(base + 2u);
+        return;
+    }
     const int row = ri >> 1;
     const int yy = cc[1] + (row % 3) - 1;
     const int zz = D == 3 ? cc[2] + (row / 3) - 1 : 0;
@@ -635,7 +673,8 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         // matter there, and most waves then skip the x-wrapped ranges (in 3D
         // a wave spans several x columns, so nearly every wave holds an edge)
         active_cell<YF && D == 2>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
-        const uint32_t beg = cl.begin(c), fin = cl.end(c);
+        const uint32_t ci = cl.index(cc, c, n);  // storage index (c unless ghost columns)
+        const uint32_t beg = cl.begin(ci), fin = cl.end(ci);
         if (beg != fin) {
             ct.attempted++;
             const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
@@ -708,7 +747,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         // (lane `sub` of a group takes ranges sub, sub + G, ...), queued exact
         // tests.  The outer loop over ranges is uniform; each inner loop runs to
         // the longest range of the wave.
-        constexpr int NR = Neighbourhood<D>::ranges;
+        constexpr int NR = CELLS::ghost ? 3 : Neighbourhood<D>::ranges;
         constexpr int NK = (NR + G - 1) / G;
         constexpr bool TAGQ = kGlobalList<CELLS>;
         constexpr int U = kScanUnroll<D, TAGQ>;
@@ -721,9 +760,9 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
         uint32_t queued2 = 0;  // wave-uniform, polygons only
         // with one lane per cell, the x-wrapped (odd) ranges are empty unless a
         // live cell of the wave sits at the periodic x edge: skip them then
-        const bool x_edge = G > 1 || wave_ballot(live && (cc[0] == 0 || cc[0] == n - 1)) != 0ull;
+        const bool x_edge = G > 1 || CELLS::ghost || wave_ballot(live && (cc[0] == 0 || cc[0] == n - 1)) != 0ull;
         for (int kr = 0; kr < NK; ++kr) {
-            if (G == 1 && (kr & 1) && !x_edge) continue;
+            if (G == 1 && !CELLS::ghost && (kr & 1) && !x_edge) continue;
             const int ri = sub + kr * G;
             uint32_t p = 0, e = 0;
             float ref[3] = {0.0f, 0.0f, 0.0f};
@@ -807,7 +846,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
 #pragma unroll
             for (int c4 = 0; c4 < 4; ++c4) qn[c4] = __shfl(qn[c4], leader, 64);
         }
-        constexpr int NR = Neighbourhood<D>::ranges;
+        constexpr int NR = CELLS::ghost ? 3 : Neighbourhood<D>::ranges;
         constexpr int NK = (NR + G - 1) / G;
         const float t2 = S.scan_t2;
         bool flagged = false;
@@ -861,10 +900,22 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     ct.overlap_reject += (sub == 0 && rejected) ? 1u : 0u;
     ct.accept += (sub == 0 && live && !rejected) ? 1u : 0u;
     if (sub == 0 && live) {
-        if (!rejected && c_moved)
+        if (!rejected && c_moved) {
             xs.store(pi, yn);
-        else if (PARK)
+            if constexpr (CELLS::ghost) {
+                // the ghost copy of an edge-column particle follows it: same
+                // offset in the copy of its cell, x shifted by +L (copy after
+                // the row's last cell) or -L (before its first)
+                if (cc[0] == 0 || cc[0] == n - 1) {
+                    const uint32_t ci = cl.index(cc, c, n);
+                    const uint32_t gi = cc[0] == 0 ? ci + (uint32_t)n : ci - (uint32_t)n;
+                    const double gy[3] = {cc[0] == 0 ? yn[0] + S.L : yn[0] - S.L, yn[1], yn[2]};
+                    xs.store(pi - cl.begin(ci) + cl.begin(gi), gy);
+                }
+            }
+        } else if (PARK) {
             xs.store(pi, own);
+        }
         // only what the move changed
         if (!rejected && c_moved) {
 #pragma unroll

@@ -796,19 +796,24 @@ struct BatchLayout {
 
 // Residency level: 0 = particle data in global memory, 1 = positions in LDS,
 // 2 = positions and orientations in LDS, 3 = the same without the binary32
-// copy.  wave_words: per-wave scratch (wave_scratch_words).
+// copy.  wave_words: per-wave scratch (wave_scratch_words).  ghost_cap > 0
+// (2D, res <= 2): the cell list has ghost edge columns, 2 n more cells and up
+// to ghost_cap more slots.
 __host__ __device__ inline BatchLayout batch_layout(int dim, int ncomp, int N, int ncells,
-                                                    int nwaves, int res, int wave_words) {
+                                                    int nwaves, int res, int wave_words, int n = 0,
+                                                    int ghost_cap = 0) {
     BatchLayout b;
+    const size_t slots = (size_t)N + (size_t)ghost_cap;
+    if (ghost_cap > 0) ncells += 2 * n;
     size_t o = 0;
     b.pos = o;
     o += res >= 1 ? align16((size_t)dim * N * 8) : 0;
     b.ori = o;
     o += res >= 2 ? align16((size_t)ncomp * N * 8) : 0;
     b.xs = o;
-    o += res <= 2 ? align16((size_t)N * (size_t)xs_bytes(dim)) : 0;
+    o += res <= 2 ? align16(slots * (size_t)xs_bytes(dim)) : 0;
     b.mem = o;
-    o += align16((size_t)N * 2);
+    o += align16(slots * 2);
     b.ends = o;
     o += align16((size_t)ncells * 2);
     b.uni = o;
@@ -822,7 +827,7 @@ __host__ __device__ inline BatchLayout batch_layout(int dim, int ncomp, int N, i
     return b;
 }
 
-template <int KIND, int PREC, int RES, int NV>
+template <int KIND, int PREC, int RES, int NV, bool GH>
 __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict__ sys,
                                                        const SpeciesDev* __restrict__ spc,
                                                        const int32_t* __restrict__ list,
@@ -831,16 +836,19 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
                                                        unsigned long long* __restrict__ stats,
                                                        const Clock* __restrict__ clock) {
     constexpr int D = Traits<KIND>::dim;
+    static_assert(!GH || (D == 2 && RES <= 2), "ghost edge columns: 2D, binary32 copy in LDS");
     extern __shared__ __align__(16) unsigned char lds[];
     const int r = list[blockIdx.x];
     const SysDev S = sys[r];
     const SpeciesDev& P = spc[S.species];
     const int tid = threadIdx.x, B = blockDim.x, nwaves = B >> 6, wave = tid >> 6;
-    const int N = S.N, nc = S.ncells;
+    const int N = S.N, nc = S.ncells, n = S.n;
     constexpr int NC = Traits<KIND>::ncomp;
     constexpr int WW = wave_scratch_words(KIND, PREC);
     constexpr bool XS = RES <= 2;  // binary32 cell-sorted copy kept in LDS
-    const BatchLayout lay = batch_layout(D, NC, N, nc, nwaves, RES, WW);
+    const int gcap = GH ? S.ghost_cap : 0;
+    const int nst = GH ? nc + 2 * n : nc;  // stored cells (with the ghost columns)
+    const BatchLayout lay = batch_layout(D, NC, N, nc, nwaves, RES, WW, n, gcap);
     double* gpos = pos_base + S.pos_off;
     double* gori = ori_base + S.orient_off;
     const PosView pos{RES >= 1 ? reinterpret_cast<double*>(lds + lay.pos) : gpos, N};
@@ -862,10 +870,23 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     pc.start();
     const Clock ck = *clock;
     const uint32_t t0 = ck.t, k0 = ck.k0, k1 = ck.k1, n_sweeps = ck.n;
-    const int half = S.n / 2;
+    const int half = n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
-    const int chunk = (nc + B - 1) / B;
+    const int chunk = (nst + B - 1) / B;
     const WaveScratch wscr = wave_scratch(uni + wave * WW);
+    // storage cell of grid coordinates y, and the side of its ghost copy:
+    // +1 (column 0, copied after the row's last cell, x + L), -1 (column
+    // n - 1, copied before the first, x - L), 0 (none)
+    auto stored_cell = [&](const double (&y)[3], int& gh) -> uint32_t {
+        if constexpr (GH) {
+            const int cx = cell_of_coord(y[0], S.inv_w, n), cy = cell_of_coord(y[1], S.inv_w, n);
+            gh = cx == 0 ? 1 : (cx == n - 1 ? -1 : 0);
+            return (uint32_t)(cx + 1 + (n + 2) * cy);
+        } else {
+            gh = 0;
+            return cell_of_grid<D>(S, y);
+        }
+    };
     for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
         const uint32_t t = t0 + sw;
         double sh[3];
@@ -875,31 +896,44 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         // shifted-frame coordinates in registers between the passes
         constexpr int kOwn = kBatchOwn;
         uint32_t own_cell[kOwn];
+        int own_gh[kOwn];
         float own_y[kOwn][3];
+        double own_x[kOwn];
         uint32_t* count = uni;
-        for (int c = tid; c < nc; c += B) count[c] = 0u;
+        for (int c = tid; c < nst; c += B) count[c] = 0u;
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kOwn; ++j) {
             const int i = tid + j * B;
             own_cell[j] = 0u;
+            own_gh[j] = 0;
+            own_x[j] = 0.0;
             own_y[j][0] = own_y[j][1] = own_y[j][2] = 0.0f;
             if (i < N) {
                 double y[3];
                 particle_grid<D>(S, pos, (uint32_t)i, sh, y);
-                own_cell[j] = cell_of_grid<D>(S, y);
+                own_cell[j] = stored_cell(y, own_gh[j]);
+                own_x[j] = y[0];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) own_y[j][a] = (float)y[a];
                 atomicAdd(count + own_cell[j], 1u);
+                if (GH && own_gh[j]) atomicAdd(count + own_cell[j] + own_gh[j] * n, 1u);
             }
         }
-        for (int i = tid + kOwn * B; i < N; i += B) atomicAdd(count + particle_cell<D>(S, pos, (uint32_t)i, sh), 1u);
+        for (int i = tid + kOwn * B; i < N; i += B) {
+            double y[3];
+            particle_grid<D>(S, pos, (uint32_t)i, sh, y);
+            int gh;
+            const uint32_t c = stored_cell(y, gh);
+            atomicAdd(count + c, 1u);
+            if (GH && gh) atomicAdd(count + c + gh * n, 1u);
+        }
         __syncthreads();
+        uint32_t total;
         {
-            const int c0 = tid * chunk, c1 = min(nc, c0 + chunk);
+            const int c0 = tid * chunk, c1 = min(nst, c0 + chunk);
             uint32_t s = 0;
             for (int c = c0; c < c1; ++c) s += count[c];
-            uint32_t total;
             uint32_t run = block_exclusive_scan(s, sm, total);
             for (int c = c0; c < c1; ++c) {
                 const uint32_t v = count[c];
@@ -907,8 +941,14 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
                 run += v;
             }
         }
+        if (GH && total > (uint32_t)(N + gcap)) {
+            // more edge-column particles than the bound for a state without
+            // overlaps allows: stop before any write, report it
+            if (tid == 0) atomicAdd(stat_stripe(stats, r) + kCellOverflow, 1ull);
+            break;
+        }
         __syncthreads();
-        // scatter the tags and their binary32 coordinates
+        // scatter the tags and their binary32 coordinates (ghost copies too)
 #pragma unroll
         for (int j = 0; j < kOwn; ++j) {
             const int i = tid + j * B;
@@ -916,18 +956,36 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
                 const uint32_t slot = atomicAdd(count + own_cell[j], 1u);
                 mem[slot] = (uint16_t)i;
                 if constexpr (XS) xs.store(slot, own_y[j]);
+                if constexpr (GH) {
+                    if (own_gh[j]) {
+                        const uint32_t g = atomicAdd(count + own_cell[j] + own_gh[j] * n, 1u);
+                        mem[g] = (uint16_t)i;
+                        const float gy[3] = {(float)(own_x[j] + (double)own_gh[j] * S.L), own_y[j][1], own_y[j][2]};
+                        xs.store(g, gy);
+                    }
+                }
             }
         }
         for (int i = tid + kOwn * B; i < N; i += B) {
             double y[3];
             particle_grid<D>(S, pos, (uint32_t)i, sh, y);
-            const uint32_t slot = atomicAdd(count + cell_of_grid<D>(S, y), 1u);
+            int gh;
+            const uint32_t c = stored_cell(y, gh);
+            const uint32_t slot = atomicAdd(count + c, 1u);
             mem[slot] = (uint16_t)i;
             if constexpr (XS) xs.store(slot, y);
+            if constexpr (GH) {
+                if (gh) {
+                    const uint32_t g = atomicAdd(count + c + gh * n, 1u);
+                    mem[g] = (uint16_t)i;
+                    const double gy[3] = {y[0] + (double)gh * S.L, y[1], y[2]};
+                    xs.store(g, gy);
+                }
+            }
         }
         __syncthreads();
         // ascending tags within each cell; the coordinates move with their tags
-        for (int c = tid; c < nc; c += B) {
+        for (int c = tid; c < nst; c += B) {
             const uint32_t b = c ? count[c - 1] : 0u, e = count[c];
             ends[c] = (uint16_t)e;
             for (uint32_t p = b + 1; p < e; ++p) {
@@ -950,15 +1008,19 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         }
         __syncthreads();
         pc.mark<kPhBuild>();
-        const LdsCells cl{ends, mem};
+        using CellList = std::conditional_t<GH, LdsGhostCells, LdsCells>;
+        const CellList cl{ends, mem};
         const uint32_t ncol = 1u << D;
         for (int rnd = 0; rnd < S.rounds; ++rnd) {
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
                 for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64) {
                     if constexpr (XS) {
-                        pass_tile<KIND, PREC, 1, NV, true>(S, P, pos, ori, cl, xs, colour, select, t, k0,
-                                                           k1, sh, a0, n_act, wscr, ct, pc);
+                        // ghost columns make x-first order free of wrapped
+                        // ranges; plain lists index y first
+                        pass_tile<KIND, PREC, 1, NV, true, kWaveQueue, !GH>(S, P, pos, ori, cl, xs, colour,
+                                                                            select, t, k0, k1, sh, a0,
+                                                                            n_act, wscr, ct, pc);
                     } else {
                         const PosXsView<D> pxs{mem, pos.p, N, sh[0], sh[1], sh[2], S.L};
                         pass_tile<KIND, PREC, 1, NV, false, kWaveQueue, true>(
@@ -988,10 +1050,13 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
 // ---------------------------------------------------------------------------
 static inline int blocks_for(long n, int b) { return (int)((n + b - 1) / b); }
 
-size_t persistent_lds_bytes(int kind, int precision, int ncells, int N, int res, int block) {
+size_t persistent_lds_bytes(int kind, int precision, int ncells, int n, int N, int res, int block,
+                            int ghost_cap) {
     const int dim = kind == kPolyhedron ? 3 : 2;
     const int ncomp = orient_comps(kind);
-    return batch_layout(dim, ncomp, N, ncells, block / 64, res, wave_scratch_words(kind, precision)).total;
+    return batch_layout(dim, ncomp, N, ncells, block / 64, res, wave_scratch_words(kind, precision), n,
+                        ghost_cap)
+        .total;
 }
 
 hipError_t fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t stream) {
@@ -1156,10 +1221,10 @@ hipError_t grid_passes(const Workspace& ws, const BatchGroup& g, double* pos, do
     return hipGetLastError();
 }
 
-template <int KIND, int PREC, int RES, int NV>
+template <int KIND, int PREC, int RES, int NV, bool GH = false>
 static hipError_t launch_batch(const Workspace& ws, const int32_t* list, int n, int block, size_t lds,
                                double* pos, double* orient, bool prepare, hipStream_t stream) {
-    auto kern = k_batch<KIND, PREC, RES, NV>;
+    auto kern = k_batch<KIND, PREC, RES, NV, GH>;
     if (prepare)  // raise the dynamic-LDS limit (not a stream operation; done before capture)
         return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds);
@@ -1172,6 +1237,19 @@ template <int KIND, int PREC, int NV>
 static hipError_t launch_batch_res(const Workspace& ws, const BatchGroup& g, double* pos,
                                    double* orient, bool prepare, hipStream_t stream) {
     const int32_t* list = ws.batch_list + g.first;
+    if constexpr (KIND != kPolyhedron) {
+        // 2D kinds keep ghost edge columns at the levels where they fit
+        if ((g.ghost >> g.resident) & 1) {
+            if (g.resident == 2 && KIND != kDisk)
+                return launch_batch<KIND, PREC, 2, NV, true>(ws, list, g.count, g.block, g.lds_bytes, pos,
+                                                             orient, prepare, stream);
+            if (g.resident >= 1)
+                return launch_batch<KIND, PREC, 1, NV, true>(ws, list, g.count, g.block, g.lds_bytes, pos,
+                                                             orient, prepare, stream);
+            return launch_batch<KIND, PREC, 0, NV, true>(ws, list, g.count, g.block, g.lds_bytes, pos,
+                                                         orient, prepare, stream);
+        }
+    }
     if (g.resident >= 3)
         return launch_batch<KIND, PREC, 3, NV>(ws, list, g.count, g.block, g.lds_bytes, pos, orient,
                                                prepare, stream);

@@ -69,6 +69,8 @@ struct ReplicaHost {
     int32_t ncells_cap;      // cells allocated for this replica (grid of its largest box)
     double L, L_max;         // current box side, largest allowed (NPT box moves)
     int32_t lanes_per_cell;  // grid path: lanes per active cell (1, 2, 4, ..., 64)
+    int32_t ghost_cap;       // persistent 2D path: ghost-column slots (0: none)
+    int32_t n_cap;           // cells per side of the largest box (L_max)
     int32_t nv;              // polygon vertex count (compile-time fast path for 5)
     int64_t pos_off, orient_off;
 };
@@ -80,6 +82,7 @@ struct BatchGroup {
     int32_t resident;  // persistent: 0 none, 1 positions, 2 positions + orientations in LDS,
                        // 3 the same without the binary32 cell-sorted copy
     int32_t fits;      // bit lv set when residency level lv fits in LDS
+    int32_t ghost;     // bit lv set when level lv keeps ghost edge columns
     int32_t nv;        // common polygon vertex count, 0 when mixed or not a polygon
     size_t lds_bytes;
     size_t need[4];    // dynamic LDS per residency level
@@ -154,7 +157,9 @@ hipError_t read_phase_trace(unsigned long long* out, bool reset);
 constexpr int kResidencyLevels = 4;
 
 // Dynamic LDS of a persistent work-group of `block` lanes for a replica of
-// this kind, precision, cell count and N at residency level res.
-size_t persistent_lds_bytes(int kind, int precision, int ncells, int N, int res, int block);
+// this kind, precision, cell count (n per side) and N at residency level
+// res; ghost_cap > 0: with that many ghost-column slots (2D, res <= 2).
+size_t persistent_lds_bytes(int kind, int precision, int ncells, int n, int N, int res, int block,
+                            int ghost_cap);
 
 }  // namespace hpmc

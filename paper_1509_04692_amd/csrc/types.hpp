@@ -25,7 +25,7 @@ constexpr int xs_bytes(int dim) { return dim == 3 ? 16 : 8; }
 // Counters kept per replica in the workspace (u64 each), same order as
 // hpmc_stats minus the host-side sweep count.
 enum Stat : int { kAttempted = 0, kAttemptedRot, kCellReject, kOverlapReject, kAccept,
-                  kPairTests, kPairFp64, kNumStats };
+                  kPairTests, kPairFp64, kCellOverflow, kNumStats };
 
 // The counters of a replica are kept in kStatStripes copies, one 64-byte line
 // each; a work-group adds into stripe blockIdx % kStatStripes, so that
@@ -87,6 +87,9 @@ struct alignas(16) SysDev {
     // queued full tests at which a wave drains its queue (16, 32 or 64; the
     // autotuner's queue depth)
     uint32_t drain_at;
+    // persistent 2D path: LDS slots reserved for the ghost copies of the two
+    // edge columns of the cell list (0: no ghost columns)
+    int32_t ghost_cap;
 };
 
 // Phases of the per-wave clock of a trace build (HPMC_TRACE): cell-list
