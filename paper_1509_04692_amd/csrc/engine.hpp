@@ -584,10 +584,11 @@ __device__ __forceinline__ void compact_queue(uint32_t* q, uint32_t from, uint32
 }
 
 // Trial move of active cell a (index within its colour): uniform occupant
-// (Philox SELECT), translation or rotation (Philox MOVE keyed on the tag),
-// periodic wrap, and the rule that a translation must stay in the cell.
-// Sets live when the cell is non-empty and the trial stays in it.
-template <int KIND, class POS, class CELLS>
+// (Philox SELECT keyed on the cell), translation or rotation (Philox MOVE
+// keyed on the tag), periodic wrap, and the rule that a translation must
+// stay in the cell.  Sets live when the cell is non-empty and the trial
+// stays in it.  YF: active cells indexed y first (2D).
+template <int KIND, bool YF = false, class POS, class CELLS>
 __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, const POS& pos,
                                         const double* __restrict__ ori, const CELLS& cl,
                                         uint32_t colour, uint32_t select, uint32_t t, uint32_t k0,
@@ -597,8 +598,9 @@ __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, co
                                         bool& c_moved, Counters& ct) {
     constexpr int D = Traits<KIND>::dim;
     const int n = S.n;
-    active_cell(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
-    const uint32_t beg = cl.begin(c), fin = cl.end(c);
+    active_cell<YF && D == 2>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
+    const uint32_t ci = cl.index(cc, c, n);  // storage index (c unless ghost columns)
+    const uint32_t beg = cl.begin(ci), fin = cl.end(ci);
     if (beg != fin) {
         ct.attempted++;
         const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
@@ -660,62 +662,19 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     const int a = a0 + grp;
     const int n = S.n, N = S.N;
 
-    // ---- 1. propose (group leaders; the steps of propose() above, kept inline here
-    // because the call changes the register allocation of this hot kernel)
+    // ---- 1. propose (group leaders)
     int cc[3] = {0, 0, 0};
     uint32_t c = 0, i = 0, pi = 0;  // active cell, moving tag, its slot in the cell list
     bool live = false;
     double xn[3] = {0.0, 0.0, 0.0};
     double qn[4] = {1.0, 0.0, 0.0, 0.0};
     bool c_rot = false, c_moved = false;  // rotation attempted / translation attempted
-    if (sub == 0 && a < n_act) {
-        // LDS-resident 2D tiles (YF) index y first: data locality does not
-        // matter there, and most waves then skip the x-wrapped ranges (in 3D
-        // a wave spans several x columns, so nearly every wave holds an edge)
-        active_cell<YF && D == 2>(S, D, colour, a, 1.0 / (double)(n / 2), cc, c);
-        const uint32_t ci = cl.index(cc, c, n);  // storage index (c unless ghost columns)
-        const uint32_t beg = cl.begin(ci), fin = cl.end(ci);
-        if (beg != fin) {
-            ct.attempted++;
-            const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
-            pi = beg + index_below(wsel.x, fin - beg);
-            i = cl.member(pi);
-            const uint4 m = draw(t, kMove, select, i, S.replica, k0, k1);
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) xn[ax] = pos.get(ax, i);
-            load_orient<KIND>(ori, N, i, qn);
-            const bool rotate = KIND != kDisk && P.p_rot > 0.0 && u01(m.x) < P.p_rot;
-            live = true;
-            c_rot = rotate;
-            c_moved = !rotate;
-            if (!rotate) {
-                const uint32_t mw[3] = {m.y, m.z, m.w};
-#pragma unroll
-                for (int ax = 0; ax < D; ++ax) {
-                    xn[ax] = wrap_periodic(xn[ax] + P.d * (2.0 * u01(mw[ax]) - 1.0), S.L);
-                    live &= cell_coord(xn[ax], sh[ax], S.L, S.inv_w, n) == cc[ax];
-                }
-            } else {
-                if constexpr (kPlanarTurn<KIND>) {
-                    const double delta = P.a * (2.0 * u01(m.y) - 1.0);
-                    double cd, sd;
-                    small_angle_sincos(delta, cd, sd);
-                    const double c0 = qn[0], s0 = qn[1];
-                    qn[0] = c0 * cd - s0 * sd;
-                    qn[1] = s0 * cd + c0 * sd;
-                } else if constexpr (KIND == kPolyhedron) {
-                    const Quat dq{1.0, P.a * (2.0 * u01(m.y) - 1.0), P.a * (2.0 * u01(m.z) - 1.0),
-                                  P.a * (2.0 * u01(m.w) - 1.0)};
-                    const Quat p = qmul(Quat{qn[0], qn[1], qn[2], qn[3]}, dq);
-                    const double nrm = sqrt(((p.w * p.w + p.x * p.x) + p.y * p.y) + p.z * p.z);
-                    qn[0] = p.w / nrm;
-                    qn[1] = p.x / nrm;
-                    qn[2] = p.y / nrm;
-                    qn[3] = p.z / nrm;
-                }
-            }
-        }
-    }
+    // LDS-resident 2D tiles (YF) index y first: data locality does not matter
+    // there, and most waves then skip the x-wrapped ranges (in 3D a wave
+    // spans several x columns, so nearly every wave holds an edge)
+    if (sub == 0 && a < n_act)
+        propose<KIND, YF>(S, P, pos, ori, cl, colour, select, t, k0, k1, sh, a, cc, c, i, pi, live, xn, qn,
+                          c_rot, c_moved, ct);
     ct.attempted_rot += (sub == 0 && a < n_act && c_rot) ? 1u : 0u;
     ct.cell_reject += (sub == 0 && a < n_act && c_moved && !live) ? 1u : 0u;
     // the moving particle's own slot is parked at infinity for the scan (no
