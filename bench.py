@@ -103,6 +103,11 @@ def workload(name):
         sp, N, L, pos, ori = inputs.workload_spheres(4096, 0.40)
         return {"desc": "spheres (one-vertex spheropolyhedra) N=4096 sigma=1 phi=0.40 d=0.1",
                 "items": [(sp, N, L, pos, ori)], "replicas": 256}
+    if name == "rounded_pentagons":
+        sp, N, L, pos, ori = inputs.workload_rounded_pentagons(4096, 0.50)
+        return {"desc": "spheropolygons: regular pentagons of core circumradius 0.4 swept by 0.1, "
+                        "N=4096 phi=0.50 d=0.1 a=0.2 p_rot=0.5",
+                "items": [(sp, N, L, pos, ori)], "replicas": 512}
     if name == "large":
         sp, N, L, pos, ori = inputs.workload_pentagons(4194304, 0.60)
         return {"desc": "regular pentagons N=4194304 R=0.5 phi=0.60 d=0.1 a=0.2 p_rot=0.5",
@@ -298,7 +303,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=128, help="untimed sweeps first")
     ap.add_argument("--workload", default="pentagons",
                     choices=["pentagons", "pentagons676", "disks", "cubes", "trunc_oct", "dodecahedra",
-                             "spheres", "spherocylinders", "large", "screening"])
+                             "spheres", "spherocylinders", "rounded_pentagons", "large", "screening"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--queue", default="wave", choices=["wave", "register", "global"],
                     help="schedule of the full overlap tests (register/global: grid path, "
