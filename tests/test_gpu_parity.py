@@ -605,6 +605,29 @@ def test_ghost_column_overflow_stops_the_sweep():
     assert np.array_equal(system.orientations(1), ref_ori)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plain_lds_layout_for_a_shape_centred_outside_itself(precision):
+    """A triangle whose particle-frame origin (its rotation centre) lies
+    outside it has no inscribed disk about that centre, so its persistent
+    replicas keep the plain LDS cell list (no ghost edge columns; tiles taken
+    y first, x-wrapped ranges): two such replicas against the oracle, five
+    colour rounds per sweep, whole chunks and a remainder."""
+    v = np.array([[0.2, 0.1], [0.9, 0.1], [0.5, 0.7]])
+    sp = {"dim": 2, "shape": "polygon", "verts": v, "d": 0.1, "a": 0.2, "p_rot": 0.5, "rounds": 0,
+          "volume": inputs.polygon_area(v)}
+    L, pos, orient = inputs.initial_state(sp, 1024, 0.3)
+    announce(f"off-centre triangles, plain LDS layout, {precision}")
+    system = _system([sp, sp], [1024, 1024], [L, L], [pos, pos], [orient, orient], precision=precision,
+                     path="persistent")
+    system.sweep(70, 3)
+    for r in range(2):
+        ref_pos, ref_ori = pos.copy(), orient.copy()
+        ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=3, n_sweeps=70, replica=r)
+        assert_parity((system.positions(r), system.orientations(r), system.stats()[r]),
+                      (ref_pos, ref_ori, ref_stats), sp)
+    assert list(system.count_overlaps()) == [0, 0]
+
+
 def test_single_particle_and_sparse_cells():
     """N=1 (every move in the only occupied cell) and a dilute system in which
     most cells are empty."""
