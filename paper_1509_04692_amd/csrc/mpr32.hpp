@@ -131,6 +131,8 @@ HPMC_HD Sup32 support32(const SpeciesDev& P, const Mink32& mk, const TV& n) {
     float bb = dotf(nb, F3{P.vx32[0], P.vy32[0], P.vz32[0]});
     float ba = -dotf(n.v, F3{P.vx32[0], P.vy32[0], P.vz32[0]});
     float b2 = -INFINITY, a2 = -INFINITY;
+    // two vertices per iteration share one wait for their scalar loads
+#pragma unroll 2
     for (int k = 1; k < nv; ++k) {
         const F3 v{P.vx32[k], P.vy32[k], P.vz32[k]};
         const float pb = dotf(nb, v);

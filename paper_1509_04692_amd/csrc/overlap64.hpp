@@ -195,6 +195,9 @@ __device__ __forceinline__ V3 support64(const SpeciesDev& P, const Minkowski64& 
     int kb = 0, ka = 0;
     double bb = (nb.x * P.vx[0] + nb.y * P.vy[0]) + nb.z * P.vz[0];
     double ba = (na.x * P.vx[0] + na.y * P.vy[0]) + na.z * P.vz[0];
+    // four vertices per iteration: their scalar loads are issued together and
+    // share one wait (the vertex count is a run-time value)
+#pragma unroll 4
     for (int k = 1; k < nv; ++k) {
         const double vx = P.vx[k], vy = P.vy[k], vz = P.vz[k];
         const double pb = (nb.x * vx + nb.y * vy) + nb.z * vz;
