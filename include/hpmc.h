@@ -297,13 +297,16 @@ int hpmc_uses_graph(hpmc_state *st);
 int hpmc_graph_sweeps(hpmc_state *st, uint64_t *out);
 
 /* Per-wave phase clock of a trace build (compiled with -DHPMC_TRACE; the
- * normal build returns HPMC_ERR_UNSUPPORTED).  out (host, n >= 16 words)
+ * normal build returns HPMC_ERR_UNSUPPORTED).  out (host, n >= 24 words)
  * receives, for the persistent batch kernel and then the grid path's colour
  * pass, the shader-clock cycles that all their waves together spent in each
- * of 7 phases -- cell-list build, trial move, pre-filter scan, queued full
- * tests, write-back, waiting at the barrier after a pass, other -- followed
- * by the number of waves, summed over every launch since the last reset.
- * The device is synchronised first; reset != 0 clears the totals. */
+ * of 11 phases -- cell-list build, trial move, pre-filter scan, queued full
+ * tests, write-back, waiting at the barrier after a pass, other, and the
+ * persistent kernel's in-LDS build split into counting, prefix sum, scatter
+ * and in-cell ordering (its first phase then holds only the clearing of the
+ * counts) -- followed by the number of waves, summed over every launch since
+ * the last reset.  The device is synchronised first; reset != 0 clears the
+ * totals. */
 int hpmc_phase_trace(uint64_t *out, int32_t n, int32_t reset);
 
 /* The hipError_t of the last failed HIP call of this state (0 if none); with

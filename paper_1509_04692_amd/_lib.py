@@ -86,7 +86,10 @@ class Stats(ctypes.Structure):
 _lib = None
 
 
-PHASES = ("build", "propose", "scan", "drain", "write", "barrier", "other")
+# order of the phase enum; the build_* phases split the persistent kernel's
+# in-LDS cell-list build ("build" is then its clearing of the counts)
+PHASES = ("build", "propose", "scan", "drain", "write", "barrier", "other",
+          "build_count", "build_prefix", "build_scatter", "build_sort")
 TRACED_KERNELS = ("k_batch", "k_update")
 
 

@@ -643,6 +643,8 @@ __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, co
     }
 }
 
+// One wave's share of a colour pass: active cells a0 + lane / G below a_end
+// (at most 64 / G of them).
 // PARK: the sorted copy is in LDS and the moving particle's slot is parked
 // at infinity during its own scan (else the scan tests the slot).
 // YF: active cells indexed y first (work-groups with their state in LDS).
@@ -652,7 +654,7 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
                                           double* __restrict__ ori, const CELLS& cl,
                                           const XSV& xs, uint32_t colour,
                                           uint32_t select, uint32_t t, uint32_t k0, uint32_t k1,
-                                          const double (&sh)[3], int a0, int n_act, WaveScratch ws,
+                                          const double (&sh)[3], int a0, int a_end, WaveScratch ws,
                                           Counters& ct, PhaseClock& pc) {
     constexpr int D = Traits<KIND>::dim;
     pc.mark<kPhOther>();
@@ -672,11 +674,11 @@ __device__ __forceinline__ void pass_tile(const SysDev& S, const SpeciesDev& P, 
     // LDS-resident 2D tiles (YF) index y first: data locality does not matter
     // there, and most waves then skip the x-wrapped ranges (in 3D a wave
     // spans several x columns, so nearly every wave holds an edge)
-    if (sub == 0 && a < n_act)
+    if (sub == 0 && a < a_end)
         propose<KIND, YF>(S, P, pos, ori, cl, colour, select, t, k0, k1, sh, a, cc, c, i, pi, live, xn, qn,
                           c_rot, c_moved, ct);
-    ct.attempted_rot += (sub == 0 && a < n_act && c_rot) ? 1u : 0u;
-    ct.cell_reject += (sub == 0 && a < n_act && c_moved && !live) ? 1u : 0u;
+    ct.attempted_rot += (sub == 0 && a < a_end && c_rot) ? 1u : 0u;
+    ct.cell_reject += (sub == 0 && a < a_end && c_moved && !live) ? 1u : 0u;
     // the moving particle's own slot is parked at infinity for the scan (no
     // candidate is closer), so the loop needs no self test
     float own[3] = {0.0f, 0.0f, 0.0f};

@@ -872,6 +872,13 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
     const uint32_t t0 = ck.t, k0 = ck.k0, k1 = ck.k1, n_sweeps = ck.n;
     const int half = n / 2;
     const int n_act = D == 3 ? half * half * half : half * half;
+    // active cells per wave and pass: at most 64 (one per lane), spread
+    // evenly over the waves a pass needs, so that no wave holds a short
+    // remainder tile; polyhedra of four or more vertices (long XenoCollide
+    // walks) spread down to 32 cells per wave, which puts more waves on a pass
+    const int min_tile = KIND == kPolyhedron && P.nv >= 4 ? 32 : 64;
+    const int wv = min(nwaves, (n_act + min_tile - 1) / min_tile);
+    const int tile = min(64, (n_act + wv - 1) / wv);
     const int chunk = (nst + B - 1) / B;
     const WaveScratch wscr = wave_scratch(uni + wave * WW);
     // storage cell of grid coordinates y, and the side of its ghost copy:
@@ -902,6 +909,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
         uint32_t* count = uni;
         for (int c = tid; c < nst; c += B) count[c] = 0u;
         __syncthreads();
+        pc.mark<kPhBuild>();
 #pragma unroll
         for (int j = 0; j < kOwn; ++j) {
             const int i = tid + j * B;
@@ -929,6 +937,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             if (GH && gh) atomicAdd(count + c + gh * n, 1u);
         }
         __syncthreads();
+        pc.mark<kPhCount>();
         uint32_t total;
         {
             const int c0 = tid * chunk, c1 = min(nst, c0 + chunk);
@@ -948,6 +957,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             break;
         }
         __syncthreads();
+        pc.mark<kPhPrefix>();
         // scatter the tags and their binary32 coordinates (ghost copies too)
 #pragma unroll
         for (int j = 0; j < kOwn; ++j) {
@@ -984,6 +994,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             }
         }
         __syncthreads();
+        pc.mark<kPhScatter>();
         // ascending tags within each cell; the coordinates move with their tags
         for (int c = tid; c < nst; c += B) {
             const uint32_t b = c ? count[c - 1] : 0u, e = count[c];
@@ -1007,24 +1018,25 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(const SysDev* __restrict_
             }
         }
         __syncthreads();
-        pc.mark<kPhBuild>();
+        pc.mark<kPhSort>();
         using CellList = std::conditional_t<GH, LdsGhostCells, LdsCells>;
         const CellList cl{ends, mem};
         const uint32_t ncol = 1u << D;
         for (int rnd = 0; rnd < S.rounds; ++rnd) {
             for (uint32_t colour = 0; colour < ncol; ++colour) {
                 const uint32_t select = (uint32_t)rnd * ncol + colour;
-                for (int a0 = wave * 64; a0 < n_act; a0 += nwaves * 64) {
+                for (int a0 = wave * tile; a0 < n_act; a0 += nwaves * tile) {
+                    const int a1 = min(a0 + tile, n_act);
                     if constexpr (XS) {
                         // ghost columns make x-first order free of wrapped
                         // ranges; plain lists index y first
                         pass_tile<KIND, PREC, 1, NV, true, kWaveQueue, !GH>(S, P, pos, ori, cl, xs, colour,
                                                                             select, t, k0, k1, sh, a0,
-                                                                            n_act, wscr, ct, pc);
+                                                                            a1, wscr, ct, pc);
                     } else {
                         const PosXsView<D> pxs{mem, pos.p, N, sh[0], sh[1], sh[2], S.L};
                         pass_tile<KIND, PREC, 1, NV, false, kWaveQueue, true>(
-                            S, P, pos, ori, cl, pxs, colour, select, t, k0, k1, sh, a0, n_act, wscr, ct, pc);
+                            S, P, pos, ori, cl, pxs, colour, select, t, k0, k1, sh, a0, a1, wscr, ct, pc);
                     }
                 }
                 pc.mark<kPhOther>();

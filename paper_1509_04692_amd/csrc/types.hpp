@@ -95,10 +95,13 @@ struct alignas(16) SysDev {
 // Phases of the per-wave clock of a trace build (HPMC_TRACE): cell-list
 // build, trial move, pre-filter scan, queued full tests, write-back, waiting
 // at the work-group barrier after a pass, everything else (loads, loop
-// overhead).  Kernels traced: the persistent batch kernel and the grid
-// path's colour pass.
+// overhead); then the steps of the persistent kernel's in-LDS build, each up
+// to the barrier that ends it: counting per cell, the prefix sum of the
+// counts, the scatter, the ascending-tag order within each cell (its kPhBuild
+// is then the clearing of the counts alone).  Kernels traced: the persistent
+// batch kernel and the grid path's colour pass.
 enum Phase : int { kPhBuild = 0, kPhPropose, kPhScan, kPhDrain, kPhWrite, kPhBarrier, kPhOther,
-                   kNumPhases };
+                   kPhCount, kPhPrefix, kPhScatter, kPhSort, kNumPhases };
 enum TracedKernel : int { kTraceBatch = 0, kTraceUpdate = 1, kTraceKernels = 2 };
 // Per traced kernel: kNumPhases cycle totals, then the number of waves.
 constexpr int kTraceWords = kTraceKernels * (kNumPhases + 1);
