@@ -38,6 +38,16 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
+def test_phase_trace_layout_matches_the_binding(lib):
+    """The binding's phase list and kernel list size the buffer of
+    hpmc_phase_trace: one word short is rejected before anything runs, the
+    full size reaches the build check (the normal build has no clock)."""
+    n = len(_lib.TRACED_KERNELS) * (len(_lib.PHASES) + 1)
+    buf = (ctypes.c_uint64 * n)()
+    assert lib.hpmc_phase_trace(buf, n - 1, 0) == -1
+    assert lib.hpmc_phase_trace(buf, n, 0) == -7
+
+
 def test_strerror(lib):
     assert lib.hpmc_strerror(0) == b"ok"
     assert b"overlap" in lib.hpmc_strerror(-3)
