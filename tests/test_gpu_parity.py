@@ -255,6 +255,34 @@ def test_three_kind_groups_on_their_own_streams(graphs):
     assert np.all(system.count_overlaps() == 0)
 
 
+def test_persistent_tile_spread_at_its_edges():
+    """The persistent kernel spreads a colour pass's active cells evenly over
+    the waves the pass needs (at most 64 per wave; polyhedra of four or more
+    vertices at least 32): cubes with 8, 27, 64, 125 and 216 active cells per
+    pass (one wave; one; two of 32; four of 32, 32, 32, 29; seven), spheres
+    with 216 (one-vertex shapes keep the 64-cell floor: four waves of 54),
+    and pentagons with 81 (two waves of 41 and 40) and 1089 (more tiles of
+    64 than waves: two waves take a second tile).  Every replica equals the
+    oracle with its own replica word."""
+    batch = [inputs.workload_cubes(N, 0.3) for N in (110, 360, 850, 1650, 2800)]
+    batch.append(inputs.workload_spheres(1000, 0.3))
+    batch.append(inputs.workload_pentagons(280, 0.5))
+    batch.append(inputs.workload_pentagons(4400, 0.6))
+    announce(f"tile spread N={[b[1] for b in batch]}")
+    system = _system([b[0] for b in batch], [b[1] for b in batch], [b[2] for b in batch],
+                     [b[3] for b in batch], [b[4] for b in batch], precision="mixed",
+                     path="persistent")
+    system.sweep(4, seed=23)
+    stats = system.stats()
+    for r, (sp, N, L, pos, orient) in enumerate(batch):
+        ref_pos, ref_ori = pos.copy(), orient.copy()
+        ref_stats = oracle.sweep(sp, L, ref_pos, ref_ori, seed=23, n_sweeps=4, replica=r)
+        assert [stats[r][k] for k in PARITY] == [int(x) for x in ref_stats], r
+        assert np.array_equal(system.positions(r), ref_pos), r
+        assert np.array_equal(system.orientations(r), ref_ori), r
+    assert np.all(system.count_overlaps() == 0)
+
+
 @pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("shape", ["pentagons", "cubes", "dodeca"])
 def test_every_lane_count_equals_the_oracle(shape, lanes):
