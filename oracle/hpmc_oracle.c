@@ -959,13 +959,8 @@ int or_sweep(const or_species *sp, int32_t N, double L, double *pos, double *ori
                     uint32_t wsel[4];
                     draw(seed, t, PURPOSE_SELECT, select, (uint32_t)c, replica, wsel);
                     int i = cl.members[cl.start[c] + (int)or_index(wsel[0], (uint32_t)cl.count[c])];
-                    /* the move's words: in 2D the three words of the same
-                     * block that the occupant choice leaves (rotate or not,
-                     * then the displacement or the angle); 3D moves need four,
-                     * from a second block keyed on the particle */
-                    uint32_t m[4] = { wsel[1], wsel[2], wsel[3], 0 };
-                    if (g.dim == 3)
-                        draw(seed, t, PURPOSE_MOVE, select, (uint32_t)i, replica, m);
+                    uint32_t m[4];
+                    draw(seed, t, PURPOSE_MOVE, select, (uint32_t)i, replica, m);
                     double x[3] = { 0, 0, 0 }, q[4] = { 1, 0, 0, 0 }, xn[3], qn[4];
                     for (int a = 0; a < g.dim; ++a)
                         x[a] = pos[a * N + i];

@@ -584,9 +584,9 @@ __device__ __forceinline__ void compact_queue(uint32_t* q, uint32_t from, uint32
 }
 
 // Trial move of active cell a (index within its colour): uniform occupant
-// (Philox SELECT keyed on the cell), translation or rotation (2D: the other
-// three words of that block; 3D: Philox MOVE keyed on the tag), periodic
-// wrap, and the rule that a translation must stay in the cell.  Sets live when the cell is non-empty and the trial
+// (Philox SELECT keyed on the cell), translation or rotation (Philox MOVE
+// keyed on the tag), periodic wrap, and the rule that a translation must
+// stay in the cell.  Sets live when the cell is non-empty and the trial
 // stays in it.  YF: active cells indexed y first (2D).
 template <int KIND, bool YF = false, class POS, class CELLS>
 __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, const POS& pos,
@@ -606,11 +606,7 @@ __device__ __forceinline__ void propose(const SysDev& S, const SpeciesDev& P, co
         const uint4 wsel = draw(t, kSelect, select, c, S.replica, k0, k1);
         pi = beg + index_below(wsel.x, fin - beg);
         i = cl.member(pi);
-        // the move's words: in 2D the three words of the same block that the
-        // occupant choice leaves; 3D moves need four, from a block keyed on
-        // the tag
-        const uint4 m = D == 2 ? make_uint4(wsel.y, wsel.z, wsel.w, 0u)
-                               : draw(t, kMove, select, i, S.replica, k0, k1);
+        const uint4 m = draw(t, kMove, select, i, S.replica, k0, k1);
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) xn[ax] = pos.get(ax, i);
         load_orient<KIND>(ori, S.N, i, qn);
